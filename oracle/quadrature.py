@@ -1,0 +1,351 @@
+"""RBF quadrature weights on closed surfaces (FP64 CPU oracle; test infrastructure).
+
+This module is part of the correctness oracle.  Only the test-suite, the smoke
+check and the CPU-baseline leg of the benchmark may import it; the GPU library
+never does.
+
+It computes surface quadrature weights q with Q_n f = sum_i q_i f(x_i), the
+``mu_j`` of the discrete collocation scheme (paper section 2.2, eq.
+NFODETilde), following the paper's section 3:
+
+* local interpolation with the polyharmonic spline r^3 plus polynomials of
+  degree <= deg on stencils of the k nodes nearest to an element's centre
+  (section 3.1, eqs. polyHarmonic and interp_system);
+* RBF-QF for the integral functional: per element, the weights solve the
+  saddle-point system with right-hand side the exact integrals of the basis
+  functions over the element, and a node's weight is the sum of its
+  element weights (section 3.2, eq. functional_stencil);
+* on a curved surface, the flat triangles E_j are mapped to curved patches by
+  central projection from projection points p_j; each stencil is pulled back
+  to the plane of E_j along rays through p_j, planar RBF-QF is applied there,
+  and the Jacobian of the map multiplies each weight (section 3.3, eq.
+  integral).
+
+Readings where the paper is silent or garbled:
+
+* the cutting plane of an edge shared by E_j and E_j' contains that edge and
+  has normal n_j - n_j' (the printed condition drops the edge point);
+* star-shaped surfaces use p_j = 0 for every triangle: every plane through the
+  origin and an edge is shared by both neighbours, so the curved patches
+  partition the surface exactly;
+* where the three cutting planes of a torus triangle are nearly parallel
+  (zero Gaussian curvature), the projection is taken orthogonally onto the
+  triangle's plane (p_j at infinity along n_j);
+* the Jacobian that eq. integral carries is applied to the planar weights,
+  evaluated at each stencil node's pre-image;
+* stencil ties are broken by (distance, index).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.spatial import ConvexHull, cKDTree
+
+# ------------------------------------------------------------- triangulation
+
+
+def triangulate(surface) -> np.ndarray:
+    """Flat triangulation {E_j} whose vertices are exactly the nodes.
+
+    Star-shaped surfaces: convex hull of the node directions.  Torus: strips
+    between consecutive node rings, closed in both angles.  Triangles are
+    oriented so that (b - a) x (c - a) points along the outward normal.
+    """
+    x = surface.xyz
+    if surface.star_shaped:
+        u = x / np.linalg.norm(x, axis=1, keepdims=True)
+        tris = ConvexHull(u).simplices.astype(np.int64)
+    elif surface.kind == "torus":
+        tris = _torus_strips(surface)
+    else:
+        raise ValueError("no triangulation for %s" % surface.kind)
+    a, b, c = x[tris[:, 0]], x[tris[:, 1]], x[tris[:, 2]]
+    nrm = np.cross(b - a, c - a)
+    ref = surface.normal_at((a + b + c) / 3.0)
+    flip = np.sum(nrm * ref, axis=1) < 0
+    tris[flip] = tris[flip][:, [0, 2, 1]]
+    return tris
+
+
+def _torus_strips(surface) -> np.ndarray:
+    ring = surface.ring
+    phi = surface.angles[:, 0]
+    n_rings = int(ring.max()) + 1
+    members = []
+    for k in range(n_rings):
+        idx = np.nonzero(ring == k)[0]
+        members.append(idx[np.argsort(phi[idx], kind="stable")])
+    out = []
+    two_pi = 2.0 * math.pi
+    for k in range(n_rings):
+        A = members[k]
+        B = members[(k + 1) % n_rings]
+        a_ang = phi[A]
+        b_ang = phi[B]
+        ma, mb = len(A), len(B)
+        d = np.abs(np.angle(np.exp(1j * (b_ang - a_ang[0]))))
+        j0 = int(np.argmin(d))
+        b0 = b_ang[j0]
+        if b0 - a_ang[0] > math.pi:
+            b0 -= two_pi
+        elif a_ang[0] - b0 > math.pi:
+            b0 += two_pi
+        sa = np.arange(ma + 1)
+        A_u = a_ang[sa % ma] + two_pi * (sa // ma)
+        tb = np.arange(mb + 1)
+        jb = (j0 + tb) % mb
+        B_u = b_ang[jb] + two_pi * ((j0 + tb) // mb) - b_ang[j0] + b0
+        s = t = 0
+        while s < ma or t < mb:
+            if s < ma and (t == mb or A_u[s + 1] <= B_u[t + 1]):
+                out.append((A[s % ma], A[(s + 1) % ma], B[jb[t]]))
+                s += 1
+            else:
+                out.append((A[s % ma], B[jb[t + 1]], B[jb[t]]))
+                t += 1
+    return np.asarray(out, dtype=np.int64)
+
+
+def edges_of(tris: np.ndarray):
+    """Unique undirected edges and, for every triangle edge, the other triangle."""
+    m = tris.shape[0]
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])  # (3m, 2)
+    owner = np.concatenate([np.arange(m)] * 3)
+    key = np.sort(e, axis=1)
+    order = np.lexsort((key[:, 1], key[:, 0]))
+    ks = key[order]
+    same = np.all(ks[1:] == ks[:-1], axis=1)
+    neighbour = np.full(3 * m, -1, dtype=np.int64)
+    i = np.nonzero(same)[0]
+    neighbour[order[i]] = owner[order[i + 1]]
+    neighbour[order[i + 1]] = owner[order[i]]
+    uniq = np.unique(key, axis=0)
+    return uniq, neighbour.reshape(3, m).T   # neighbour[j, e]: across edge e of triangle j
+
+
+# ------------------------------------------------- exact integrals on a triangle
+
+
+def _log_rho_plus_l(rho, l, d):
+    """log(rho + l) with rho = sqrt(d^2 + l^2); for l < 0 uses rho + l = d^2 / (rho - l)."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        pos = np.log(np.where(l >= 0, rho + l, 1.0))
+        neg = 2.0 * np.log(np.where(l < 0, d, 1.0)) - np.log(np.where(l < 0, rho - l, 1.0))
+    return np.where(l >= 0, pos, neg)
+
+
+def _safe_diff(d, a, b):
+    with np.errstate(invalid="ignore"):
+        return np.where(d > 0, a - b, 0.0)
+
+
+def r3_over_apex_triangle(P, p, q):
+    """Integral of |s - P|^3 over the triangle (P, p, q), unsigned (2-D points).
+
+    In polar coordinates about P, with d the distance from P to the line pq and
+    alpha the angle from the foot of the perpendicular,
+      int = (d^5 / 5) [S(alpha)]  with  S = int sec^5 = sec^3 tan / 4
+            + 3 sec tan / 8 + 3 ln(sec + tan) / 8,
+    written with rho = d sec(alpha) and l = d tan(alpha) so that d = 0 is safe:
+      int = (d / 5) [ rho^3 l / 4 + 3 d^2 rho l / 8 + 3 d^4 ln(rho + l) / 8 ].
+    Arrays broadcast over leading dimensions; the last axis has length 2.
+    """
+    t = q - p
+    L = np.linalg.norm(t, axis=-1)
+    t = t / L[..., None]
+    lp = np.sum((p - P) * t, axis=-1)           # signed position of p along t, from the foot
+    lq = lp + L
+    d = np.abs((p - P)[..., 0] * t[..., 1] - (p - P)[..., 1] * t[..., 0])
+    rp = np.sqrt(d * d + lp * lp)
+    rq = np.sqrt(d * d + lq * lq)
+    d2 = d * d
+    term = (0.25 * (rq ** 3 * lq - rp ** 3 * lp)
+            + 0.375 * d2 * (rq * lq - rp * lp)
+            + 0.375 * d2 * d2 * _safe_diff(d, _log_rho_plus_l(rq, lq, d), _log_rho_plus_l(rp, lp, d)))
+    return d * term / 5.0
+
+
+def r3_over_triangle(P, v0, v1, v2):
+    """Integral of |s - P|^3 over triangle (v0, v1, v2) for points P (..., 2).
+
+    Signed decomposition into the three triangles with apex P: each apex
+    triangle counts with the sign of its orientation relative to the triangle's.
+    """
+    def cross2(a, b):
+        return a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]
+    o = np.sign(cross2(v1 - v0, v2 - v0))
+    total = 0.0
+    for p, q in ((v0, v1), (v1, v2), (v2, v0)):
+        s = np.sign(cross2(p - P, q - P)) * o
+        total = total + s * r3_over_apex_triangle(P, p, q)
+    return total
+
+
+def monomials_deg2(s):
+    """Polynomial basis of degree <= 2 in 2-D: 1, x, y, x^2, x y, y^2."""
+    x, y = s[..., 0], s[..., 1]
+    return np.stack([np.ones_like(x), x, y, x * x, x * y, y * y], axis=-1)
+
+
+def monomial_integrals_deg2(v0, v1, v2):
+    """Exact integrals of the degree-2 basis over a triangle (edge-midpoint rule)."""
+    area = 0.5 * np.abs((v1 - v0)[..., 0] * (v2 - v0)[..., 1] - (v1 - v0)[..., 1] * (v2 - v0)[..., 0])
+    mids = ((v0 + v1) / 2, (v1 + v2) / 2, (v2 + v0) / 2)
+    acc = sum(monomials_deg2(m) for m in mids)
+    return acc * (area / 3.0)[..., None]
+
+
+# -------------------------------------------------------------- projection
+
+
+def projection_points(surface, tris, cond_max: float = 1e8):
+    """p_j for every triangle, or NaN rows meaning "at infinity along n_j".
+
+    Star-shaped surfaces: the origin.  Otherwise the intersection of the three
+    cutting planes {y : (n_j - n_j') . (y - a_e) = 0}, one per edge e shared
+    with neighbour j'; if those planes are nearly parallel (condition number
+    above cond_max) the triangle falls back to orthogonal projection.
+    """
+    m = tris.shape[0]
+    if surface.star_shaped:
+        return np.zeros((m, 3)), 0
+    x = surface.xyz
+    a, b, c = x[tris[:, 0]], x[tris[:, 1]], x[tris[:, 2]]
+    nj = np.cross(b - a, c - a)
+    nj /= np.linalg.norm(nj, axis=1, keepdims=True)
+    _, nb = edges_of(tris)
+    if np.any(nb < 0):
+        raise ValueError("triangulation is not closed")
+    M = nj[:, None, :] - nj[nb]                       # (m, 3, 3): rows are cutting-plane normals
+    M /= np.linalg.norm(M, axis=2, keepdims=True)
+    ea = np.stack([a, b, c], axis=1)                  # a point on each edge (edge e starts at vertex e)
+    cen = (a + b + c) / 3.0
+    rhs = np.sum(M * (ea - cen[:, None, :]), axis=2)
+    sv = np.linalg.svd(M, compute_uv=False)
+    cond = sv[:, 0] / np.maximum(sv[:, 2], 1e-300)
+    ok = cond <= cond_max
+    p = np.full((m, 3), np.nan)
+    p[ok] = cen[ok] + np.linalg.solve(M[ok], rhs[ok][..., None])[..., 0]
+    return p, int(np.count_nonzero(~ok))
+
+
+# -------------------------------------------------------------- weights
+
+
+def planar_element_weights(s2, v0, v1, v2):
+    """RBF-QF weights of one flat element for its (planar) stencil.
+
+    s2: (..., k, 2) stencil points; v0, v1, v2: (..., 2) triangle vertices.
+    Solves [A Pi; Pi^T 0][w; gamma] = [int_E |s - s_r|^3 ds ; int_E pi(s) ds]
+    with A_rs = |s_r - s_s|^3 and Pi the degree-2 monomials, and returns w.
+    """
+    k = s2.shape[-2]
+    mpoly = 6
+    kk = k + mpoly
+    lead = s2.shape[:-2]
+    diff = s2[..., :, None, :] - s2[..., None, :, :]
+    Amat = np.linalg.norm(diff, axis=-1) ** 3
+    Pi = monomials_deg2(s2)
+    sysm = np.zeros(lead + (kk, kk))
+    sysm[..., :k, :k] = Amat
+    sysm[..., :k, k:] = Pi
+    sysm[..., k:, :k] = np.swapaxes(Pi, -1, -2)
+    rhs = np.empty(lead + (kk,))
+    rhs[..., :k] = r3_over_triangle(s2, v0[..., None, :], v1[..., None, :], v2[..., None, :])
+    rhs[..., k:] = monomial_integrals_deg2(v0, v1, v2)
+    sol = np.linalg.solve(sysm, rhs[..., None])[..., 0]
+    return sol[..., :k]
+
+
+
+def stencils(xyz: np.ndarray, centres: np.ndarray, k: int) -> np.ndarray:
+    """k nearest nodes to every centre, ordered by (distance, index)."""
+    if k > xyz.shape[0]:
+        raise ValueError("stencil larger than the node set")
+    tree = cKDTree(xyz)
+    kq = min(xyz.shape[0], k + 4)          # a few extra so ties at the k-th place resolve by index
+    dist, idx = tree.query(centres, k=kq)
+    dist = np.round(dist, 14)
+    srt = np.argsort(idx, axis=1, kind="stable")
+    idx_s = np.take_along_axis(idx, srt, axis=1)
+    dist_s = np.take_along_axis(dist, srt, axis=1)
+    srt2 = np.argsort(dist_s, axis=1, kind="stable")
+    return np.take_along_axis(idx_s, srt2, axis=1)[:, :k].astype(np.int64)
+
+
+def surface_weights(surface, k: int = 32, deg: int = 2, chunk: int = 8192,
+                    return_info: bool = False):
+    """Surface RBF-QF weights q (length N) with phi(r) = r^3 and degree-deg polynomials.
+
+    For every triangle E_j: pull the stencil S(E_j) back to the plane of E_j
+    along rays from p_j, scale by h_j about the centroid, solve
+      [A  Pi; Pi^T 0] [w; gamma] = [int_E r^3 ; int_E pi]
+    and add w_r * h_j^2 * J_j(xi_r) to q at stencil node r.
+    """
+    if deg != 2:
+        raise ValueError("only deg = 2 is implemented")
+    mpoly = 6
+    if k < mpoly:
+        raise ValueError("stencil too small: k >= C(deg + 2, 2) is required")
+    x, nrm_x = surface.xyz, surface.normals
+    n = x.shape[0]
+    tris = triangulate(surface)
+    m = tris.shape[0]
+    P, n_orth = projection_points(surface, tris)
+    a, b, c = x[tris[:, 0]], x[tris[:, 1]], x[tris[:, 2]]
+    cen = (a + b + c) / 3.0
+    nj = np.cross(b - a, c - a)
+    nj /= np.linalg.norm(nj, axis=1, keepdims=True)
+    st = stencils(x, cen, k)
+    q = np.zeros(n)
+    min_cos = np.inf
+    for lo in range(0, m, chunk):
+        hi = min(m, lo + chunk)
+        sl = slice(lo, hi)
+        xs = x[st[sl]]                                   # (c, k, 3)
+        ns = nrm_x[st[sl]]
+        nn = nj[sl][:, None, :]
+        p = P[sl]
+        orth = np.isnan(p[:, 0])
+        # pre-images on the plane of E_j
+        xi = np.empty_like(xs)
+        J = np.empty(xs.shape[:2])
+        if np.any(~orth):
+            pp = p[~orth][:, None, :]
+            dxp = xs[~orth] - pp
+            num = np.sum(nn[~orth] * (a[sl][~orth][:, None, :] - pp), axis=2)
+            den = np.sum(nn[~orth] * dxp, axis=2)
+            t = num / den
+            xi_c = pp + t[..., None] * dxp
+            xi[~orth] = xi_c
+            u = dxp / np.linalg.norm(dxp, axis=2, keepdims=True)
+            ratio = np.linalg.norm(dxp, axis=2) / np.linalg.norm(xi_c - pp, axis=2)
+            cos_plane = np.abs(np.sum(nn[~orth] * u, axis=2))
+            cos_surf = np.abs(np.sum(ns[~orth] * u, axis=2))
+            min_cos = min(min_cos, float(cos_surf.min()))
+            J[~orth] = ratio ** 2 * cos_plane / cos_surf
+        if np.any(orth):
+            h_off = np.sum(nn[orth] * (xs[orth] - a[sl][orth][:, None, :]), axis=2)
+            xi[orth] = xs[orth] - h_off[..., None] * nn[orth]
+            cs = np.abs(np.sum(ns[orth] * nn[orth], axis=2))
+            min_cos = min(min_cos, float(cs.min()))
+            J[orth] = 1.0 / cs
+        # local 2-D frame centred at the centroid, scaled by h_j
+        e1 = b[sl] - a[sl]
+        e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+        e2 = np.cross(nj[sl], e1)
+        rel = xi - cen[sl][:, None, :]
+        h = np.max(np.linalg.norm(rel, axis=2), axis=1)
+        s2 = np.stack([np.sum(rel * e1[:, None, :], axis=2),
+                       np.sum(rel * e2[:, None, :], axis=2)], axis=2) / h[:, None, None]
+        verts = [np.stack([np.sum((v[sl] - cen[sl]) * e1, axis=1),
+                           np.sum((v[sl] - cen[sl]) * e2, axis=1)], axis=1) / h[:, None]
+                 for v in (a, b, c)]
+        wplan = planar_element_weights(s2, verts[0], verts[1], verts[2])
+        wE = wplan * (h * h)[:, None] * J
+        q += np.bincount(st[sl].ravel(), weights=wE.ravel(), minlength=n)
+    if return_info:
+        return q, {"triangles": m, "orthogonal_fallbacks": n_orth, "min_cos": min_cos,
+                   "tris": tris}
+    return q
