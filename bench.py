@@ -1,0 +1,218 @@
+"""Throughput of the neural-field hot path on one MI355X.
+
+Workload (one "step" = one whole integration): torus R = 1, r = 0.4 with
+N = 32768 jittered-ring nodes, exponential Mexican hat
+w(r) = 2 exp(-r/0.1) - exp(-r/0.3), sigmoid beta = 20, theta = 0.25, two
+bumps as u0, classical RK4 with dt = 0.02 for 500 steps (2000 operator
+applications of N^2 pairs each).  Inputs are resident on the GPU before the
+timed region.  Quadrature weights are the area-share stand-in |D|/N (the
+oracle's RBF-QF weights are used by the parity tests; the weight values do not
+change the work).
+
+Both evaluation forms run: on-the-fly FP32 pair sums, and precomputed FP32 W
+(its build is inside every timed step).  `value` is the faster form's
+pair-interactions per second; both forms are listed under "forms".
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
+VALU_LANES_PER_S = 256 * 64 * 2.4e9   # FP32 lane-operations/s, non-packed (256 CUs x 4 SIMD x 16 lanes x 2.4 GHz)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rk4-steps", type=int, default=500)
+    ap.add_argument("--forms", default="otf,w32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probes", action="store_true", help="also run the roofline microbenchmarks")
+    return ap.parse_args()
+
+
+def run_form(P, torch, prob, w, q_t, form, args, u0_t):
+    k = P.kernel_struct(w.kernel_kind, *w.kernel)
+    f = P.Firing(w.beta, float(w.theta[0]))
+    L = P.lib()
+    ctx = prob.ctx
+    u = torch.empty_like(u0_t)
+    ws = prob.integrate_workspace(1, form)
+    wbytes = L.nfr_w_bytes(w.n, form) if form != P.FORM_ONTHEFLY_FP32 else 0
+    Wbuf = None
+    if wbytes:
+        from paper_2504_13379_amd.api import _dev_buffer
+        Wbuf = _dev_buffer(wbytes, ctx.device)
+
+    def one():
+        u.copy_(u0_t)
+        if Wbuf is not None:
+            P._lib.check(L.nfr_w_build(prob.handle, __import__("ctypes").byref(k), form, Wbuf.data_ptr(), wbytes))
+        prob.integrate(k, f, u, w.dt, args.rk4_steps, form=form, W=Wbuf, ws=ws)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    import ctypes
+    L.nfr_context_set_timing(ctx.handle, 1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches = ctypes.c_int64()
+    tot_ms = ctypes.c_double()
+    P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot_ms)))
+    L.nfr_context_set_timing(ctx.handle, 0)
+    sec = (t1 - t0) / args.steps
+    pairs = 4.0 * args.rk4_steps * float(w.n) ** 2
+    return {
+        "ms_per_step": sec * 1e3,
+        "value": pairs / sec,
+        "kernel_launches": int(launches.value),
+        "kernel_avg_ms": tot_ms.value / max(1, launches.value),
+        "u": u,
+    }
+
+
+def roofline(form_name, res, n, npad):
+    avg_s = res["kernel_avg_ms"] * 1e-3
+    if form_name == "w32":
+        bytes_per_launch = float(n) * npad * 4.0          # every W element once per application
+        ach = bytes_per_launch / avg_s
+        return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": ach / HBM_PEAK, "traffic": None, "kernel": "k_w_gemv_f32<1>"}
+    # on-the-fly: 12 FP32 lane-operations per pair for the exponential kernel
+    # (3 sub, 1 mul + 2 fma for r^2, sqrt, 1 mul, 2 exp2, 2 fma accumulates)
+    ops = 12.0 * float(npad) * npad
+    ach = ops / avg_s
+    return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tlane-op/s",
+            "frac": ach / VALU_LANES_PER_S, "traffic": None, "kernel": "k_otf_pair_sum<1,4,1>"}
+
+
+def cpu_baseline(w, q, gpu_y_rows, rows):
+    """The FP64 oracle's operator on a bounded sample: all sources, a subset of target rows."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import neural_field as NF
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ref = NF.apply_K(w.surface.xyz, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows=rows)
+        t1 = time.perf_counter()
+    import numpy as np
+    err = float(np.max(np.abs(gpu_y_rows - ref)) / np.max(np.abs(ref)))
+    return {"value": float(len(rows)) * w.n / (t1 - t0), "unit": "pair-interactions/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "one operator application, %d of %d target rows x all %d sources, FP64 NumPy, 1 thread"
+                      % (len(rows), w.n, w.n)}, err
+
+
+def probes(P, torch, ctx):
+    import ctypes
+    L = P.lib()
+    out = {}
+    grid_threads = torch.cuda.get_device_properties(0).multi_processor_count * 8 * 256
+    small = torch.empty(grid_threads * 4 + 256, dtype=torch.uint8, device="cuda")
+    for name, which, size in (("fma_lane_ops", 0, 20000), ("exp_lane_ops", 1, 5000), ("sqrt_lane_ops", 2, 5000),
+                              ("mfma_bf16_flops", 5, 20000)):
+        r = ctypes.c_double()
+        P._lib.check(L.nfr_probe(ctx.handle, which, size, small.data_ptr(), small.numel(), ctypes.byref(r)))
+        out[name] = r.value
+    nfl = 1 << 30                                   # 4 GiB read, 2 x 2 GiB copy
+    big = torch.empty(nfl * 4 + grid_threads * 4 + 256, dtype=torch.uint8, device="cuda")
+    for name, which, size in (("hbm_read_Bps", 3, nfl), ("hbm_copy_Bps", 4, nfl // 2)):
+        best = 0.0
+        for _ in range(3):
+            r = ctypes.c_double()
+            P._lib.check(L.nfr_probe(ctx.handle, which, size, big.data_ptr(), big.numel(), ctypes.byref(r)))
+            best = max(best, r.value)
+        out[name] = best
+    del big
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported (the path shards by target rows, "
+              "see the design notes)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2504_13379_amd as P
+    from workloads import configs as C
+
+    w = C.torus_exp(32768, steps=args.rk4_steps)
+    q = C.area_share_weights(w.surface)
+    ctx = P.Context(0)
+    xyz_t = torch.from_numpy(w.surface.xyz).cuda()
+    q_t = torch.from_numpy(q).cuda()
+    prob = P.Problem(ctx, xyz_t, q_t)
+    u0_t = torch.from_numpy(w.u0.copy()).cuda()
+    torch.cuda.synchronize()
+
+    names = {"otf": P.FORM_ONTHEFLY_FP32, "w32": P.FORM_W_FP32}
+    results = {}
+    for nm in args.forms.split(","):
+        print("bench: form %s, %d warmup + %d timed integrations of %d RK4 steps" % (nm, args.warmup, args.steps,
+              args.rk4_steps), file=sys.stderr, flush=True)
+        results[nm] = run_form(P, torch, prob, w, q_t, names[nm], args, u0_t)
+        print("bench: form %s %.3f ms/step" % (nm, results[nm]["ms_per_step"]), file=sys.stderr, flush=True)
+    best = max(results, key=lambda k: results[k]["value"])
+    r = results[best]
+    rl = roofline(best, r, w.n, prob.npad)
+
+    forms = {}
+    for nm, rr in results.items():
+        rlf = roofline(nm, rr, w.n, prob.npad)
+        forms[nm] = {"value": rr["value"], "ms_per_step": rr["ms_per_step"], "kernel_avg_ms": rr["kernel_avg_ms"],
+                     "roofline_frac": rlf["frac"]}
+    if len(results) == 2:
+        ua, ub = results["otf"]["u"].cpu().numpy(), results["w32"]["u"].cpu().numpy()
+        forms["otf_vs_w32_rel_linf"] = float(np.max(np.abs(ua - ub)) / np.max(np.abs(ub)))
+
+    line = {
+        "metric": "kernel pair-interactions/s (RK4 integration, FP32 pair sums, FP64 state)",
+        "value": r["value"],
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "torus R=1 r=0.4, N=32768, exp Mexican hat, B=1, RK4 dt=0.02 x %d steps"
+                               % args.rk4_steps, "form": best, "n": w.n, "B": 1},
+        "roofline": rl,
+        "forms": forms,
+    }
+    if not args.no_cpu_baseline:
+        rows = np.random.default_rng(7).choice(w.n, 12288, replace=False)
+        y = prob.apply(P.kernel_struct(w.kernel_kind, *w.kernel), P.Firing(w.beta, float(w.theta[0])), u0_t)
+        torch.cuda.synchronize()
+        cb, err = cpu_baseline(w, q, y.cpu().numpy()[:, rows], rows)
+        line["cpu_baseline"] = cb
+        line["rel_err_vs_fp64_sampled_apply"] = err
+    if args.probes:
+        line["probes"] = probes(P, torch, ctx)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

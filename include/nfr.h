@@ -1,0 +1,211 @@
+/*
+ * nfr.h -- C ABI of the MI355X (gfx950) library for RBF neural fields on surfaces.
+ *
+ * The library applies and time-steps the discrete nonlocal operator of the
+ * discrete collocation scheme (paper section 2.2, eq. NFODETilde, without the
+ * forcing term):
+ *
+ *     u_i'(t) = -u_i + K_i(u),    K_i(u) = sum_{j=0}^{N-1} w(|x_i - x_j|) q_j f(u_j),
+ *
+ * over N nodes x_i on a surface with quadrature weights q_j (the mu_j of eq.
+ * NFODETilde, produced by RBF-QF, paper section 3), a radial Mexican-hat
+ * kernel w of the chordal distance and the sigmoid firing rate f of eq.
+ * firing_rate.  The sum runs over every j, j = i included.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an int status: NFR_OK (0) or a negative NFR_ERR_*.
+ *     nfr_last_error() gives a message for the calling thread's last failure.
+ *     No C++ exception crosses this interface.
+ *   - Pointers named *_dev are device pointers on the context's GPU; pointers
+ *     named *_host are host pointers.  All memory is owned by the caller; the
+ *     library never allocates device memory and never frees caller memory.
+ *     Scratch space comes from a caller-supplied workspace whose size the
+ *     matching nfr_*_workspace_size() call returns.
+ *   - Device work is enqueued on the stream given at context creation; calls
+ *     return after enqueueing (unless stated otherwise) and the caller
+ *     synchronises.  Arguments are validated on the host before anything is
+ *     enqueued; a failed call enqueues nothing.
+ *   - A state array of B states is stored state-major: element (i, b) of an
+ *     N x B array lives at [b * N + i] (each state contiguous, FP64).
+ *   - One context per thread, or external locking.
+ */
+#ifndef NFR_H
+#define NFR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NFR_VERSION_MAJOR 0
+#define NFR_VERSION_MINOR 1
+#define NFR_VERSION_PATCH 0
+
+enum nfr_status_code {
+  NFR_OK = 0,
+  NFR_ERR_INVALID_ARG = -1,      /* null pointer, bad size or enum, inconsistent arguments */
+  NFR_ERR_NONFINITE = -2,        /* a scalar argument is NaN or infinite */
+  NFR_ERR_NO_DEVICE = -3,        /* no HIP device with that index */
+  NFR_ERR_UNSUPPORTED_ARCH = -4, /* the device is not gfx950 */
+  NFR_ERR_HIP = -5,              /* a HIP runtime call failed */
+  NFR_ERR_WORKSPACE = -6,        /* workspace or buffer smaller than required */
+  NFR_ERR_INTERNAL = -7
+};
+
+/* Kernel families w(r), r = |x - y| chordal distance (unnormalised Mexican hats;
+ * the paper's eq. winh is the normalised Gaussian version):
+ *   NFR_KERNEL_GAUSS_MH: w(r) = A_e exp(-r^2 / s_e^2) - A_i exp(-r^2 / s_i^2)
+ *   NFR_KERNEL_EXP_MH:   w(r) = A_e exp(-r / s_e)     - A_i exp(-r / s_i)      */
+enum nfr_kernel_kind { NFR_KERNEL_GAUSS_MH = 0, NFR_KERNEL_EXP_MH = 1 };
+
+typedef struct {
+  int kind;            /* nfr_kernel_kind */
+  double A_e, s_e;     /* excitatory amplitude and length scale, s_e > 0 */
+  double A_i, s_i;     /* inhibitory amplitude and length scale, s_i > 0 */
+} nfr_kernel;
+
+/* Sigmoid firing rate f_b(u) = 1 / (1 + exp(-beta (u - theta_b))) (eq. firing_rate).
+ * theta_b = theta_dev[b] when theta_dev is non-NULL (device, B doubles), else theta. */
+typedef struct {
+  double beta;               /* gain, beta >= 0 (beta = 0 gives f = 1/2) */
+  double theta;              /* threshold shared by all states */
+  const double* theta_dev;   /* optional per-state thresholds (device), may be NULL */
+} nfr_firing;
+
+/* How the operator is evaluated.
+ *   ONTHEFLY_FP32: kernel values recomputed for every pair in FP32, FP32 sums
+ *                  over source tiles, FP64 combination of tile sums.
+ *   W_FP32:        W_ij = w(|x_i - x_j|) q_j precomputed once in FP32 (row-major,
+ *                  N x Npad) and streamed from HBM at every application.
+ *   W_BF16X3 / W_FP16X3: W split as hi + lo in BF16 / FP16 and applied on the
+ *                  matrix cores with FP32 accumulation (three products,
+ *                  hi*hi + hi*lo + lo*hi); requires B >= 2.
+ *   AUTO:          the library picks a form from the problem size and B. */
+enum nfr_form {
+  NFR_FORM_AUTO = -1,
+  NFR_FORM_ONTHEFLY_FP32 = 0,
+  NFR_FORM_W_FP32 = 1,
+  NFR_FORM_W_BF16X3 = 2,
+  NFR_FORM_W_FP16X3 = 3
+};
+
+typedef struct nfr_context nfr_context;
+typedef struct nfr_problem nfr_problem;
+
+/* ---------------------------------------------------------------- status */
+
+int nfr_version(int* major, int* minor, int* patch);
+/* Static string naming a status code (never NULL). */
+const char* nfr_status_string(int status);
+/* Message of the calling thread's most recent failed call ("" if none). */
+const char* nfr_last_error(void);
+
+/* ---------------------------------------------------------------- context */
+
+/* Binds a HIP device and stream.  `hip_stream` is a hipStream_t (NULL = the
+ * default stream).  Fails with NFR_ERR_UNSUPPORTED_ARCH unless the device is
+ * gfx950.  The context is host memory owned by the library until destroy. */
+int nfr_context_create(int device, void* hip_stream, nfr_context** out);
+int nfr_context_destroy(nfr_context* ctx);
+/* Name of the device architecture the context runs on (e.g. "gfx950"). */
+const char* nfr_context_arch(const nfr_context* ctx);
+
+/* Timing of pair-sum launches (the operator's dominant kernel) with HIP events
+ * recorded on the context stream around each launch; not recorded for launches
+ * replayed from graphs.  set_timing(ctx, 1) starts a fresh measurement;
+ * nfr_context_timing synchronises the stream and returns the number of timed
+ * launches and their summed duration in milliseconds, then resets. */
+int nfr_context_set_timing(nfr_context* ctx, int enable);
+int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms);
+
+/* Roofline microbenchmarks (synchronous).  Rates returned in *rate:
+ *   FMA, EXP, SQRT: FP32 lane-operations per second (v_fma / v_exp / v_sqrt),
+ *                   `size` = iterations of 8 independent chains per thread;
+ *   HBM_READ:       bytes per second reading `size` floats from buf_dev;
+ *   HBM_COPY:       bytes per second (read + write) copying `size` floats from
+ *                   the first half of buf_dev to the second half;
+ *   MFMA_BF16:      FLOP per second of 32x32x16 BF16 MFMA, `size` iterations.
+ * buf_dev must hold 4*size bytes plus one float per thread of a grid of
+ * 8 workgroups per compute unit (HBM_READ), 8*size bytes (HBM_COPY), or one
+ * float per thread (others). */
+enum nfr_probe_kind {
+  NFR_PROBE_FMA = 0,
+  NFR_PROBE_EXP = 1,
+  NFR_PROBE_SQRT = 2,
+  NFR_PROBE_HBM_READ = 3,
+  NFR_PROBE_HBM_COPY = 4,
+  NFR_PROBE_MFMA_BF16 = 5
+};
+int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t buf_bytes, double* rate);
+
+/* ---------------------------------------------------------------- problem */
+
+/* Bytes of device memory a packed problem of n nodes occupies. */
+size_t nfr_problem_bytes(int64_t n);
+
+/* Packs a node set (paper section 2.1: nodes Xi; section 2.2: weights mu_j)
+ * into `pack_dev` (caller-owned, >= nfr_problem_bytes(n) bytes, 256-byte
+ * aligned):  coordinates become FP32 (x, y, z) padded to a multiple of 256
+ * nodes, weights stay FP64; padding nodes carry weight 0 and never
+ * contribute.  xyz_dev: n x 3 row-major FP64 (device); q_dev: n FP64 (device).
+ * The inputs are read by a kernel enqueued on the context stream and may be
+ * freed once it has run.  The handle (host memory) references pack_dev, which
+ * must stay allocated until nfr_problem_destroy. */
+int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev,
+                       void* pack_dev, size_t pack_bytes, nfr_problem** out);
+int nfr_problem_destroy(nfr_problem* prob);
+int64_t nfr_problem_n(const nfr_problem* prob);
+/* Padded node count (multiple of 256): the row stride of a W matrix. */
+int64_t nfr_problem_npad(const nfr_problem* prob);
+
+/* ---------------------------------------------------------------- W form */
+
+/* Bytes of a precomputed W for n nodes in a W_* form (0 for other forms). */
+size_t nfr_w_bytes(int64_t n, int form);
+
+/* Builds W_ij = w(|x_i - x_j|) q_j (paper eq. NFODETilde: kernel times quadrature
+ * weight) for targets i < n and sources j < npad into `w_dev` (caller-owned,
+ * >= nfr_w_bytes(n, form), 256-byte aligned).  Rows are targets, row stride
+ * npad elements.  For W_BF16X3 / W_FP16X3 the buffer holds the hi matrix then
+ * the lo matrix, and W is scaled by 2^s with s chosen from the largest |W|
+ * so that FP16 does not underflow (the scale is stored in the buffer). */
+int nfr_w_build(nfr_problem* prob, const nfr_kernel* kernel, int form, void* w_dev, size_t w_bytes);
+
+/* ---------------------------------------------------------------- operator */
+
+size_t nfr_apply_workspace_size(const nfr_problem* prob, int B, int form);
+
+/* One operator application (paper eq. NFODETilde, the sum K~):
+ *   y_dev[b*n + i] = sum_j w(|x_i - x_j|) q_j f_b(u_dev[b*n + j]),  i < n, b < B.
+ * u_dev, y_dev: n x B FP64 (device, state-major, must not overlap).  For W_*
+ * forms `w_dev` is the matrix from nfr_w_build with the same kernel (it is
+ * ignored otherwise and may be NULL). */
+int nfr_apply(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B,
+              const double* u_dev, double* y_dev, int form, const void* w_dev,
+              void* ws_dev, size_t ws_bytes);
+
+/* ---------------------------------------------------------------- time stepping */
+
+size_t nfr_integrate_workspace_size(const nfr_problem* prob, int B, int form);
+
+/* Classical fourth-order Runge-Kutta with fixed step dt for `steps` steps of
+ * u' = -u + K(u) (paper eq. NFODETilde; the stepper is this library's choice):
+ *   k_s = -v_s + K(v_s),  v_1 = u,  v_2 = u + dt/2 k_1,  v_3 = u + dt/2 k_2,
+ *   v_4 = u + dt k_3,     u <- u + dt/6 (k_1 + 2 k_2 + 2 k_3 + k_4),
+ * with every state update in FP64.  u_dev (n x B FP64) holds u(0) on entry and
+ * u(steps * dt) on exit; integration can resume from any state.  If ckpt_dev is
+ * non-NULL it receives u at steps 0, ckpt_every, 2 ckpt_every, ... (each n x B,
+ * consecutive; 1 + steps / ckpt_every of them).  use_graph != 0 replays each
+ * RK4 step from a captured HIP graph (same results, fewer launches). */
+int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B,
+                  double* u_dev, double dt, int64_t steps, int form, const void* w_dev,
+                  double* ckpt_dev, int64_t ckpt_every, int use_graph,
+                  void* ws_dev, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NFR_H */

@@ -1,0 +1,161 @@
+"""Thin torch-facing wrapper over the C ABI (argument marshalling only).
+
+Every computation runs in libnfr.so.  PyTorch provides device memory and the
+stream; tensors are passed as raw device pointers.  States are (B, N) float64
+CUDA tensors: state b is row b, i.e. the state-major N x B layout of the ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int, c_void_p
+
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _dev_buffer(nbytes: int, device) -> torch.Tensor:
+    buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + max(int(nbytes), 1)]
+
+
+def kernel_struct(kind: int, A_e: float, s_e: float, A_i: float, s_i: float) -> L.NfrKernel:
+    return L.NfrKernel(int(kind), float(A_e), float(s_e), float(A_i), float(s_i))
+
+
+class Firing:
+    """Sigmoid firing rate; `theta` is a float or a per-state CUDA float64 tensor."""
+
+    def __init__(self, beta: float, theta):
+        self.beta = float(beta)
+        if isinstance(theta, torch.Tensor):
+            self.theta_t = theta.to(torch.float64).contiguous()
+            self.theta = 0.0
+        else:
+            self.theta_t = None
+            self.theta = float(theta)
+
+    def struct(self, device) -> L.NfrFiring:
+        tp = None
+        if self.theta_t is not None:
+            if self.theta_t.device != device:
+                self.theta_t = self.theta_t.to(device)
+            tp = self.theta_t.data_ptr()
+        return L.NfrFiring(self.beta, self.theta, tp)
+
+
+class Context:
+    """A device and the stream every call of the library is enqueued on."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = c_void_p()
+        L.check(L.lib().nfr_context_create(device, c_void_p(self.stream.cuda_stream), byref(h)))
+        self.handle = h
+
+    @property
+    def arch(self) -> str:
+        return L.lib().nfr_context_arch(self.handle).decode()
+
+    def close(self):
+        if self.handle:
+            L.lib().nfr_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Packed node set: xyz (N, 3) and q (N,) float64 CUDA tensors."""
+
+    def __init__(self, ctx: Context, xyz: torch.Tensor, q: torch.Tensor):
+        if xyz.dim() != 2 or xyz.shape[1] != 3 or q.shape != (xyz.shape[0],):
+            raise ValueError("xyz must be (N, 3) and q (N,)")
+        self.ctx = ctx
+        self.n = int(xyz.shape[0])
+        xyz = xyz.to(ctx.device, torch.float64).contiguous()
+        q = q.to(ctx.device, torch.float64).contiguous()
+        nbytes = L.lib().nfr_problem_bytes(self.n)
+        if nbytes == 0:
+            raise ValueError("unsupported problem size %d" % self.n)
+        self.pack = _dev_buffer(nbytes, ctx.device)
+        h = c_void_p()
+        with torch.cuda.stream(ctx.stream):
+            L.check(L.lib().nfr_problem_create(ctx.handle, self.n, xyz.data_ptr(), q.data_ptr(),
+                                               self.pack.data_ptr(), nbytes, byref(h)))
+        self._keep = (xyz, q)            # the pack kernel reads them asynchronously
+        self.handle = h
+        self.npad = int(L.lib().nfr_problem_npad(h))
+
+    def close(self):
+        if self.handle:
+            L.lib().nfr_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ W form
+
+    def w_build(self, kernel: L.NfrKernel, form: int) -> torch.Tensor:
+        nbytes = L.lib().nfr_w_bytes(self.n, form)
+        if nbytes == 0:
+            raise ValueError("form %d has no W matrix" % form)
+        W = _dev_buffer(nbytes, self.ctx.device)
+        L.check(L.lib().nfr_w_build(self.handle, byref(kernel), form, W.data_ptr(), nbytes))
+        return W
+
+    # ------------------------------------------------------------ operator
+
+    def _check_state(self, u: torch.Tensor) -> int:
+        if u.dtype != torch.float64 or u.dim() != 2 or u.shape[1] != self.n or not u.is_contiguous():
+            raise ValueError("state must be a contiguous (B, N) float64 tensor")
+        if u.device != self.ctx.device:
+            raise ValueError("state is on %s, context on %s" % (u.device, self.ctx.device))
+        return int(u.shape[0])
+
+    def apply(self, kernel: L.NfrKernel, firing: Firing, u: torch.Tensor, form: int = L.FORM_ONTHEFLY_FP32,
+              W: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+        B = self._check_state(u)
+        y = torch.empty_like(u) if out is None else out
+        ws_bytes = L.lib().nfr_apply_workspace_size(self.handle, B, form)
+        ws = _dev_buffer(ws_bytes, self.ctx.device)
+        fs = firing.struct(self.ctx.device)
+        L.check(L.lib().nfr_apply(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), y.data_ptr(), form,
+                                  _ptr(W), ws.data_ptr(), ws_bytes))
+        self._last_ws = ws
+        return y
+
+    def integrate(self, kernel: L.NfrKernel, firing: Firing, u: torch.Tensor, dt: float, steps: int,
+                  form: int = L.FORM_ONTHEFLY_FP32, W: torch.Tensor | None = None, ckpt_every: int = 0,
+                  use_graph: bool = False, ws: torch.Tensor | None = None):
+        """Advances u in place by `steps` RK4 steps; returns checkpoints (K, B, N) or None."""
+        B = self._check_state(u)
+        ws_bytes = L.lib().nfr_integrate_workspace_size(self.handle, B, form)
+        if ws is None or ws.numel() < ws_bytes:
+            ws = _dev_buffer(ws_bytes, self.ctx.device)
+        ck = None
+        if ckpt_every:
+            ck = torch.empty((1 + steps // ckpt_every, B, self.n), dtype=torch.float64, device=self.ctx.device)
+        fs = firing.struct(self.ctx.device)
+        L.check(L.lib().nfr_integrate(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), float(dt), int(steps),
+                                      form, _ptr(W), _ptr(ck), int(ckpt_every), int(bool(use_graph)),
+                                      ws.data_ptr(), ws_bytes))
+        self._last_ws = ws
+        return ck
+
+    def integrate_workspace(self, B: int, form: int) -> torch.Tensor:
+        return _dev_buffer(L.lib().nfr_integrate_workspace_size(self.handle, B, form), self.ctx.device)

@@ -1,0 +1,56 @@
+// Internal definitions shared by the kernels and the C ABI implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nfr {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWG = 256;        // threads per workgroup (four wave64s)
+constexpr int kPad = 256;       // node padding granule
+constexpr double kLog2e = 1.4426950408889634074;
+
+// Device-side view of a packed problem.  Layout inside the caller's buffer:
+//   float4 src[npad]   (x, y, z, 0) in FP32
+//   double q[npad]     quadrature weights, 0 on padding nodes
+//   double xyz[3*npad] FP64 coordinates (row-major), 0 on padding nodes
+struct ProblemView {
+  int64_t n = 0, npad = 0;
+  const float4* src = nullptr;
+  const double* q = nullptr;
+  const double* xyz = nullptr;
+};
+
+// Kernel evaluation in the on-the-fly pair sum.  Coordinates are multiplied by
+// `sig` so that the excitatory exponent becomes exp2(-t) with
+//   Gaussian:    t = |sig (x_i - x_j)|^2,  sig = sqrt(log2 e) / s_e,  rho = s_e^2 / s_i^2
+//   exponential: t = |sig (x_i - x_j)|,    sig = log2 e / s_e,        rho = s_e / s_i
+// and the inhibitory one exp2(-rho t); w = A_e exp2(-t) - A_i exp2(-rho t).
+struct PairParams {
+  float sig;
+  float rho;
+  double Ae;
+  double Ai;
+};
+
+// Sigmoid firing rate; FP64.
+struct Firing {
+  double beta;
+  double theta;
+  const double* theta_dev;  // per state, may be null
+};
+
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__device__ inline double sigmoid(double u, double beta, double theta) {
+  return 1.0 / (1.0 + exp(-beta * (u - theta)));
+}
+
+__device__ inline double state_theta(const Firing& f, int b) {
+  return f.theta_dev ? f.theta_dev[b] : f.theta;
+}
+
+}  // namespace nfr

@@ -1,0 +1,346 @@
+// Core device kernels: problem packing, source preparation, the on-the-fly
+// tiled pair sum, partial reduction, the RK4 stage combination, and the FP32
+// precomputed-W build and apply.
+//
+// Operator (paper section 2.2, eq. NFODETilde):
+//     K_i(u) = sum_j w(|x_i - x_j|) q_j f(u_j),   all j including j = i.
+#pragma once
+
+#include "common.h"
+
+namespace nfr {
+
+// ------------------------------------------------------------------ packing
+
+// xyz (n x 3 FP64) and q (n FP64) -> FP32 float4 coordinates, FP64 weights and
+// FP64 coordinates, each padded to npad with zeros (weight 0: padding sources
+// never contribute; padding targets are computed and discarded).
+__global__ __launch_bounds__(kWG) void k_pack(const double* __restrict__ xyz, const double* __restrict__ q,
+                                              int64_t n, int64_t npad, float4* __restrict__ src,
+                                              double* __restrict__ qd, double* __restrict__ xyz64) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= npad) return;
+  double x = 0.0, y = 0.0, z = 0.0, w = 0.0;
+  if (i < n) {
+    x = xyz[3 * i + 0];
+    y = xyz[3 * i + 1];
+    z = xyz[3 * i + 2];
+    w = q[i];
+  }
+  src[i] = make_float4((float)x, (float)y, (float)z, 0.0f);
+  qd[i] = w;
+  xyz64[3 * i + 0] = x;
+  xyz64[3 * i + 1] = y;
+  xyz64[3 * i + 2] = z;
+}
+
+// ------------------------------------------------------------------ sources
+
+// g[b*npad + j] = s_j f_b(u[b*n + j]) in FP32 with s_j = q_j (with_q) or 1;
+// zero on padding nodes.  Optionally copies u into v (the first RK4 stage input).
+__global__ __launch_bounds__(kWG) void k_source_prep(const double* __restrict__ u, int64_t n, int64_t npad, int B,
+                                                     const double* __restrict__ qd, int with_q, Firing fr,
+                                                     float* __restrict__ g, double* __restrict__ v_copy) {
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (idx >= npad * (int64_t)B) return;
+  const int b = (int)(idx / npad);
+  const int64_t j = idx - (int64_t)b * npad;
+  float out = 0.0f;
+  if (j < n) {
+    const double uj = u[(int64_t)b * n + j];
+    const double s = with_q ? qd[j] : 1.0;
+    out = (float)(s * sigmoid(uj, fr.beta, state_theta(fr, b)));
+    if (v_copy) v_copy[(int64_t)b * n + j] = uj;
+  }
+  g[idx] = out;
+}
+
+// ------------------------------------------------------------------ on-the-fly pair sum
+
+// Partial pair sums over one source chunk:
+//   part[(split*B + b)*npad + i] = sum_{j in chunk(split)} w(|x_i - x_j|) g[b*npad + j]
+// Grid: x = target tiles of kWG*TPT targets (thread t owns tile + t + kWG*k),
+//       y = source chunks of `chunk` nodes (a multiple of kWG),
+//       z = state blocks of BS states.
+// Sources are staged kWG at a time in LDS as scaled float4 coordinates plus
+// their g values and read back as broadcasts.  Each thread sums one LDS tile
+// of kWG sources in FP32 (e and i parts separately), then folds the tile sum
+// into FP64 accumulators: A_e * sum_e - A_i * sum_i.
+template <int KIND, int TPT, int BS>
+__global__ __launch_bounds__(kWG) void k_otf_pair_sum(const float4* __restrict__ src, const float* __restrict__ g,
+                                                      int64_t npad, int B, int64_t chunk, PairParams pp,
+                                                      double* __restrict__ part) {
+  __shared__ float4 s_src[kWG];
+  __shared__ float s_g[BS][kWG];
+  const int tid = threadIdx.x;
+  const int64_t tbase = (int64_t)blockIdx.x * (kWG * TPT);
+  const int split = blockIdx.y;
+  const int b0 = blockIdx.z * BS;
+
+  float xi[TPT], yi[TPT], zi[TPT];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    int64_t t = tbase + tid + (int64_t)kWG * k;
+    if (t >= npad) t = npad - 1;
+    const float4 p = src[t];
+    xi[k] = p.x * pp.sig;
+    yi[k] = p.y * pp.sig;
+    zi[k] = p.z * pp.sig;
+  }
+  double acc[TPT][BS];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k)
+#pragma unroll
+    for (int b = 0; b < BS; ++b) acc[k][b] = 0.0;
+
+  const int64_t j_begin = (int64_t)split * chunk;
+  int64_t j_end = j_begin + chunk;
+  if (j_end > npad) j_end = npad;
+  const float rho = pp.rho;
+
+  for (int64_t j0 = j_begin; j0 < j_end; j0 += kWG) {
+    {
+      const float4 s = src[j0 + tid];
+      s_src[tid] = make_float4(s.x * pp.sig, s.y * pp.sig, s.z * pp.sig, 0.0f);
+#pragma unroll
+      for (int b = 0; b < BS; ++b)
+        s_g[b][tid] = (b0 + b < B) ? g[(int64_t)(b0 + b) * npad + j0 + tid] : 0.0f;
+    }
+    __syncthreads();
+    float ae[TPT][BS], ai[TPT][BS];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k)
+#pragma unroll
+      for (int b = 0; b < BS; ++b) ae[k][b] = ai[k][b] = 0.0f;
+
+#pragma unroll 4
+    for (int jj = 0; jj < kWG; ++jj) {
+      const float4 s = s_src[jj];
+      float gv[BS];
+#pragma unroll
+      for (int b = 0; b < BS; ++b) gv[b] = s_g[b][jj];
+#pragma unroll
+      for (int k = 0; k < TPT; ++k) {
+        const float dx = xi[k] - s.x;
+        const float dy = yi[k] - s.y;
+        const float dz = zi[k] - s.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float t = (KIND == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+        const float e1 = __builtin_amdgcn_exp2f(-t);
+        const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
+#pragma unroll
+        for (int b = 0; b < BS; ++b) {
+          ae[k][b] = fmaf(e1, gv[b], ae[k][b]);
+          ai[k][b] = fmaf(e2, gv[b], ai[k][b]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TPT; ++k)
+#pragma unroll
+      for (int b = 0; b < BS; ++b) acc[k][b] += pp.Ae * (double)ae[k][b] - pp.Ai * (double)ai[k][b];
+  }
+
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int64_t t = tbase + tid + (int64_t)kWG * k;
+    if (t >= npad) continue;
+#pragma unroll
+    for (int b = 0; b < BS; ++b)
+      if (b0 + b < B) part[((int64_t)split * B + b0 + b) * npad + t] = acc[k][b];
+  }
+}
+
+// ------------------------------------------------------------------ reductions
+
+// y[b*n + i] = sum over splits (in order) of part[(s*B + b)*npad + i], FP64.
+__global__ __launch_bounds__(kWG) void k_reduce_partials(const double* __restrict__ part, int nsplit, int64_t n,
+                                                         int64_t npad, int B, double* __restrict__ y) {
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (idx >= n * (int64_t)B) return;
+  const int b = (int)(idx / n);
+  const int64_t i = idx - (int64_t)b * n;
+  double s = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * B + b) * npad + i];
+  y[idx] = s;
+}
+
+// RK4 stage combination, all FP64 (one thread per (i, b), i < n):
+//   y   = sum of partials (= K(v_s)),  k = -v_s + y
+//   s=1: ksum = k,        v <- u + dt/2 k
+//   s=2: ksum += 2k,      v <- u + dt/2 k
+//   s=3: ksum += 2k,      v <- u + dt k
+//   s=4: u <- u + dt/6 (ksum + k),  v <- u
+// then g[b*npad + i] = s_i f_b(v) for the next stage (s_i = q_i or 1).
+__global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ part, int nsplit, int64_t n,
+                                                     int64_t npad, int B, int stage, double dt,
+                                                     double* __restrict__ u, double* __restrict__ v,
+                                                     double* __restrict__ ksum, const double* __restrict__ qd,
+                                                     int with_q, Firing fr, float* __restrict__ g) {
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (idx >= n * (int64_t)B) return;
+  const int b = (int)(idx / n);
+  const int64_t i = idx - (int64_t)b * n;
+  double y = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  const double k = -v[idx] + y;
+  double ui = u[idx];
+  double vn;
+  if (stage == 1) {
+    ksum[idx] = k;
+    vn = ui + 0.5 * dt * k;
+  } else if (stage == 2) {
+    ksum[idx] += 2.0 * k;
+    vn = ui + 0.5 * dt * k;
+  } else if (stage == 3) {
+    ksum[idx] += 2.0 * k;
+    vn = ui + dt * k;
+  } else {
+    ui = ui + (dt / 6.0) * (ksum[idx] + k);
+    u[idx] = ui;
+    vn = ui;
+  }
+  v[idx] = vn;
+  const double s = with_q ? qd[i] : 1.0;
+  g[(int64_t)b * npad + i] = (float)(s * sigmoid(vn, fr.beta, state_theta(fr, b)));
+}
+
+// ------------------------------------------------------------------ W form (FP32)
+
+struct KernelF64 {
+  int kind;
+  double Ae, se, Ai, si;
+};
+
+__device__ inline double kernel_w64(const KernelF64& k, double r2) {
+  if (k.kind == 0) return k.Ae * exp(-r2 / (k.se * k.se)) - k.Ai * exp(-r2 / (k.si * k.si));
+  const double r = sqrt(r2);
+  return k.Ae * exp(-r / k.se) - k.Ai * exp(-r / k.si);
+}
+
+// W[i*npad + j] = w(|x_i - x_j|) q_j, FP64 arithmetic rounded once to FP32;
+// rows i < n, columns j < npad (zero where q_j = 0).
+// Grid: x = rows, y = column blocks of kWG.
+__global__ __launch_bounds__(kWG) void k_w_build_f32(const double* __restrict__ xyz64, const double* __restrict__ qd,
+                                                     int64_t n, int64_t npad, KernelF64 kp, float* __restrict__ W) {
+  const int64_t i = blockIdx.x;
+  const int64_t j = (int64_t)blockIdx.y * kWG + threadIdx.x;
+  if (i >= n || j >= npad) return;
+  const double dx = xyz64[3 * i] - xyz64[3 * j];
+  const double dy = xyz64[3 * i + 1] - xyz64[3 * j + 1];
+  const double dz = xyz64[3 * i + 2] - xyz64[3 * j + 2];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double wq = qd[j] == 0.0 ? 0.0 : kernel_w64(kp, r2) * qd[j];
+  W[i * npad + j] = (float)wq;
+}
+
+// Row-blocked GEMV / small GEMM with W streamed from HBM:
+//   part[(split*B + b)*npad + i] = sum_{j in chunk(split)} W[i*npad + j] G[b*npad + j]
+// WG = 4 waves, each wave owns kRowsPerWave rows; a column step of kColStep
+// stages G in LDS, every lane loads two float4 per row (coalesced 1 KB rows per
+// wave instruction).  Lane partials are FP32 per column step, folded into FP64,
+// then reduced across the wave in FP64.
+constexpr int kRowsPerWave = 4;
+constexpr int kGemvRows = 4 * kRowsPerWave;  // rows per workgroup
+constexpr int kColStep = 2048;
+
+template <int BS>
+__global__ __launch_bounds__(kWG) void k_w_gemv_f32(const float* __restrict__ W, const float* __restrict__ G,
+                                                    int64_t n, int64_t npad, int B, int64_t chunk,
+                                                    double* __restrict__ part) {
+  __shared__ float4 s_g[BS][kColStep / 4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * kGemvRows + wave * kRowsPerWave;
+  const int split = blockIdx.y;
+  const int b0 = blockIdx.z * BS;
+  const int64_t c_begin = (int64_t)split * chunk;
+  int64_t c_end = c_begin + chunk;
+  if (c_end > npad) c_end = npad;
+
+  double acc[kRowsPerWave][BS];
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+    for (int b = 0; b < BS; ++b) acc[r][b] = 0.0;
+
+  const f32x4* W4 = reinterpret_cast<const f32x4*>(W);
+  const int64_t ld4 = npad / 4;
+
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += kColStep) {
+    const int64_t cols = (c_end - c0) < kColStep ? (c_end - c0) : kColStep;   // multiple of 256
+    const int64_t q4 = cols / 4;
+    for (int e = threadIdx.x; e < kColStep / 4; e += kWG) {
+#pragma unroll
+      for (int b = 0; b < BS; ++b) {
+        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < q4 && b0 + b < B) val = reinterpret_cast<const float4*>(G + (int64_t)(b0 + b) * npad + c0)[e];
+        s_g[b][e] = val;
+      }
+    }
+    __syncthreads();
+    float pa[kRowsPerWave][BS];
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+      for (int b = 0; b < BS; ++b) pa[r][b] = 0.0f;
+#pragma unroll
+    for (int h = 0; h < kColStep / 4 / 64; ++h) {
+      const int e = h * 64 + lane;
+      if (e < q4) {
+        float4 wv[kRowsPerWave];
+#pragma unroll
+        for (int r = 0; r < kRowsPerWave; ++r) {
+          const int64_t row = row0 + r;
+          if (row < n) {
+            const f32x4 t = __builtin_nontemporal_load(&W4[row * ld4 + c0 / 4 + e]);
+            wv[r] = make_float4(t.x, t.y, t.z, t.w);
+          } else {
+            wv[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < BS; ++b) {
+          const float4 gv = s_g[b][e];
+#pragma unroll
+          for (int r = 0; r < kRowsPerWave; ++r) {
+            float s = pa[r][b];
+            s = fmaf(wv[r].x, gv.x, s);
+            s = fmaf(wv[r].y, gv.y, s);
+            s = fmaf(wv[r].z, gv.z, s);
+            s = fmaf(wv[r].w, gv.w, s);
+            pa[r][b] = s;
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+      for (int b = 0; b < BS; ++b) acc[r][b] += (double)pa[r][b];
+  }
+
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r)
+#pragma unroll
+    for (int b = 0; b < BS; ++b) {
+      double s = acc[r][b];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      acc[r][b] = s;
+    }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) {
+      const int64_t row = row0 + r;
+      if (row >= npad) continue;
+#pragma unroll
+      for (int b = 0; b < BS; ++b)
+        if (b0 + b < B) part[((int64_t)split * B + b0 + b) * npad + row] = row < n ? acc[r][b] : 0.0;
+    }
+  }
+}
+
+}  // namespace nfr

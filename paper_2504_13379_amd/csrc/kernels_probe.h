@@ -1,0 +1,113 @@
+// Roofline microbenchmarks: issue rates of FP32 FMA, exp2, sqrt; MFMA rate;
+// HBM read and copy bandwidth.  Every kernel touches only `out[gid]` (one float
+// per thread) or the caller's [src, src + n) / [dst, dst + n) ranges.
+#pragma once
+
+#include "common.h"
+
+namespace nfr {
+
+constexpr int kProbeChains = 8;
+
+// Eight independent FMA chains per thread, `iters` iterations each; register
+// operands only (compact accumulate encoding).
+__global__ __launch_bounds__(kWG) void k_probe_fma(int64_t iters, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  float a[kProbeChains], b[kProbeChains];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) {
+    a[c] = 1.0f + 1e-7f * (float)(threadIdx.x + c);
+    b[c] = 1e-9f * (float)((threadIdx.x + 3 * c) & 7);
+  }
+  const float m = 1.0f - 1e-6f * (float)(threadIdx.x & 1);
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) a[c] = fmaf(b[c], m, a[c]);
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) r += a[c];
+  out[gid] = r;
+}
+
+// Eight independent exp2 chains per thread: x <- exp2(-x) stays in (0, 1].
+__global__ __launch_bounds__(kWG) void k_probe_exp(int64_t iters, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  float a[kProbeChains];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) a[c] = 0.5f + 1e-3f * (float)((threadIdx.x + c) & 63);
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) a[c] = __builtin_amdgcn_exp2f(-a[c]);
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) r += a[c];
+  out[gid] = r;
+}
+
+// Eight independent sqrt chains per thread: x <- sqrt(x) + 0.5 stays in [0.5, 2].
+__global__ __launch_bounds__(kWG) void k_probe_sqrt(int64_t iters, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  float a[kProbeChains];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) a[c] = 1.0f + 1e-3f * (float)((threadIdx.x + c) & 63);
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) a[c] = __builtin_amdgcn_sqrtf(a[c]) + 0.5f;
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) r += a[c];
+  out[gid] = r;
+}
+
+// Reads n floats (n a multiple of 4) with a grid-stride float4 loop; one partial per thread.
+__global__ __launch_bounds__(kWG) void k_probe_read(const float* __restrict__ src, int64_t n, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kWG;
+  const f32x4* s4 = reinterpret_cast<const f32x4*>(src);
+  const int64_t n4 = n / 4;
+  float acc = 0.0f;
+  for (int64_t i = gid; i < n4; i += stride) {
+    const f32x4 v = __builtin_nontemporal_load(&s4[i]);
+    acc += (v.x + v.y) + (v.z + v.w);
+  }
+  out[gid] = acc;
+}
+
+// Plain copy of n floats (n a multiple of 4): the reference for HBM byte counters.
+__global__ __launch_bounds__(kWG) void k_probe_copy(const float* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kWG;
+  const f32x4* s4 = reinterpret_cast<const f32x4*>(src);
+  f32x4* d4 = reinterpret_cast<f32x4*>(dst);
+  for (int64_t i = gid; i < n / 4; i += stride) d4[i] = s4[i];
+}
+
+typedef __attribute__((ext_vector_type(8))) __bf16 probe_bf16x8;
+typedef __attribute__((ext_vector_type(16))) float probe_f32x16;
+
+// Four independent 32x32x16 BF16 MFMA accumulation chains per wave.
+__global__ __launch_bounds__(kWG) void k_probe_mfma(int64_t iters, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  probe_bf16x8 a, b;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    a[e] = (__bf16)(1e-3f * (float)((threadIdx.x + e) & 7));
+    b[e] = (__bf16)(1e-3f * (float)((threadIdx.x * 3 + e) & 7));
+  }
+  probe_f32x16 c0 = {}, c1 = {}, c2 = {}, c3 = {};
+  for (int64_t it = 0; it < iters; ++it) {
+    c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c1, 0, 0, 0);
+    c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c2, 0, 0, 0);
+    c3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c3, 0, 0, 0);
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) r += c0[e] + c1[e] + c2[e] + c3[e];
+  out[gid] = r;
+}
+
+}  // namespace nfr

@@ -1,0 +1,639 @@
+// C ABI of the neural-field library: validation, planning and launches.
+// The operator and the time stepper are specified in include/nfr.h.
+#include "nfr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels_core.h"
+#include "kernels_mfma.h"
+#include "kernels_probe.h"
+
+using namespace nfr;
+
+struct nfr_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int cu_count = 0;
+  char arch[64] = {0};
+  // optional event timing of the pair-sum launches (not inside graph capture)
+  bool timing = false;
+  bool capturing = false;
+  std::vector<hipEvent_t> events;
+  size_t events_used = 0;
+};
+
+struct nfr_problem {
+  nfr_context* ctx = nullptr;
+  ProblemView view;
+  void* pack = nullptr;
+};
+
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return code;
+}
+
+#define NFR_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(NFR_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define NFR_HIP_LAUNCH()                                                                    \
+  do {                                                                                      \
+    hipError_t e_ = hipGetLastError();                                                      \
+    if (e_ != hipSuccess) return fail(NFR_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int64_t kMaxN = 4000000;   // keeps every grid dimension below 65536 blocks
+constexpr int kMaxB = 4096;
+
+bool is_finite_d(double x) { return std::isfinite(x); }
+
+int check_kernel(const nfr_kernel* k) {
+  if (!k) return fail(NFR_ERR_INVALID_ARG, "kernel is NULL");
+  if (k->kind != NFR_KERNEL_GAUSS_MH && k->kind != NFR_KERNEL_EXP_MH)
+    return fail(NFR_ERR_INVALID_ARG, "unknown kernel kind %d", k->kind);
+  if (!is_finite_d(k->A_e) || !is_finite_d(k->s_e) || !is_finite_d(k->A_i) || !is_finite_d(k->s_i))
+    return fail(NFR_ERR_NONFINITE, "kernel parameters must be finite");
+  if (!(k->s_e > 0.0) || !(k->s_i > 0.0)) return fail(NFR_ERR_INVALID_ARG, "kernel length scales must be > 0");
+  return NFR_OK;
+}
+
+int check_firing(const nfr_firing* f) {
+  if (!f) return fail(NFR_ERR_INVALID_ARG, "firing is NULL");
+  if (!is_finite_d(f->beta) || !is_finite_d(f->theta)) return fail(NFR_ERR_NONFINITE, "firing parameters must be finite");
+  if (f->beta < 0.0) return fail(NFR_ERR_INVALID_ARG, "beta must be >= 0");
+  return NFR_OK;
+}
+
+int check_form(int form) {
+  if (form < NFR_FORM_AUTO || form > NFR_FORM_W_FP16X3) return fail(NFR_ERR_INVALID_ARG, "unknown form %d", form);
+  if (is_mfma_form(form) && !kMfmaAvailable) return fail(NFR_ERR_INVALID_ARG, "form %d is not available in this build", form);
+  return NFR_OK;
+}
+
+PairParams pair_params(const nfr_kernel& k) {
+  PairParams p;
+  if (k.kind == NFR_KERNEL_GAUSS_MH) {
+    p.sig = (float)(std::sqrt(kLog2e) / k.s_e);
+    p.rho = (float)((k.s_e / k.s_i) * (k.s_e / k.s_i));
+  } else {
+    p.sig = (float)(kLog2e / k.s_e);
+    p.rho = (float)(k.s_e / k.s_i);
+  }
+  p.Ae = k.A_e;
+  p.Ai = k.A_i;
+  return p;
+}
+
+KernelF64 kernel64(const nfr_kernel& k) { return KernelF64{k.kind, k.A_e, k.s_e, k.A_i, k.s_i}; }
+
+Firing firing_of(const nfr_firing& f) { return Firing{f.beta, f.theta, f.theta_dev}; }
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------- plans
+
+constexpr int kOtfTPT = 4;
+constexpr int64_t kTargetWGs = 1024;   // about four workgroups per compute unit
+
+struct OtfPlan {
+  int bs = 1, nsb = 1;
+  int64_t tiles = 0, chunk = 0;
+  int nsplit = 1;
+};
+
+OtfPlan plan_otf(int64_t npad, int B) {
+  OtfPlan p;
+  p.bs = B == 1 ? 1 : (B == 2 ? 2 : 4);
+  p.nsb = (int)ceil_div(B, p.bs);
+  p.tiles = ceil_div(npad, (int64_t)kWG * kOtfTPT);
+  int64_t want = ceil_div(kTargetWGs, p.tiles * p.nsb);
+  const int64_t max_split = npad / kWG;
+  if (want < 1) want = 1;
+  if (want > max_split) want = max_split;
+  p.chunk = round_up(ceil_div(npad, want), kWG);
+  p.nsplit = (int)ceil_div(npad, p.chunk);
+  return p;
+}
+
+struct GemvPlan {
+  int bs = 1, nsb = 1;
+  int64_t rowblocks = 0, chunk = 0;
+  int nsplit = 1;
+};
+
+GemvPlan plan_gemv(int64_t n, int64_t npad, int B) {
+  GemvPlan p;
+  p.bs = B == 1 ? 1 : (B == 2 ? 2 : 4);
+  p.nsb = (int)ceil_div(B, p.bs);
+  p.rowblocks = ceil_div(n, kGemvRows);
+  int64_t want = ceil_div(2 * kTargetWGs, p.rowblocks * p.nsb);
+  const int64_t max_split = ceil_div(npad, kColStep);
+  if (want < 1) want = 1;
+  if (want > max_split) want = max_split;
+  p.chunk = round_up(ceil_div(npad, want), kColStep);
+  p.nsplit = (int)ceil_div(npad, p.chunk);
+  return p;
+}
+
+int resolve_form(int form, int64_t n, int B) {
+  if (form != NFR_FORM_AUTO) return form;
+  (void)n;
+  (void)B;
+  return NFR_FORM_ONTHEFLY_FP32;
+}
+
+int nsplit_for(const ProblemView& pv, int B, int form) {
+  if (form == NFR_FORM_ONTHEFLY_FP32) return plan_otf(pv.npad, B).nsplit;
+  if (form == NFR_FORM_W_FP32) return plan_gemv(pv.n, pv.npad, B).nsplit;
+  return mfma_nsplit(pv.n, pv.npad, B);
+}
+
+struct Workspace {
+  float* g = nullptr;
+  double* part = nullptr;
+  double* v = nullptr;
+  double* ksum = nullptr;
+  size_t bytes = 0;
+};
+
+Workspace carve(void* base, const ProblemView& pv, int B, int form, bool stepping) {
+  Workspace w;
+  char* p = static_cast<char*>(base);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* r = p ? p + off : nullptr;
+    off += align256(bytes);
+    return r;
+  };
+  const size_t gbytes = is_mfma_form(form) ? mfma_g_bytes(pv.npad, B) : size_t(pv.npad) * B * sizeof(float);
+  w.g = reinterpret_cast<float*>(take(gbytes));
+  w.part = reinterpret_cast<double*>(take(size_t(nsplit_for(pv, B, form)) * B * pv.npad * sizeof(double)));
+  if (stepping) {
+    w.v = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
+    w.ksum = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
+  }
+  w.bytes = off;
+  return w;
+}
+
+// ---------------------------------------------------------------- launches
+
+template <int KIND>
+void launch_otf_kind(const ProblemView& pv, const PairParams& pp, int B, const float* g, double* part,
+                     const OtfPlan& pl, hipStream_t s) {
+  dim3 grid((unsigned)pl.tiles, (unsigned)pl.nsplit, (unsigned)pl.nsb);
+  if (pl.bs == 1)
+    hipLaunchKernelGGL((k_otf_pair_sum<KIND, kOtfTPT, 1>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
+  else if (pl.bs == 2)
+    hipLaunchKernelGGL((k_otf_pair_sum<KIND, kOtfTPT, 2>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
+  else
+    hipLaunchKernelGGL((k_otf_pair_sum<KIND, kOtfTPT, 4>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
+}
+
+void launch_gemv(const ProblemView& pv, const float* W, int B, const float* G, double* part, const GemvPlan& pl,
+                 hipStream_t s) {
+  dim3 grid((unsigned)pl.rowblocks, (unsigned)pl.nsplit, (unsigned)pl.nsb);
+  if (pl.bs == 1)
+    hipLaunchKernelGGL((k_w_gemv_f32<1>), grid, dim3(kWG), 0, s, W, G, pv.n, pv.npad, B, pl.chunk, part);
+  else if (pl.bs == 2)
+    hipLaunchKernelGGL((k_w_gemv_f32<2>), grid, dim3(kWG), 0, s, W, G, pv.n, pv.npad, B, pl.chunk, part);
+  else
+    hipLaunchKernelGGL((k_w_gemv_f32<4>), grid, dim3(kWG), 0, s, W, G, pv.n, pv.npad, B, pl.chunk, part);
+}
+
+// Source preparation for a given form; `v_copy` may be null.
+int launch_prep(const ProblemView& pv, int form, int B, const double* u, const Firing& fr, const Workspace& w,
+                double* v_copy, hipStream_t s) {
+  if (is_mfma_form(form)) {
+    launch_mfma_prep(pv, form, B, u, fr, w.g, v_copy, s);
+  } else {
+    const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
+    const int64_t total = pv.npad * (int64_t)B;
+    hipLaunchKernelGGL(k_source_prep, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, u, pv.n, pv.npad, B,
+                       pv.q, with_q, fr, w.g, v_copy);
+  }
+  NFR_HIP_LAUNCH();
+  return NFR_OK;
+}
+
+// Pair sums into w.part for the current w.g.
+int timing_mark(nfr_context* ctx) {
+  if (!ctx->timing || ctx->capturing) return NFR_OK;
+  if (ctx->events_used == ctx->events.size()) {
+    hipEvent_t e;
+    NFR_HIP(hipEventCreate(&e));
+    ctx->events.push_back(e);
+  }
+  NFR_HIP(hipEventRecord(ctx->events[ctx->events_used++], ctx->stream));
+  return NFR_OK;
+}
+
+int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B, const void* W, const Workspace& w,
+                     hipStream_t s) {
+  if (form == NFR_FORM_ONTHEFLY_FP32) {
+    const OtfPlan pl = plan_otf(pv.npad, B);
+    const PairParams pp = pair_params(k);
+    if (k.kind == NFR_KERNEL_GAUSS_MH)
+      launch_otf_kind<0>(pv, pp, B, w.g, w.part, pl, s);
+    else
+      launch_otf_kind<1>(pv, pp, B, w.g, w.part, pl, s);
+  } else if (form == NFR_FORM_W_FP32) {
+    launch_gemv(pv, static_cast<const float*>(W), B, w.g, w.part, plan_gemv(pv.n, pv.npad, B), s);
+  } else {
+    launch_mfma_apply(pv, form, B, W, w.g, w.part, s);
+  }
+  NFR_HIP_LAUNCH();
+  return NFR_OK;
+}
+
+// The pair-sum launch of one operator application, bracketed by timing events when enabled.
+int launch_pairs(nfr_context* ctx, const ProblemView& pv, const nfr_kernel& k, int form, int B, const void* W,
+                 const Workspace& w) {
+  int st;
+  if ((st = timing_mark(ctx))) return st;
+  if ((st = launch_pairs_raw(pv, k, form, B, W, w, ctx->stream))) return st;
+  return timing_mark(ctx);
+}
+
+int launch_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, const Workspace& w,
+                   const Firing& fr, hipStream_t s) {
+  const int nsplit = nsplit_for(pv, B, form);
+  const int64_t total = pv.n * (int64_t)B;
+  if (is_mfma_form(form)) {
+    launch_mfma_combine(pv, form, B, stage, dt, u, w.v, w.ksum, w.part, nsplit, fr, w.g, s);
+  } else {
+    const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
+    hipLaunchKernelGGL(k_rk4_combine, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
+                       pv.npad, B, stage, dt, u, w.v, w.ksum, pv.q, with_q, fr, w.g);
+  }
+  NFR_HIP_LAUNCH();
+  return NFR_OK;
+}
+
+int check_problem(const nfr_problem* p) {
+  if (!p || !p->ctx) return fail(NFR_ERR_INVALID_ARG, "problem is NULL");
+  return NFR_OK;
+}
+
+int check_w(const nfr_problem* p, int form, const void* w_dev) {
+  if (form == NFR_FORM_ONTHEFLY_FP32) return NFR_OK;
+  if (!w_dev) return fail(NFR_ERR_INVALID_ARG, "form %d needs a W matrix (w_dev is NULL)", form);
+  (void)p;
+  return NFR_OK;
+}
+
+int check_mfma_b(int form, int B) {
+  if (is_mfma_form(form) && B < 2) return fail(NFR_ERR_INVALID_ARG, "split-precision MFMA forms need B >= 2");
+  return NFR_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+int nfr_version(int* major, int* minor, int* patch) {
+  if (!major || !minor || !patch) return fail(NFR_ERR_INVALID_ARG, "NULL output pointer");
+  *major = NFR_VERSION_MAJOR;
+  *minor = NFR_VERSION_MINOR;
+  *patch = NFR_VERSION_PATCH;
+  return NFR_OK;
+}
+
+const char* nfr_status_string(int status) {
+  switch (status) {
+    case NFR_OK: return "NFR_OK";
+    case NFR_ERR_INVALID_ARG: return "NFR_ERR_INVALID_ARG";
+    case NFR_ERR_NONFINITE: return "NFR_ERR_NONFINITE";
+    case NFR_ERR_NO_DEVICE: return "NFR_ERR_NO_DEVICE";
+    case NFR_ERR_UNSUPPORTED_ARCH: return "NFR_ERR_UNSUPPORTED_ARCH";
+    case NFR_ERR_HIP: return "NFR_ERR_HIP";
+    case NFR_ERR_WORKSPACE: return "NFR_ERR_WORKSPACE";
+    case NFR_ERR_INTERNAL: return "NFR_ERR_INTERNAL";
+    default: return "NFR_ERR_UNKNOWN";
+  }
+}
+
+const char* nfr_last_error(void) { return t_err.c_str(); }
+
+int nfr_context_create(int device, void* hip_stream, nfr_context** out) {
+  if (!out) return fail(NFR_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(NFR_ERR_NO_DEVICE, "no HIP device");
+  if (device < 0 || device >= count) return fail(NFR_ERR_NO_DEVICE, "device %d out of range (count %d)", device, count);
+  hipDeviceProp_t prop;
+  NFR_HIP(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(NFR_ERR_UNSUPPORTED_ARCH, "device %d is %s, this library is built for gfx950", device, prop.gcnArchName);
+  nfr_context* c = new (std::nothrow) nfr_context;
+  if (!c) return fail(NFR_ERR_INTERNAL, "out of host memory");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->cu_count = prop.multiProcessorCount;
+  std::snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+  *out = c;
+  return NFR_OK;
+}
+
+int nfr_context_destroy(nfr_context* ctx) {
+  if (ctx)
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  delete ctx;
+  return NFR_OK;
+}
+
+int nfr_context_set_timing(nfr_context* ctx, int enable) {
+  if (!ctx) return fail(NFR_ERR_INVALID_ARG, "context is NULL");
+  ctx->timing = enable != 0;
+  ctx->events_used = 0;
+  return NFR_OK;
+}
+
+int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms) {
+  if (!ctx || !launches || !total_ms) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
+  NFR_HIP(hipSetDevice(ctx->device));
+  NFR_HIP(hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < ctx->events_used; i += 2) {
+    float ms = 0.0f;
+    NFR_HIP(hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]));
+    tot += ms;
+  }
+  *launches = (int64_t)(ctx->events_used / 2);
+  *total_ms = tot;
+  ctx->events_used = 0;
+  return NFR_OK;
+}
+
+int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t buf_bytes, double* rate) {
+  if (!ctx || !buf_dev || !rate) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
+  if (which < NFR_PROBE_FMA || which > NFR_PROBE_MFMA_BF16) return fail(NFR_ERR_INVALID_ARG, "unknown probe %d", which);
+  if (size < 1) return fail(NFR_ERR_INVALID_ARG, "size must be >= 1");
+  const int64_t grid = (int64_t)ctx->cu_count * 8;
+  const size_t out_bytes = size_t(grid) * kWG * sizeof(float);
+  const bool memprobe = which == NFR_PROBE_HBM_READ || which == NFR_PROBE_HBM_COPY;
+  if (memprobe && size % 4) return fail(NFR_ERR_INVALID_ARG, "size must be a multiple of 4 floats");
+  const size_t need = memprobe ? (which == NFR_PROBE_HBM_READ ? size_t(size) * 4 + out_bytes : size_t(size) * 8)
+                               : out_bytes;
+  if (buf_bytes < need) return fail(NFR_ERR_WORKSPACE, "probe buffer has %zu bytes, needs %zu", buf_bytes, need);
+  NFR_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0, e1;
+  NFR_HIP(hipEventCreate(&e0));
+  NFR_HIP(hipEventCreate(&e1));
+  float* f = static_cast<float*>(buf_dev);
+  NFR_HIP(hipEventRecord(e0, s));
+  const dim3 g((unsigned)grid), b(kWG);
+  switch (which) {
+    case NFR_PROBE_FMA: hipLaunchKernelGGL(k_probe_fma, g, b, 0, s, size, f); break;
+    case NFR_PROBE_EXP: hipLaunchKernelGGL(k_probe_exp, g, b, 0, s, size, f); break;
+    case NFR_PROBE_SQRT: hipLaunchKernelGGL(k_probe_sqrt, g, b, 0, s, size, f); break;
+    case NFR_PROBE_HBM_READ: hipLaunchKernelGGL(k_probe_read, g, b, 0, s, f, size, f + size); break;
+    case NFR_PROBE_HBM_COPY: hipLaunchKernelGGL(k_probe_copy, g, b, 0, s, f, f + size, size); break;
+    default: hipLaunchKernelGGL(k_probe_mfma, g, b, 0, s, size, f); break;
+  }
+  hipError_t le = hipGetLastError();
+  NFR_HIP(hipEventRecord(e1, s));
+  NFR_HIP(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  NFR_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (le != hipSuccess) return fail(NFR_ERR_HIP, "probe launch failed: %s", hipGetErrorString(le));
+  const double sec = ms * 1e-3;
+  const double lanes = double(grid) * kWG;
+  switch (which) {
+    case NFR_PROBE_FMA:
+    case NFR_PROBE_EXP:
+    case NFR_PROBE_SQRT: *rate = lanes * kProbeChains * double(size) / sec; break;
+    case NFR_PROBE_HBM_READ: *rate = double(size) * 4 / sec; break;
+    case NFR_PROBE_HBM_COPY: *rate = double(size) * 8 / sec; break;
+    default: *rate = double(grid) * (kWG / 64) * 4 * double(size) * (32.0 * 32 * 16 * 2) / sec; break;
+  }
+  return NFR_OK;
+}
+
+const char* nfr_context_arch(const nfr_context* ctx) { return ctx ? ctx->arch : ""; }
+
+size_t nfr_problem_bytes(int64_t n) {
+  if (n < 1 || n > kMaxN) return 0;
+  const int64_t npad = round_up(n, kPad);
+  return align256(npad * sizeof(float4)) + align256(npad * sizeof(double)) + align256(3 * npad * sizeof(double));
+}
+
+int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev, void* pack_dev,
+                       size_t pack_bytes, nfr_problem** out) {
+  if (!out) return fail(NFR_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(NFR_ERR_INVALID_ARG, "context is NULL");
+  if (n < 1 || n > kMaxN) return fail(NFR_ERR_INVALID_ARG, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxN);
+  if (!xyz_dev || !q_dev || !pack_dev) return fail(NFR_ERR_INVALID_ARG, "NULL device pointer");
+  if (reinterpret_cast<uintptr_t>(pack_dev) % 256) return fail(NFR_ERR_INVALID_ARG, "pack buffer must be 256-byte aligned");
+  const size_t need = nfr_problem_bytes(n);
+  if (pack_bytes < need) return fail(NFR_ERR_WORKSPACE, "pack buffer has %zu bytes, needs %zu", pack_bytes, need);
+  NFR_HIP(hipSetDevice(ctx->device));
+  nfr_problem* p = new (std::nothrow) nfr_problem;
+  if (!p) return fail(NFR_ERR_INTERNAL, "out of host memory");
+  const int64_t npad = round_up(n, kPad);
+  char* base = static_cast<char*>(pack_dev);
+  p->ctx = ctx;
+  p->pack = pack_dev;
+  p->view.n = n;
+  p->view.npad = npad;
+  p->view.src = reinterpret_cast<const float4*>(base);
+  p->view.q = reinterpret_cast<const double*>(base + align256(npad * sizeof(float4)));
+  p->view.xyz = reinterpret_cast<const double*>(base + align256(npad * sizeof(float4)) + align256(npad * sizeof(double)));
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, ctx->stream, xyz_dev, q_dev, n, npad,
+                     const_cast<float4*>(p->view.src), const_cast<double*>(p->view.q), const_cast<double*>(p->view.xyz));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete p;
+    return fail(NFR_ERR_HIP, "pack launch failed: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return NFR_OK;
+}
+
+int nfr_problem_destroy(nfr_problem* prob) {
+  delete prob;
+  return NFR_OK;
+}
+
+int64_t nfr_problem_n(const nfr_problem* prob) { return prob ? prob->view.n : -1; }
+int64_t nfr_problem_npad(const nfr_problem* prob) { return prob ? prob->view.npad : -1; }
+
+size_t nfr_w_bytes(int64_t n, int form) {
+  if (n < 1 || n > kMaxN) return 0;
+  const int64_t npad = round_up(n, kPad);
+  if (form == NFR_FORM_W_FP32) return align256(size_t(n) * npad * sizeof(float));
+  if (is_mfma_form(form)) return mfma_w_bytes(n, npad);
+  return 0;
+}
+
+int nfr_w_build(nfr_problem* prob, const nfr_kernel* kernel, int form, void* w_dev, size_t w_bytes) {
+  int st;
+  if ((st = check_problem(prob)) || (st = check_kernel(kernel))) return st;
+  if ((st = check_form(form))) return st;
+  if (form != NFR_FORM_W_FP32 && !is_mfma_form(form)) return fail(NFR_ERR_INVALID_ARG, "form %d has no W matrix", form);
+  if (!w_dev) return fail(NFR_ERR_INVALID_ARG, "w_dev is NULL");
+  if (reinterpret_cast<uintptr_t>(w_dev) % 256) return fail(NFR_ERR_INVALID_ARG, "W buffer must be 256-byte aligned");
+  const ProblemView& pv = prob->view;
+  const size_t need = nfr_w_bytes(pv.n, form);
+  if (w_bytes < need) return fail(NFR_ERR_WORKSPACE, "W buffer has %zu bytes, needs %zu", w_bytes, need);
+  NFR_HIP(hipSetDevice(prob->ctx->device));
+  hipStream_t s = prob->ctx->stream;
+  if (form == NFR_FORM_W_FP32) {
+    hipLaunchKernelGGL(k_w_build_f32, dim3((unsigned)pv.n, (unsigned)ceil_div(pv.npad, kWG)), dim3(kWG), 0, s, pv.xyz,
+                       pv.q, pv.n, pv.npad, kernel64(*kernel), static_cast<float*>(w_dev));
+  } else {
+    launch_mfma_w_build(pv, form, kernel64(*kernel), w_dev, s);
+  }
+  NFR_HIP_LAUNCH();
+  return NFR_OK;
+}
+
+size_t nfr_apply_workspace_size(const nfr_problem* prob, int B, int form) {
+  if (!prob || B < 1 || B > kMaxB) return 0;
+  form = resolve_form(form, prob->view.n, B);
+  return carve(nullptr, prob->view, B, form, false).bytes;
+}
+
+int nfr_apply(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, const double* u_dev,
+              double* y_dev, int form, const void* w_dev, void* ws_dev, size_t ws_bytes) {
+  int st;
+  if ((st = check_problem(prob)) || (st = check_kernel(kernel)) || (st = check_firing(firing)) || (st = check_form(form)))
+    return st;
+  if (B < 1 || B > kMaxB) return fail(NFR_ERR_INVALID_ARG, "B = %d outside [1, %d]", B, kMaxB);
+  if (!u_dev || !y_dev) return fail(NFR_ERR_INVALID_ARG, "NULL state pointer");
+  const ProblemView& pv = prob->view;
+  form = resolve_form(form, pv.n, B);
+  if ((st = check_w(prob, form, w_dev)) || (st = check_mfma_b(form, B))) return st;
+  const Workspace w = carve(ws_dev, pv, B, form, false);
+  if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
+  NFR_HIP(hipSetDevice(prob->ctx->device));
+  hipStream_t s = prob->ctx->stream;
+  const Firing fr = firing_of(*firing);
+  if ((st = launch_prep(pv, form, B, u_dev, fr, w, nullptr, s))) return st;
+  if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return st;
+  const int nsplit = nsplit_for(pv, B, form);
+  const int64_t total = pv.n * (int64_t)B;
+  if (is_mfma_form(form))
+    launch_mfma_reduce(pv, form, B, w.part, nsplit, y_dev, s);
+  else
+    hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
+                       pv.npad, B, y_dev);
+  NFR_HIP_LAUNCH();
+  return NFR_OK;
+}
+
+size_t nfr_integrate_workspace_size(const nfr_problem* prob, int B, int form) {
+  if (!prob || B < 1 || B > kMaxB) return 0;
+  form = resolve_form(form, prob->view.n, B);
+  return carve(nullptr, prob->view, B, form, true).bytes;
+}
+
+int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, double* u_dev,
+                  double dt, int64_t steps, int form, const void* w_dev, double* ckpt_dev, int64_t ckpt_every,
+                  int use_graph, void* ws_dev, size_t ws_bytes) {
+  int st;
+  if ((st = check_problem(prob)) || (st = check_kernel(kernel)) || (st = check_firing(firing)) || (st = check_form(form)))
+    return st;
+  if (B < 1 || B > kMaxB) return fail(NFR_ERR_INVALID_ARG, "B = %d outside [1, %d]", B, kMaxB);
+  if (!u_dev) return fail(NFR_ERR_INVALID_ARG, "u_dev is NULL");
+  if (!is_finite_d(dt)) return fail(NFR_ERR_NONFINITE, "dt must be finite");
+  if (!(dt > 0.0)) return fail(NFR_ERR_INVALID_ARG, "dt must be > 0");
+  if (steps < 0) return fail(NFR_ERR_INVALID_ARG, "steps must be >= 0");
+  if (ckpt_dev && ckpt_every < 1) return fail(NFR_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+  const ProblemView& pv = prob->view;
+  form = resolve_form(form, pv.n, B);
+  if ((st = check_w(prob, form, w_dev)) || (st = check_mfma_b(form, B))) return st;
+  const Workspace w = carve(ws_dev, pv, B, form, true);
+  if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
+  if (use_graph && prob->ctx->stream == nullptr)
+    return fail(NFR_ERR_INVALID_ARG, "graph replay needs a non-default stream");
+  NFR_HIP(hipSetDevice(prob->ctx->device));
+  hipStream_t s = prob->ctx->stream;
+  const Firing fr = firing_of(*firing);
+  const size_t state_bytes = size_t(pv.n) * B * sizeof(double);
+  if (ckpt_dev) NFR_HIP(hipMemcpyAsync(ckpt_dev, u_dev, state_bytes, hipMemcpyDeviceToDevice, s));
+  if (steps == 0) return NFR_OK;
+  if ((st = launch_prep(pv, form, B, u_dev, fr, w, w.v, s))) return st;
+
+  auto one_step = [&]() -> int {
+    for (int stage = 1; stage <= 4; ++stage) {
+      int r;
+      if ((r = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return r;
+      if ((r = launch_combine(pv, form, B, stage, dt, u_dev, w, fr, s))) return r;
+    }
+    return NFR_OK;
+  };
+
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    NFR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    prob->ctx->capturing = true;
+    const int r = one_step();
+    prob->ctx->capturing = false;
+    const hipError_t e_end = hipStreamEndCapture(s, &graph);
+    if (r) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r;
+    }
+    if (e_end != hipSuccess) return fail(NFR_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e_end));
+    const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e_inst != hipSuccess) return fail(NFR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e_inst));
+  }
+  int result = NFR_OK;
+  for (int64_t step = 0; step < steps; ++step) {
+    if (exec) {
+      const hipError_t e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) {
+        result = fail(NFR_ERR_HIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
+        break;
+      }
+    } else if ((result = one_step())) {
+      break;
+    }
+    if (ckpt_dev && (step + 1) % ckpt_every == 0) {
+      const hipError_t e = hipMemcpyAsync(ckpt_dev + ((step + 1) / ckpt_every) * (int64_t)pv.n * B, u_dev, state_bytes,
+                                          hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) {
+        result = fail(NFR_ERR_HIP, "checkpoint copy failed: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+  }
+  if (exec) {
+    // the executable graph may only be released once its launches have run
+    const hipError_t e = hipStreamSynchronize(s);
+    (void)hipGraphExecDestroy(exec);
+    if (e != hipSuccess && result == NFR_OK) result = fail(NFR_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+  }
+  return result;
+}
+
+}  // extern "C"

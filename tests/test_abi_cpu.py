@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/nfr.h declares, and rejects bad arguments before any
+device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nfr.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nfr_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2504_13379_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ("nfr_apply", "nfr_integrate", "nfr_w_build", "nfr_problem_create", "nfr_context_create"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version(L):
+    assert L.nfr_status_string(0) == b"NFR_OK"
+    assert L.nfr_status_string(-6) == b"NFR_ERR_WORKSPACE"
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert L.nfr_version(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == 0
+    assert (a.value, b.value) == (0, 1)
+
+
+def test_size_queries(L):
+    assert L.nfr_problem_bytes(0) == 0
+    assert L.nfr_problem_bytes(1) > 0
+    npad = 32768
+    assert L.nfr_w_bytes(32768, 1) == 32768 * npad * 4
+    assert L.nfr_w_bytes(1000, 0) == 0
+
+
+def test_null_arguments_rejected_before_device_work(L):
+    from paper_2504_13379_amd import _lib
+    k = _lib.NfrKernel(0, 1.0, 0.15, 0.5, 0.4)
+    f = _lib.NfrFiring(20.0, 0.2, None)
+    st = L.nfr_apply(None, ctypes.byref(k), ctypes.byref(f), 1, None, None, 0, None, None, 0)
+    assert st == _lib.NFR_ERR_INVALID_ARG
+    assert b"problem" in L.nfr_last_error()
+    st = L.nfr_integrate(None, ctypes.byref(k), ctypes.byref(f), 1, None, 0.05, 1, 0, None, None, 0, 0, None, 0)
+    assert st == _lib.NFR_ERR_INVALID_ARG
+    out = ctypes.c_void_p()
+    assert L.nfr_problem_create(None, 10, None, None, None, 0, ctypes.byref(out)) == _lib.NFR_ERR_INVALID_ARG
+
+
+def test_context_without_gpu_reports_no_device(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2504_13379_amd import _lib
+    out = ctypes.c_void_p()
+    assert L.nfr_context_create(0, None, ctypes.byref(out)) == _lib.NFR_ERR_NO_DEVICE

@@ -1,0 +1,209 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances come from the arithmetic:
+* operator (one application), on-the-fly FP32: every pair term carries a few
+  FP32 roundings (coordinates, differences, sqrt/exp, products) plus FP32 sums
+  over 256-source tiles, i.e. a relative error of a few 1e-7 of the term;
+  compared norm-wise against S_i = sum_j |w_ij q_j f(u_j)|:  |dy_i| <= 1e-5 S_i.
+* W_FP32: W and f rounded once to FP32, FP32 row-chunk sums: |dy_i| <= 2e-6 S_i.
+* time integration: u(T) to relative L-infinity <= 1e-5 per state (the target
+  stated for the FP32 path).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import neural_field as NF
+from oracle import quadrature as Q
+from workloads import configs as C
+from workloads import surfaces as S
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2504_13379_amd")
+
+GAUSS = (1.0, 0.15, 0.5, 0.4)
+EXPK = (2.0, 0.1, 1.0, 0.3)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return P.Context(0)
+
+
+def _abs_scale(x, q, U, kind, p, beta, theta, rows):
+    G = q[None, :] * NF.firing(U, beta, theta)
+    W = np.abs(NF.kernel_matrix(x, kind, p, rows=rows))
+    return np.abs(G) @ W.T
+
+
+def _run_apply(ctx, x, q, U, kind, p, beta, theta, form):
+    prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
+    k = P.kernel_struct(kind, *p)
+    th = torch.from_numpy(np.asarray(theta, dtype=np.float64)).cuda() if np.ndim(theta) else float(theta)
+    f = P.Firing(beta, th)
+    u = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+    W = prob.w_build(k, form) if form != P.FORM_ONTHEFLY_FP32 else None
+    y = prob.apply(k, f, u, form=form, W=W)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+CASES = [(1, 1), (2, 1), (7, 2), (255, 1), (256, 3), (257, 1), (1000, 5), (3001, 2)]
+
+
+@pytest.mark.parametrize("n,B", CASES)
+@pytest.mark.parametrize("kind", [NF.GAUSS_MH, NF.EXP_MH])
+@pytest.mark.parametrize("form", [0, 1])
+def test_apply_matches_oracle(ctx, n, B, kind, form):
+    rng = np.random.default_rng(1000 * n + 10 * B + kind)
+    x = S.fibonacci_sphere(n) * rng.uniform(0.9, 1.1)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    if n > 3:
+        q[rng.integers(n)] *= -0.1
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.1, 0.3, size=B) if B > 1 else 0.2
+    p = GAUSS if kind == NF.GAUSS_MH else EXPK
+    y = _run_apply(ctx, x, q, U, kind, p, 20.0, theta, form)
+    ref = NF.apply_K(x, q, U, kind, p, 20.0, theta)
+    scale = _abs_scale(x, q, U, kind, p, 20.0, theta, None)
+    tol = 1e-5 if form == 0 else 2e-6
+    err = np.max(np.abs(y - ref) / scale)
+    assert err <= tol, err
+
+
+def test_apply_full_size_torus_sampled_rows(ctx):
+    """Torus workload at its full size (N = 32768): one application, 64 sampled rows."""
+    w = C.torus_exp()
+    x = w.surface.xyz
+    q = C.area_share_weights(w.surface)
+    rows = np.random.default_rng(5).choice(w.n, 64, replace=False)
+    ref = NF.apply_K(x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows=rows)
+    scale = _abs_scale(x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows)
+    for form in (0, 1):
+        y = _run_apply(ctx, x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, form)
+        err = np.max(np.abs(y[:, rows] - ref) / scale)
+        assert err <= (1e-5 if form == 0 else 2e-6), (form, err)
+
+
+def _integrate(ctx, x, q, U, kind, p, beta, theta, dt, steps, form=0, graph=False, ckpt_every=0):
+    stream = torch.cuda.Stream() if graph else None
+    c = P.Context(0, stream) if graph else ctx
+    prob = P.Problem(c, torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
+    k = P.kernel_struct(kind, *p)
+    th = torch.from_numpy(np.asarray(theta, dtype=np.float64)).cuda() if np.ndim(theta) else float(theta)
+    f = P.Firing(beta, th)
+    u = torch.from_numpy(np.ascontiguousarray(U, dtype=np.float64)).cuda()
+    W = prob.w_build(k, form) if form != 0 else None
+    ck = prob.integrate(k, f, u, dt, steps, form=form, W=W, use_graph=graph, ckpt_every=ckpt_every)
+    torch.cuda.synchronize()
+    out = u.cpu().numpy()
+    return (out, ck.cpu().numpy()) if ckpt_every else out
+
+
+@pytest.fixture(scope="module")
+def sphere_case():
+    w = C.sphere_small()
+    q = Q.surface_weights(w.surface)
+    op = NF.DenseOperator(w.surface.xyz, q, w.kernel_kind, w.kernel)
+    ref = NF.rk4(op, w.u0, w.beta, w.theta, w.dt, w.steps)
+    return w, q, ref
+
+
+def test_integrate_sphere_workload_fp32(ctx, sphere_case):
+    """Unit sphere, N = 2000, Gaussian Mexican hat, 50 RK4 steps, FP32 on the fly."""
+    w, q, ref = sphere_case
+    u = _integrate(ctx, w.surface.xyz, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta[0], w.dt, w.steps)
+    err = NF.rel_linf(u, ref)
+    assert np.all(err <= 1e-5), err
+
+
+def test_integrate_sphere_workload_w_form(ctx, sphere_case):
+    w, q, ref = sphere_case
+    u = _integrate(ctx, w.surface.xyz, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta[0], w.dt, w.steps, form=1)
+    assert np.all(NF.rel_linf(u, ref) <= 1e-5)
+
+
+@pytest.fixture(scope="module")
+def torus_case():
+    w = C.torus_exp(4096, steps=100)
+    q = Q.surface_weights(w.surface)
+    op = NF.DenseOperator(w.surface.xyz, q, w.kernel_kind, w.kernel)
+    return w, q, NF.rk4(op, w.u0, w.beta, w.theta, w.dt, w.steps)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_integrate_torus_exp_kernel(ctx, torus_case, form):
+    w, q, ref = torus_case
+    u = _integrate(ctx, w.surface.xyz, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta[0], w.dt, w.steps, form=form)
+    err = NF.rel_linf(u, ref)
+    assert np.all(err <= 1e-5), err
+
+
+def test_integrate_ensemble_per_state_theta(ctx):
+    w = C.ellipsoid_ensemble(3000, 5, steps=20)
+    q = Q.surface_weights(w.surface)
+    op = NF.DenseOperator(w.surface.xyz, q, w.kernel_kind, w.kernel)
+    ref = NF.rk4(op, w.u0, w.beta, w.theta, w.dt, w.steps)
+    for form in (0, 1):
+        u = _integrate(ctx, w.surface.xyz, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, w.dt, w.steps, form)
+        err = NF.rel_linf(u, ref)
+        assert np.all(err <= 1e-5), (form, err)
+
+
+def test_integrate_beta_zero_closed_form_full_size(ctx):
+    """beta = 0: u_n = b + R(-dt)^n (u0 - b), b_i = K_i = sum_j w_ij q_j / 2 (f = 1/2),
+    checked at sampled rows of the full-size torus workload (N = 32768)."""
+    w = C.torus_exp()
+    x = w.surface.xyz
+    q = C.area_share_weights(w.surface)
+    steps = 20
+    u = _integrate(ctx, x, q, w.u0, w.kernel_kind, w.kernel, 0.0, 0.25, w.dt, steps)
+    rows = np.random.default_rng(6).choice(w.n, 64, replace=False)
+    b = NF.apply_K(x, q, np.zeros((1, w.n)), w.kernel_kind, w.kernel, 0.0, 0.25, rows=rows)[0]
+    z = -w.dt
+    R = (1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24) ** steps
+    expect = b + R * (w.u0[0, rows] - b)
+    assert np.max(np.abs(u[0, rows] - expect)) <= 1e-5 * np.max(np.abs(expect))
+
+
+def test_integrate_deterministic_graph_and_resume(ctx, sphere_case):
+    w, q, _ = sphere_case
+    args = (w.surface.xyz, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta[0], w.dt)
+    a = _integrate(ctx, *args, 30)
+    b = _integrate(ctx, *args, 30)
+    g = _integrate(ctx, *args, 30, graph=True)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, g)
+    half = _integrate(ctx, *args, 15)
+    resumed = _integrate(ctx, w.surface.xyz, q, half, w.kernel_kind, w.kernel, w.beta, w.theta[0], w.dt, 15)
+    assert np.array_equal(a, resumed)
+    full, ck = _integrate(ctx, *args, 30, ckpt_every=10)
+    assert ck.shape == (4, 1, w.n)
+    assert np.array_equal(ck[0], w.u0)
+    assert np.array_equal(ck[3], a)
+    assert np.array_equal(ck[1], _integrate(ctx, *args, 10))
+
+
+def test_invalid_arguments_rejected(ctx):
+    x = S.fibonacci_sphere(100)
+    prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.full((100,), 0.1, dtype=torch.float64).cuda())
+    u = torch.zeros((1, 100), dtype=torch.float64, device="cuda")
+    f = P.Firing(20.0, 0.2)
+    with pytest.raises(P.NfrError) as e:
+        prob.apply(P.kernel_struct(0, 1.0, -0.15, 0.5, 0.4), f, u)
+    assert e.value.status == -1
+    with pytest.raises(P.NfrError) as e:
+        prob.apply(P.kernel_struct(0, float("nan"), 0.15, 0.5, 0.4), f, u)
+    assert e.value.status == -2
+    with pytest.raises(P.NfrError):
+        prob.integrate(P.kernel_struct(0, *GAUSS), f, u, -0.1, 3)
+    with pytest.raises(P.NfrError):
+        prob.apply(P.kernel_struct(0, *GAUSS), f, u, form=1, W=None)
+    with pytest.raises(P.NfrError) as e:
+        prob.apply(P.kernel_struct(7, *GAUSS), f, u)
+    assert e.value.status == -1
