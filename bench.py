@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--forms", default="otf,w32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="also run the roofline microbenchmarks")
+    ap.add_argument("--ens-rk4-steps", type=int, default=10,
+                    help="RK4 steps of the ellipsoid-ensemble comparison leg (0 = skip it)")
     return ap.parse_args()
 
 
@@ -100,6 +102,66 @@ def roofline(form_name, res, n, npad):
     ach = ops / avg_s
     return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tlane-op/s",
             "frac": ach / VALU_LANES_PER_S, "traffic": None, "kernel": "k_otf_pair_sum<1,4,1>"}
+
+
+def ensemble_leg(P, torch, args):
+    """Ellipsoid (1, .8, .6), N = 65536, B = 64 Gaussian-kernel ensemble: the split-precision
+    MFMA W forms against the plain FP32 on-the-fly path on the same GPU."""
+    import ctypes
+
+    from workloads import configs as C
+    w = C.ellipsoid_ensemble(65536, 64, steps=args.ens_rk4_steps)
+    q = C.area_share_weights(w.surface)
+    ctx = P.Context(0)
+    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
+    L = P.lib()
+    k = P.kernel_struct(w.kernel_kind, *w.kernel)
+    f = P.Firing(w.beta, torch.from_numpy(w.theta).cuda())
+    u0 = torch.from_numpy(w.u0.copy()).cuda()
+    out = {"workload": "ellipsoid (1,.8,.6), N=65536, B=64, Gauss Mexican hat, RK4 dt=0.05 x %d steps"
+                       % args.ens_rk4_steps}
+    finals = {}
+    for nm, form in (("bf16x3", P.FORM_W_BF16X3), ("fp16x3", P.FORM_W_FP16X3), ("otf_fp32", P.FORM_ONTHEFLY_FP32)):
+        print("bench: ensemble form %s" % nm, file=sys.stderr, flush=True)
+        W = None
+        t_build = 0.0
+        if form != P.FORM_ONTHEFLY_FP32:
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            W = prob.w_build(k, form)
+            torch.cuda.synchronize()
+            t_build = time.perf_counter() - tb
+        ws = prob.integrate_workspace(64, form)
+        u = u0.clone()
+        prob.integrate(k, f, u, w.dt, 1, form=form, W=W, ws=ws)          # warm-up
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        L.nfr_context_set_timing(ctx.handle, 1)
+        t0 = time.perf_counter()
+        prob.integrate(k, f, u, w.dt, args.ens_rk4_steps, form=form, W=W, ws=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        launches, tot = ctypes.c_int64(), ctypes.c_double()
+        P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot)))
+        L.nfr_context_set_timing(ctx.handle, 0)
+        pairs = 4.0 * args.ens_rk4_steps * float(w.n) ** 2 * 64
+        avg = tot.value / max(1, launches.value) * 1e-3
+        entry = {"value": pairs / (t1 - t0), "unit": "pair-interactions/s", "ms_per_integration": (t1 - t0) * 1e3,
+                 "w_build_ms": t_build * 1e3, "kernel_avg_ms": avg * 1e3}
+        if W is not None:
+            wbytes = 2.0 * 2 * prob.npad * prob.npad     # hi + lo, 2 bytes each, every element once
+            entry["roofline"] = {"bound": "hbm", "achieved": wbytes / avg / 1e9, "peak": HBM_PEAK / 1e9,
+                                 "unit": "GB/s", "frac": wbytes / avg / HBM_PEAK}
+        out[nm] = entry
+        finals[nm] = u.cpu().numpy()
+        del W
+        torch.cuda.empty_cache()
+    import numpy as np
+    ref = finals["otf_fp32"]
+    for nm in ("bf16x3", "fp16x3"):
+        out[nm]["max_rel_linf_vs_otf_fp32"] = float(np.max(np.max(np.abs(finals[nm] - ref), axis=1) /
+                                                            np.max(np.abs(ref), axis=1)))
+    return out
 
 
 def cpu_baseline(w, q, gpu_y_rows, rows):
@@ -209,6 +271,8 @@ def main():
         cb, err = cpu_baseline(w, q, y.cpu().numpy()[:, rows], rows)
         line["cpu_baseline"] = cb
         line["rel_err_vs_fp64_sampled_apply"] = err
+    if args.ens_rk4_steps > 0:
+        line["ensemble"] = ensemble_leg(P, torch, args)
     if args.probes:
         line["probes"] = probes(P, torch, ctx)
     print(json.dumps(line), flush=True)

@@ -81,7 +81,9 @@ typedef struct {
  *                  N x Npad) and streamed from HBM at every application.
  *   W_BF16X3 / W_FP16X3: W split as hi + lo in BF16 / FP16 and applied on the
  *                  matrix cores with FP32 accumulation (three products,
- *                  hi*hi + hi*lo + lo*hi); requires B >= 2.
+ *                  hi*hi + hi*lo + lo*hi; f(u) split the same way).  Meant
+ *                  for blocks of states (states are processed 32 or 64 at a
+ *                  time; B = 1 works but wastes the matrix cores).
  *   AUTO:          the library picks a form from the problem size and B. */
 enum nfr_form {
   NFR_FORM_AUTO = -1,
@@ -168,9 +170,13 @@ size_t nfr_w_bytes(int64_t n, int form);
 /* Builds W_ij = w(|x_i - x_j|) q_j (paper eq. NFODETilde: kernel times quadrature
  * weight) for targets i < n and sources j < npad into `w_dev` (caller-owned,
  * >= nfr_w_bytes(n, form), 256-byte aligned).  Rows are targets, row stride
- * npad elements.  For W_BF16X3 / W_FP16X3 the buffer holds the hi matrix then
- * the lo matrix, and W is scaled by 2^s with s chosen from the largest |W|
- * so that FP16 does not underflow (the scale is stored in the buffer). */
+ * npad elements.  For W_BF16X3 / W_FP16X3 the buffer holds a 256-byte header
+ * then the hi matrix then the lo matrix, each npad x npad (rows >= n zero)
+ * stored as 32 x 16 tiles in matrix-core operand order (an opaque layout:
+ * only nfr_apply / nfr_integrate read it);
+ * W is scaled by 2^s, s = 14 - ceil(log2((|A_e| + |A_i|) max|q|)) for FP16
+ * (0 for BF16), so that FP16 neither overflows nor underflows; s is stored in
+ * the header and undone when W is applied. */
 int nfr_w_build(nfr_problem* prob, const nfr_kernel* kernel, int form, void* w_dev, size_t w_bytes);
 
 /* ---------------------------------------------------------------- operator */

@@ -1,4 +1,20 @@
-// Split-precision W form on the matrix cores (BF16 / FP16 hi + lo).
+// Split-precision W form on the matrix cores (BF16 or FP16, hi + lo).
+//
+//   W_ij = w(|x_i - x_j|) q_j  (targets i, sources j; paper eq. NFODETilde),
+//   W' = 2^sW W = Whi + 2^-c Wlo,   G = f(U) = Ghi + 2^-c Glo   (c = 8 BF16, 11 FP16),
+//   Y = 2^-sW [ Whi Ghi + 2^-c (Whi Glo + Wlo Ghi) ]     (the lo*lo product is dropped).
+//
+// The two FP32 accumulators (main, correction) are kept apart and only combined
+// in the epilogue.  sW lifts W into FP16's normal range (0 for BF16).
+//
+// Buffers: W = [header 256 B | Whi | Wlo], each npad x npad (rows = targets,
+// zero beyond n) stored in matrix-core fragment order: for every 32-row block
+// rb and 16-column block kb, the 32 x 16 tile is 64 lanes x 8 halves in the
+// A-operand order of a 32x32x16 MFMA (lane m + 32 h holds row m, columns
+// 8 h .. 8 h + 7), tiles ordered (rb, kb) with kb fastest.  A wave streaming
+// its rows therefore reads one contiguous 1 KB block per load instruction.
+// G = [Ghi Bp x npad | Glo Bp x npad] state-major with states padded to Bp
+// (a multiple of 64) with zeros.
 #pragma once
 
 #include "common.h"
@@ -6,17 +22,424 @@
 
 namespace nfr {
 
-constexpr bool kMfmaAvailable = false;
+constexpr bool kMfmaAvailable = true;
+constexpr int kMfmaSplits = 8;        // one source chunk per XCD (workgroup id % 8 picks the XCD)
+constexpr int kMfmaRowsPerWG = 128;   // 4 waves x 32 rows
+constexpr int kMfmaHeader = 256;
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8_t;
+typedef __attribute__((ext_vector_type(16))) float f32x16_t;
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4_t;
+
+template <typename T> struct MfmaTraits;
+template <> struct MfmaTraits<__bf16> {
+  typedef bf16x8_t vec;
+  static constexpr int c = 8;
+  static __device__ inline f32x16_t mma(vec a, vec b, f32x16_t acc) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+};
+template <> struct MfmaTraits<_Float16> {
+  typedef f16x8_t vec;
+  static constexpr int c = 11;
+  static __device__ inline f32x16_t mma(vec a, vec b, f32x16_t acc) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+  }
+};
 
 inline bool is_mfma_form(int form) { return form == 2 || form == 3; }
-inline size_t mfma_g_bytes(int64_t npad, int B) { return size_t(npad) * B * 8; }
-inline int mfma_nsplit(int64_t, int64_t, int) { return 1; }
-inline size_t mfma_w_bytes(int64_t n, int64_t npad) { return size_t(n) * npad * 4 + 256; }
-inline void launch_mfma_prep(const ProblemView&, int, int, const double*, const Firing&, float*, double*, hipStream_t) {}
-inline void launch_mfma_apply(const ProblemView&, int, int, const void*, const float*, double*, hipStream_t) {}
-inline void launch_mfma_combine(const ProblemView&, int, int, int, double, double*, double*, double*, const double*, int,
-                                const Firing&, float*, hipStream_t) {}
-inline void launch_mfma_reduce(const ProblemView&, int, int, const double*, int, double*, hipStream_t) {}
-inline void launch_mfma_w_build(const ProblemView&, int, const KernelF64&, void*, hipStream_t) {}
+inline int64_t mfma_bp(int B) { return round_up(B, 64); }
+inline size_t mfma_g_bytes(int64_t npad, int B) { return size_t(2) * mfma_bp(B) * npad * 2; }
+inline int mfma_nsplit(int64_t, int64_t, int) { return kMfmaSplits; }
+inline size_t mfma_w_bytes(int64_t, int64_t npad) { return kMfmaHeader + size_t(2) * npad * npad * 2; }
+
+// Round-to-nearest-even conversions of a double through float.
+template <typename T> __device__ inline T to_half_type(double x) { return (T)(float)x; }
+
+// hi/lo split of a double: hi = T(x), lo = T((x - hi) * 2^c).
+template <typename T>
+__device__ inline void split_hi_lo(double x, T& hi, T& lo) {
+  hi = to_half_type<T>(x);
+  const double r = x - (double)(float)hi;
+  lo = to_half_type<T>(r * (double)(1 << MfmaTraits<T>::c));
+}
+
+// One workgroup: header[0] = sW, header[1] = 2^-sW, header[2] = 2^-(sW + c).
+// FP16: sW = 14 - ceil(log2((|A_e| + |A_i|) max_j |q_j|)) puts the largest
+// possible |W| just below 2^14.  BF16: sW = 0.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_mfma_scale(const double* __restrict__ qd, int64_t npad, double amp,
+                                                    int is_fp16, float* __restrict__ header) {
+  __shared__ double red[kWG];
+  double m = 0.0;
+  for (int64_t j = threadIdx.x; j < npad; j += kWG) m = fmax(m, fabs(qd[j]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kWG / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int sW = 0;
+    const double bound = amp * red[0];
+    if (is_fp16 && bound > 0.0) sW = 14 - (int)ceil(log2(bound));
+    header[0] = (float)sW;
+    header[1] = (float)ldexp(1.0, -sW);
+    header[2] = (float)ldexp(1.0, -(sW + MfmaTraits<T>::c));
+    header[3] = 0.0f;
+  }
+}
+
+// Whi/Wlo in fragment order; zero for rows i >= n or q_j = 0.  A thread
+// builds the 8 entries W_i,8g .. W_i,8g+7 (one lane's share of one tile) and
+// stores them as one 16-byte chunk per matrix.
+// Grid: x = rows (npad), y = blocks of kWG column groups (npad / 8 groups).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_mfma_w_build(const double* __restrict__ xyz64, const double* __restrict__ qd,
+                                                      int64_t n, int64_t npad, KernelF64 kp,
+                                                      const float* __restrict__ header, T* __restrict__ Whi,
+                                                      T* __restrict__ Wlo) {
+  const int64_t i = blockIdx.x;
+  const int64_t g = (int64_t)blockIdx.y * kWG + threadIdx.x;
+  if (i >= npad || g >= npad / 8) return;
+  const double scale = ldexp(1.0, (int)header[0]);
+  T hi[8], lo[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t j = 8 * g + e;
+    double wq = 0.0;
+    if (i < n && qd[j] != 0.0) {
+      const double dx = xyz64[3 * i] - xyz64[3 * j];
+      const double dy = xyz64[3 * i + 1] - xyz64[3 * j + 1];
+      const double dz = xyz64[3 * i + 2] - xyz64[3 * j + 2];
+      wq = kernel_w64(kp, dx * dx + dy * dy + dz * dz) * qd[j] * scale;
+    }
+    split_hi_lo<T>(wq, hi[e], lo[e]);
+  }
+  const int64_t rb = i >> 5, m = i & 31, kb = g >> 1, h = g & 1;
+  const int64_t off = ((rb * (npad / 16) + kb) * 64 + m + 32 * h) * 8;
+  u32x4_t vh, vl;
+  __builtin_memcpy(&vh, hi, 16);
+  __builtin_memcpy(&vl, lo, 16);
+  *reinterpret_cast<u32x4_t*>(Whi + off) = vh;
+  *reinterpret_cast<u32x4_t*>(Wlo + off) = vl;
+}
+
+// Ghi/Glo[b*npad + j] from f_b(u[b*n + j]) for b < Bp, j < npad (zero outside b < B, j < n);
+// optionally copies u into v.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_mfma_prep(const double* __restrict__ u, int64_t n, int64_t npad, int B,
+                                                   int64_t Bp, Firing fr, T* __restrict__ Ghi, T* __restrict__ Glo,
+                                                   double* __restrict__ v_copy) {
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (idx >= npad * Bp) return;
+  const int b = (int)(idx / npad);
+  const int64_t j = idx - (int64_t)b * npad;
+  double g = 0.0;
+  if (b < B && j < n) {
+    const double uj = u[(int64_t)b * n + j];
+    g = sigmoid(uj, fr.beta, state_theta(fr, b));
+    if (v_copy) v_copy[(int64_t)b * n + j] = uj;
+  }
+  T hi, lo;
+  split_hi_lo<T>(g, hi, lo);
+  Ghi[idx] = hi;
+  Glo[idx] = lo;
+}
+
+// Y partials on the matrix cores.
+// Workgroup w: source chunk split = w % kMfmaSplits, row block w / kMfmaSplits
+// (kMfmaRowsPerWG rows, 32 per wave); grid.y = state groups of 32*NB states.
+// Each wave runs over its source chunk kMfmaStep columns at a time.
+//
+// Operand placement: for MFMA step kb of a pipeline step, lane l = m + 32 h
+// holds the 8 consecutive columns 16 kb + 8 h .. +7 of its row (A operand: W,
+// read as one contiguous fragment) or of its state (B operand: G, from LDS).
+// Output element r of lane l sits at row 8 (r / 4) + 4 h + r % 4 of the
+// wave's 32 rows, state m of the 32-state block.
+//
+// Pipeline: W streams from HBM straight into registers through two register
+// stages (the next step in flight while the matrix cores work on the
+// current one); the G tile of the next step is fetched into registers, then
+// stored into the other half of a double-buffered LDS tile that the four
+// waves share.  32 rows per wave keep a wave under 256 registers, so two
+// workgroups fit on a compute unit.
+constexpr int kMfmaStep = 64;                    // source columns per pipeline step
+constexpr int kMfmaKb = kMfmaStep / 16;          // 32x32x16 MFMA steps per pipeline step
+constexpr int kMfmaLdsStride = kMfmaStep + 8;    // halves per LDS row (padding against bank conflicts)
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Whi, const T* __restrict__ Wlo,
+                                                       const T* __restrict__ Ghi, const T* __restrict__ Glo,
+                                                       int64_t npad, int B, int64_t kchunk,
+                                                       const float* __restrict__ header, double* __restrict__ part) {
+  typedef typename MfmaTraits<T>::vec V;
+  constexpr int NS = 32 * NB;                                  // states per group
+  constexpr int ROWCH = kMfmaStep / 8;                         // 16-byte chunks per LDS row
+  constexpr int CHUNKS = NS * 2 * ROWCH / kWG;                 // G chunks per thread per step
+  __shared__ __attribute__((aligned(16))) T sG[2][2][NS][kMfmaLdsStride];
+
+  const int64_t wg = blockIdx.x;
+  const int split = (int)(wg % kMfmaSplits);
+  const int64_t rb = wg / kMfmaSplits;
+  const int sg = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m = lane & 31;
+  const int h = lane >> 5;
+  const int64_t row0 = rb * kMfmaRowsPerWG + wave * 32;
+  const int64_t k_begin = (int64_t)split * kchunk;
+  int64_t k_end = k_begin + kchunk;
+  if (k_end > npad) k_end = npad;
+  const int nsteps = (int)((k_end - k_begin) / kMfmaStep);
+
+  const int64_t frag0 = ((row0 >> 5) * (npad / 16) + k_begin / 16) * 512 + (int64_t)lane * 8;
+  const T* wph = Whi + frag0;
+  const T* wpl = Wlo + frag0;
+
+  const T* gsrc[CHUNKS];
+  int g_hl[CHUNKS], g_st[CHUNKS], g_col[CHUNKS];
+#pragma unroll
+  for (int q = 0; q < CHUNKS; ++q) {
+    const int c = tid + kWG * q;
+    const int row = c / ROWCH;
+    g_hl[q] = row / NS;
+    g_st[q] = row % NS;
+    g_col[q] = 8 * (c % ROWCH);
+    gsrc[q] = (g_hl[q] ? Glo : Ghi) + ((int64_t)sg * NS + g_st[q]) * npad + k_begin + g_col[q];
+  }
+
+  f32x16_t accM[NB], accC[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accM[nb][r] = accC[nb][r] = 0.0f;
+
+  struct WSet {
+    V hi[kMfmaKb], lo[kMfmaKb];
+  };
+  auto load_w = [&](WSet& w, int t) {
+    if (t >= nsteps) return;
+    const int64_t base = (int64_t)t * kMfmaKb * 512;
+#pragma unroll
+    for (int kb = 0; kb < kMfmaKb; ++kb) {
+      const int64_t off = base + kb * 512;
+      w.hi[kb] = __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(wph + off)));
+      w.lo[kb] = __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(wpl + off)));
+    }
+  };
+  u32x4_t gn[CHUNKS];
+  auto load_g = [&](int t) {
+    if (t >= nsteps) return;
+#pragma unroll
+    for (int q = 0; q < CHUNKS; ++q) gn[q] = *reinterpret_cast<const u32x4_t*>(gsrc[q] + (int64_t)t * kMfmaStep);
+  };
+  auto store_g = [&](int t) {
+    if (t >= nsteps) return;
+#pragma unroll
+    for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[t & 1][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
+  };
+  auto compute = [&](const WSet& w, int t) {
+    const int buf = t & 1;
+#pragma unroll
+    for (int kb = 0; kb < kMfmaKb; ++kb) {
+      const int col = 16 * kb + 8 * h;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const V bh = *reinterpret_cast<const V*>(&sG[buf][0][nb * 32 + m][col]);
+        const V bl = *reinterpret_cast<const V*>(&sG[buf][1][nb * 32 + m][col]);
+        accM[nb] = MfmaTraits<T>::mma(w.hi[kb], bh, accM[nb]);
+        accC[nb] = MfmaTraits<T>::mma(w.hi[kb], bl, accC[nb]);
+        accC[nb] = MfmaTraits<T>::mma(w.lo[kb], bh, accC[nb]);
+      }
+    }
+  };
+  // step t: issue W and G loads for t + 1, compute t from LDS half t & 1,
+  // store G of t + 1 into the other half, barrier.
+  auto step = [&](const WSet& cur, WSet& ahead, int t) {
+    load_w(ahead, t + 1);
+    load_g(t + 1);
+    compute(cur, t);
+    store_g(t + 1);
+    __syncthreads();
+  };
+
+  WSet s0, s1;
+  load_w(s0, 0);
+  load_g(0);
+  store_g(0);
+  __syncthreads();
+  for (int t = 0; t < nsteps; t += 2) {
+    step(s0, s1, t);
+    if (t + 1 >= nsteps) break;
+    step(s1, s0, t + 1);
+  }
+
+  const double sm = header[1];
+  const double sc = header[2];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int b = sg * NS + nb * 32 + m;
+    if (b >= B) continue;
+    double* dst = part + ((int64_t)split * B + b) * npad;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t i = row0 + 8 * (r / 4) + 4 * h + (r % 4);
+      dst[i] = (double)accM[nb][r] * sm + (double)accC[nb][r] * sc;
+    }
+  }
+}
+
+// RK4 stage combination for the split forms: as k_rk4_combine, but the next
+// stage's sources are written as Ghi/Glo (no q: it sits inside W).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__ part, int nsplit, int64_t n,
+                                                      int64_t npad, int B, int stage, double dt,
+                                                      double* __restrict__ u, double* __restrict__ v,
+                                                      double* __restrict__ ksum, Firing fr, T* __restrict__ Ghi,
+                                                      T* __restrict__ Glo) {
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (idx >= n * (int64_t)B) return;
+  const int b = (int)(idx / n);
+  const int64_t i = idx - (int64_t)b * n;
+  double y = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  const double k = -v[idx] + y;
+  double ui = u[idx];
+  double vn;
+  if (stage == 1) {
+    ksum[idx] = k;
+    vn = ui + 0.5 * dt * k;
+  } else if (stage == 2) {
+    ksum[idx] += 2.0 * k;
+    vn = ui + 0.5 * dt * k;
+  } else if (stage == 3) {
+    ksum[idx] += 2.0 * k;
+    vn = ui + dt * k;
+  } else {
+    ui = ui + (dt / 6.0) * (ksum[idx] + k);
+    u[idx] = ui;
+    vn = ui;
+  }
+  v[idx] = vn;
+  T hi, lo;
+  split_hi_lo<T>(sigmoid(vn, fr.beta, state_theta(fr, b)), hi, lo);
+  Ghi[(int64_t)b * npad + i] = hi;
+  Glo[(int64_t)b * npad + i] = lo;
+}
+
+// ---------------------------------------------------------------- launchers
+
+struct MfmaBufs {
+  const float* header;
+  void* whi;
+  void* wlo;
+};
+
+inline MfmaBufs mfma_bufs(const void* W, int64_t npad) {
+  char* base = static_cast<char*>(const_cast<void*>(W));
+  MfmaBufs m;
+  m.header = reinterpret_cast<const float*>(base);
+  m.whi = base + kMfmaHeader;
+  m.wlo = base + kMfmaHeader + size_t(npad) * npad * 2;
+  return m;
+}
+
+inline void mfma_g_split(void* g, int64_t npad, int B, void** ghi, void** glo) {
+  char* base = static_cast<char*>(g);
+  *ghi = base;
+  *glo = base + size_t(mfma_bp(B)) * npad * 2;
+}
+
+template <typename T>
+inline void launch_mfma_w_build_t(const ProblemView& pv, const KernelF64& kp, void* W, hipStream_t s) {
+  MfmaBufs m = mfma_bufs(W, pv.npad);
+  const double amp = fabs(kp.Ae) + fabs(kp.Ai);
+  hipLaunchKernelGGL(k_mfma_scale<T>, dim3(1), dim3(kWG), 0, s, pv.q, pv.npad, amp,
+                     (int)(MfmaTraits<T>::c == 11), const_cast<float*>(m.header));
+  hipLaunchKernelGGL(k_mfma_w_build<T>, dim3((unsigned)pv.npad, (unsigned)ceil_div(pv.npad / 8, kWG)), dim3(kWG), 0, s,
+                     pv.xyz, pv.q, pv.n, pv.npad, kp, m.header, static_cast<T*>(m.whi), static_cast<T*>(m.wlo));
+}
+
+inline void launch_mfma_w_build(const ProblemView& pv, int form, const KernelF64& kp, void* W, hipStream_t s) {
+  if (form == 2)
+    launch_mfma_w_build_t<__bf16>(pv, kp, W, s);
+  else
+    launch_mfma_w_build_t<_Float16>(pv, kp, W, s);
+}
+
+template <typename T>
+inline void launch_mfma_prep_t(const ProblemView& pv, int B, const double* u, const Firing& fr, void* g, double* v,
+                               hipStream_t s) {
+  void *ghi, *glo;
+  mfma_g_split(g, pv.npad, B, &ghi, &glo);
+  const int64_t Bp = mfma_bp(B);
+  hipLaunchKernelGGL(k_mfma_prep<T>, dim3((unsigned)ceil_div(pv.npad * Bp, kWG)), dim3(kWG), 0, s, u, pv.n, pv.npad,
+                     B, Bp, fr, static_cast<T*>(ghi), static_cast<T*>(glo), v);
+}
+
+inline void launch_mfma_prep(const ProblemView& pv, int form, int B, const double* u, const Firing& fr, float* g,
+                             double* v, hipStream_t s) {
+  if (form == 2)
+    launch_mfma_prep_t<__bf16>(pv, B, u, fr, g, v, s);
+  else
+    launch_mfma_prep_t<_Float16>(pv, B, u, fr, g, v, s);
+}
+
+template <typename T>
+inline void launch_mfma_apply_t(const ProblemView& pv, int B, const void* W, const void* g, double* part,
+                                hipStream_t s) {
+  MfmaBufs m = mfma_bufs(W, pv.npad);
+  void *ghi, *glo;
+  mfma_g_split(const_cast<void*>(g), pv.npad, B, &ghi, &glo);
+  const int64_t kchunk = round_up(ceil_div(pv.npad, kMfmaSplits), kMfmaStep);
+  const unsigned grid_x = (unsigned)(pv.npad / kMfmaRowsPerWG * kMfmaSplits);
+  if (B <= 32) {
+    hipLaunchKernelGGL((k_mfma_apply<T, 1>), dim3(grid_x, 1), dim3(kWG), 0, s, static_cast<const T*>(m.whi),
+                       static_cast<const T*>(m.wlo), static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad,
+                       B, kchunk, m.header, part);
+  } else {
+    hipLaunchKernelGGL((k_mfma_apply<T, 2>), dim3(grid_x, (unsigned)(mfma_bp(B) / 64)), dim3(kWG), 0, s,
+                       static_cast<const T*>(m.whi), static_cast<const T*>(m.wlo), static_cast<const T*>(ghi),
+                       static_cast<const T*>(glo), pv.npad, B, kchunk, m.header, part);
+  }
+}
+
+inline void launch_mfma_apply(const ProblemView& pv, int form, int B, const void* W, const float* g, double* part,
+                              hipStream_t s) {
+  if (form == 2)
+    launch_mfma_apply_t<__bf16>(pv, B, W, g, part, s);
+  else
+    launch_mfma_apply_t<_Float16>(pv, B, W, g, part, s);
+}
+
+template <typename T>
+inline void launch_mfma_combine_t(const ProblemView& pv, int B, int stage, double dt, double* u, double* v,
+                                  double* ksum, const double* part, int nsplit, const Firing& fr, void* g,
+                                  hipStream_t s) {
+  void *ghi, *glo;
+  mfma_g_split(g, pv.npad, B, &ghi, &glo);
+  const int64_t total = pv.n * (int64_t)B;
+  hipLaunchKernelGGL(k_mfma_combine<T>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit, pv.n,
+                     pv.npad, B, stage, dt, u, v, ksum, fr, static_cast<T*>(ghi), static_cast<T*>(glo));
+}
+
+inline void launch_mfma_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, double* v,
+                                double* ksum, const double* part, int nsplit, const Firing& fr, float* g,
+                                hipStream_t s) {
+  if (form == 2)
+    launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, s);
+  else
+    launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, s);
+}
+
+inline void launch_mfma_reduce(const ProblemView& pv, int, int B, const double* part, int nsplit, double* y,
+                               hipStream_t s) {
+  const int64_t total = pv.n * (int64_t)B;
+  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit, pv.n,
+                     pv.npad, B, y);
+}
 
 }  // namespace nfr

@@ -303,7 +303,8 @@ int check_w(const nfr_problem* p, int form, const void* w_dev) {
 }
 
 int check_mfma_b(int form, int B) {
-  if (is_mfma_form(form) && B < 2) return fail(NFR_ERR_INVALID_ARG, "split-precision MFMA forms need B >= 2");
+  (void)form;
+  (void)B;
   return NFR_OK;
 }
 
