@@ -210,6 +210,31 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
                   double* ckpt_dev, int64_t ckpt_every, int use_graph,
                   void* ws_dev, size_t ws_bytes);
 
+/* ---------------------------------------------------------------- adjoint */
+
+size_t nfr_adjoint_workspace_size(const nfr_problem* prob, int64_t steps, int64_t ckpt_every);
+
+/* Gradients of a scalar loss L(u(T)) through `steps` RK4 steps of a single
+ * state (B = 1), by the discrete adjoint of the time stepper.  The forward
+ * trajectory is the one nfr_integrate computes with NFR_FORM_ONTHEFLY_FP32
+ * from the same inputs; ckpt_dev holds its checkpoints (u at steps 0,
+ * ckpt_every, 2 ckpt_every, ...: 1 + steps / ckpt_every arrays of n doubles,
+ * as nfr_integrate writes them).  Each segment is recomputed forward from its
+ * checkpoint (keeping its RK4 stage inputs), then swept in reverse: every
+ * reverse stage applies the transposed operator z_j = sum_i w_ij lambda_i
+ * (w is symmetric, so this is the same pair sum with lambda as the source
+ * weights) and accumulates the kernel-parameter derivatives in the same pass.
+ * The kernel and firing rate are those of the paper's eq. NFODETilde setting
+ * described above; the motivation is model inversion / connectivity
+ * inference (paper sections 1 and 6).
+ *   ubarT_dev: dL/du(T), n doubles (device);  ubar0_dev: receives dL/du(0).
+ *   pbar_host: receives dL/d(A_e, s_e, A_i, s_i, theta) (5 doubles, host).
+ * firing->theta_dev must be NULL (one threshold).  Synchronous: returns
+ * after the gradients are written. */
+int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, const double* ckpt_dev,
+                int64_t ckpt_every, int64_t steps, double dt, const double* ubarT_dev, double* ubar0_dev,
+                double* pbar_host, void* ws_dev, size_t ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

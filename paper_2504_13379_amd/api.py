@@ -157,5 +157,54 @@ class Problem:
         self._last_ws = ws
         return ck
 
+    def adjoint(self, kernel: L.NfrKernel, firing: Firing, ckpt: torch.Tensor, ckpt_every: int, steps: int,
+                dt: float, ubarT: torch.Tensor):
+        """Discrete-adjoint gradients of L(u(T)) for a single state: (dL/du0 (N,), dL/dp (5,) float64)."""
+        if ubarT.shape != (self.n,) and ubarT.shape != (1, self.n):
+            raise ValueError("ubarT must hold N values")
+        ubarT = ubarT.reshape(self.n).to(self.ctx.device, torch.float64).contiguous()
+        ckpt = ckpt.to(self.ctx.device, torch.float64).contiguous()
+        need = 1 + steps // ckpt_every
+        if ckpt.numel() < need * self.n:
+            raise ValueError("ckpt holds %d states, %d needed" % (ckpt.numel() // self.n, need))
+        ws_bytes = L.lib().nfr_adjoint_workspace_size(self.handle, int(steps), int(ckpt_every))
+        ws = _dev_buffer(ws_bytes, self.ctx.device)
+        ubar0 = torch.empty(self.n, dtype=torch.float64, device=self.ctx.device)
+        pbar = (c_double * 5)()
+        fs = firing.struct(self.ctx.device)
+        L.check(L.lib().nfr_adjoint(self.handle, byref(kernel), byref(fs), ckpt.data_ptr(), int(ckpt_every),
+                                    int(steps), float(dt), ubarT.data_ptr(), ubar0.data_ptr(), pbar,
+                                    ws.data_ptr(), ws_bytes))
+        return ubar0, torch.tensor(list(pbar), dtype=torch.float64)
+
     def integrate_workspace(self, B: int, form: int) -> torch.Tensor:
         return _dev_buffer(L.lib().nfr_integrate_workspace_size(self.handle, B, form), self.ctx.device)
+
+
+class NeuralFieldRK4(torch.autograd.Function):
+    """u(T) = RK4^steps(u0; A_e, s_e, A_i, s_i, theta) on a packed problem, single state.
+
+    forward: nfr_integrate (on-the-fly FP32 pair sums, FP64 state) keeping
+    checkpoints every `ckpt_every` steps; backward: nfr_adjoint.  `params` is
+    a CPU float64 tensor (A_e, s_e, A_i, s_i, theta); its gradient is returned
+    on the CPU.
+    """
+
+    @staticmethod
+    def forward(ctx, u0, params, problem, kind, beta, dt, steps, ckpt_every):
+        p = [float(v) for v in params.detach().cpu().tolist()]
+        k = kernel_struct(kind, *p[:4])
+        f = Firing(beta, p[4])
+        u = u0.detach().reshape(1, problem.n).to(torch.float64).clone().contiguous()
+        ck = problem.integrate(k, f, u, dt, steps, form=L.FORM_ONTHEFLY_FP32, ckpt_every=ckpt_every)
+        ctx.problem, ctx.k, ctx.f = problem, k, f
+        ctx.dt, ctx.steps, ctx.every = dt, steps, ckpt_every
+        ctx.save_for_backward(ck)
+        ctx.u0_shape = u0.shape
+        return u.reshape(u0.shape)
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        (ck,) = ctx.saved_tensors
+        gu0, gp = ctx.problem.adjoint(ctx.k, ctx.f, ck, ctx.every, ctx.steps, ctx.dt, grad_u.reshape(-1))
+        return gu0.reshape(ctx.u0_shape), gp, None, None, None, None, None, None

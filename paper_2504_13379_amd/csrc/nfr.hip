@@ -15,6 +15,7 @@
 #include "kernels_core.h"
 #include "kernels_mfma.h"
 #include "kernels_probe.h"
+#include "kernels_adjoint.h"
 
 using namespace nfr;
 
@@ -635,6 +636,146 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
     if (e != hipSuccess && result == NFR_OK) result = fail(NFR_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
   }
   return result;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- adjoint
+
+namespace {
+
+struct AdjWorkspace {
+  Workspace fwd;
+  double* store = nullptr;   // C x 4 x n stage inputs of one segment
+  double* useg = nullptr;
+  double* lam = nullptr;
+  float* lam32 = nullptr;
+  double* ubar = nullptr;
+  double* unbar = nullptr;
+  double* apart = nullptr;   // 4 x nsplit x npad
+  double* pblk = nullptr;    // nblocks x 8
+  double* pbar = nullptr;    // 8
+  size_t bytes = 0;
+};
+
+AdjWorkspace carve_adjoint(void* base, const ProblemView& pv, int64_t ckpt_every) {
+  AdjWorkspace a;
+  a.fwd = carve(base, pv, 1, NFR_FORM_ONTHEFLY_FP32, true);
+  char* p = static_cast<char*>(base);
+  size_t off = a.fwd.bytes;
+  auto take = [&](size_t bytes) {
+    char* r = p ? p + off : nullptr;
+    off += align256(bytes);
+    return r;
+  };
+  const int nsplit = plan_otf(pv.npad, 1).nsplit;
+  const int64_t nblocks = ceil_div(pv.n, kWG);
+  a.store = reinterpret_cast<double*>(take(size_t(ckpt_every) * 4 * pv.n * sizeof(double)));
+  a.useg = reinterpret_cast<double*>(take(size_t(pv.n) * sizeof(double)));
+  a.lam = reinterpret_cast<double*>(take(size_t(pv.n) * sizeof(double)));
+  a.lam32 = reinterpret_cast<float*>(take(size_t(pv.npad) * sizeof(float)));
+  a.ubar = reinterpret_cast<double*>(take(size_t(pv.n) * sizeof(double)));
+  a.unbar = reinterpret_cast<double*>(take(size_t(pv.n) * sizeof(double)));
+  a.apart = reinterpret_cast<double*>(take(size_t(4) * nsplit * pv.npad * sizeof(double)));
+  a.pblk = reinterpret_cast<double*>(take(size_t(nblocks) * 8 * sizeof(double)));
+  a.pbar = reinterpret_cast<double*>(take(8 * sizeof(double)));
+  a.bytes = off;
+  return a;
+}
+
+AdjCoef adj_coef(const nfr_kernel& k) {
+  AdjCoef c;
+  c.Ae = k.A_e;
+  c.Ai = k.A_i;
+  if (k.kind == NFR_KERNEL_GAUSS_MH) {
+    c.kse = 2.0 / (k.s_e * kLog2e);
+    c.ksi = 2.0 * k.s_e * k.s_e / (k.s_i * k.s_i * k.s_i * kLog2e);
+  } else {
+    c.kse = 1.0 / (k.s_e * kLog2e);
+    c.ksi = k.s_e / (k.s_i * k.s_i * kLog2e);
+  }
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t nfr_adjoint_workspace_size(const nfr_problem* prob, int64_t steps, int64_t ckpt_every) {
+  if (!prob || steps < 0 || ckpt_every < 1) return 0;
+  return carve_adjoint(nullptr, prob->view, ckpt_every).bytes;
+}
+
+int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, const double* ckpt_dev,
+                int64_t ckpt_every, int64_t steps, double dt, const double* ubarT_dev, double* ubar0_dev,
+                double* pbar_host, void* ws_dev, size_t ws_bytes) {
+  int st;
+  if ((st = check_problem(prob)) || (st = check_kernel(kernel)) || (st = check_firing(firing))) return st;
+  if (firing->theta_dev) return fail(NFR_ERR_INVALID_ARG, "the adjoint supports one shared threshold (theta_dev must be NULL)");
+  if (!ckpt_dev || !ubarT_dev || !ubar0_dev || !pbar_host) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
+  if (ckpt_every < 1) return fail(NFR_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+  if (steps < 0) return fail(NFR_ERR_INVALID_ARG, "steps must be >= 0");
+  if (!is_finite_d(dt)) return fail(NFR_ERR_NONFINITE, "dt must be finite");
+  if (!(dt > 0.0)) return fail(NFR_ERR_INVALID_ARG, "dt must be > 0");
+  const ProblemView& pv = prob->view;
+  const AdjWorkspace a = carve_adjoint(ws_dev, pv, ckpt_every);
+  if (!ws_dev || ws_bytes < a.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, a.bytes);
+  NFR_HIP(hipSetDevice(prob->ctx->device));
+  nfr_context* ctx = prob->ctx;
+  hipStream_t s = ctx->stream;
+  const Firing fr = firing_of(*firing);
+  const PairParams pp = pair_params(*kernel);
+  const AdjCoef co = adj_coef(*kernel);
+  const OtfPlan pl = plan_otf(pv.npad, 1);
+  const int64_t n = pv.n;
+  const int64_t nblocks = ceil_div(n, kWG);
+  const size_t vbytes = size_t(n) * sizeof(double);
+  const int form = NFR_FORM_ONTHEFLY_FP32;
+
+  hipLaunchKernelGGL(k_adj_init, dim3((unsigned)ceil_div(pv.npad, kWG)), dim3(kWG), 0, s, ubarT_dev, n, pv.npad, dt,
+                     a.ubar, a.unbar, a.lam, a.lam32);
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)ceil_div(nblocks * 8, kWG)), dim3(kWG), 0, s, a.pblk, nblocks * 8);
+  NFR_HIP_LAUNCH();
+
+  const int64_t nseg = ceil_div(steps, ckpt_every);
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t s0 = seg * ckpt_every;
+    const int64_t len = (steps - s0) < ckpt_every ? (steps - s0) : ckpt_every;
+    // recompute the segment forward from its checkpoint, keeping every stage input
+    NFR_HIP(hipMemcpyAsync(a.useg, ckpt_dev + seg * n, vbytes, hipMemcpyDeviceToDevice, s));
+    if ((st = launch_prep(pv, form, 1, a.useg, fr, a.fwd, a.fwd.v, s))) return st;
+    for (int64_t l = 0; l < len; ++l) {
+      for (int stage = 1; stage <= 4; ++stage) {
+        NFR_HIP(hipMemcpyAsync(a.store + (l * 4 + stage - 1) * n, a.fwd.v, vbytes, hipMemcpyDeviceToDevice, s));
+        if ((st = launch_pairs(ctx, pv, *kernel, form, 1, nullptr, a.fwd))) return st;
+        if ((st = launch_combine(pv, form, 1, stage, dt, a.useg, a.fwd, fr, s))) return st;
+      }
+    }
+    // reverse sweep over the segment
+    for (int64_t l = len - 1; l >= 0; --l) {
+      for (int stage = 4; stage >= 1; --stage) {
+        if ((st = timing_mark(ctx))) return st;
+        if (kernel->kind == NFR_KERNEL_GAUSS_MH)
+          hipLaunchKernelGGL(k_otf_adjoint<0>, dim3((unsigned)pl.tiles, (unsigned)pl.nsplit), dim3(kWG), 0, s, pv.src,
+                             a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart);
+        else
+          hipLaunchKernelGGL(k_otf_adjoint<1>, dim3((unsigned)pl.tiles, (unsigned)pl.nsplit), dim3(kWG), 0, s, pv.src,
+                             a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart);
+        NFR_HIP_LAUNCH();
+        if ((st = timing_mark(ctx))) return st;
+        hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)nblocks), dim3(kWG), 0, s, a.apart, pl.nsplit, n, pv.npad,
+                           stage, dt, co, pv.q, fr, a.store + (l * 4 + stage - 1) * n, a.ubar, a.unbar, a.lam,
+                           a.lam32, a.pblk);
+        NFR_HIP_LAUNCH();
+      }
+    }
+  }
+  NFR_HIP(hipMemcpyAsync(ubar0_dev, a.ubar, vbytes, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_adj_finalize, dim3(1), dim3(64), 0, s, a.pblk, nblocks, a.pbar);
+  NFR_HIP_LAUNCH();
+  NFR_HIP(hipMemcpyAsync(pbar_host, a.pbar, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+  NFR_HIP(hipStreamSynchronize(s));
+  return NFR_OK;
 }
 
 }  // extern "C"
