@@ -95,6 +95,7 @@ enum nfr_form {
 
 typedef struct nfr_context nfr_context;
 typedef struct nfr_problem nfr_problem;
+typedef struct nfr_batch nfr_batch;
 
 /* ---------------------------------------------------------------- status */
 
@@ -209,6 +210,35 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
                   double* u_dev, double dt, int64_t steps, int form, const void* w_dev,
                   double* ckpt_dev, int64_t ckpt_every, int use_graph,
                   void* ws_dev, size_t ws_bytes);
+
+/* ---------------------------------------------------------------- uneven batch */
+
+/* Groups P problems of one context (any mix of node counts, kernels, firing
+ * rates and state counts B[p]) that are time-stepped together: each RK4 stage
+ * is one persistent on-the-fly pair-sum launch over a cost-sorted list of work
+ * items (problem, target tile, source chunk, state block) plus one combine
+ * launch for all problems.  Arrays are copied; the problems must outlive the
+ * batch.  Host memory only. */
+int nfr_batch_create(nfr_context* ctx, int P, nfr_problem* const* probs, const nfr_kernel* kernels,
+                     const nfr_firing* firings, const int* B, nfr_batch** out);
+int nfr_batch_destroy(nfr_batch* batch);
+/* Workspace bytes for nfr_batch_integrate / nfr_batch_tune (any configuration). */
+size_t nfr_batch_workspace_size(const nfr_batch* batch);
+/* Tile configuration: source-chunk length (multiple of 256, >= 1024) and
+ * persistent workgroups per compute unit. */
+int nfr_batch_set_config(nfr_batch* batch, int64_t chunk, int wgs_per_cu);
+int nfr_batch_get_config(const nfr_batch* batch, int64_t* chunk, int* wgs_per_cu);
+/* Autotuner: times one pair-sum launch of every candidate configuration on the
+ * given states (which are read, not modified) and keeps the fastest; its time
+ * in ms goes to *best_ms (may be NULL).  Synchronous. */
+int nfr_batch_tune(nfr_batch* batch, double* const* u_devs, void* ws_dev, size_t ws_bytes, double* best_ms);
+/* RK4 (as nfr_integrate, on-the-fly FP32 pair sums, FP64 states) for every
+ * problem of the batch: u_devs[p] points to problem p's B[p] x n_p state
+ * (device), advanced in place by `steps` steps of size dt.  use_graph != 0
+ * replays each step from a captured HIP graph (needs a non-default stream;
+ * then the call returns after the work has run). */
+int nfr_batch_integrate(nfr_batch* batch, double* const* u_devs, double dt, int64_t steps, int use_graph,
+                        void* ws_dev, size_t ws_bytes);
 
 /* ---------------------------------------------------------------- adjoint */
 

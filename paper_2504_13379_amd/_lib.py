@@ -77,12 +77,14 @@ def _declare(lib):
         "nfr_adjoint_workspace_size": (c_size_t, [P, c_int64, c_int64]),
         "nfr_adjoint": (c_int, [P, POINTER(NfrKernel), POINTER(NfrFiring), P, c_int64, c_int64, c_double, P, P,
                                 POINTER(c_double), P, c_size_t]),
-        "nfr_batch_workspace_size": (c_size_t, [c_int, POINTER(P), POINTER(c_int)]),
+        "nfr_batch_workspace_size": (c_size_t, [P]),
         "nfr_batch_create": (c_int, [P, c_int, POINTER(P), POINTER(NfrKernel), POINTER(NfrFiring), POINTER(c_int),
                                      POINTER(P)]),
         "nfr_batch_destroy": (c_int, [P]),
+        "nfr_batch_set_config": (c_int, [P, c_int64, c_int]),
+        "nfr_batch_get_config": (c_int, [P, POINTER(c_int64), POINTER(c_int)]),
+        "nfr_batch_tune": (c_int, [P, POINTER(P), P, c_size_t, POINTER(c_double)]),
         "nfr_batch_integrate": (c_int, [P, POINTER(P), c_double, c_int64, c_int, P, c_size_t]),
-        "nfr_tune": (c_int, [P, c_char_p, c_int64, c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

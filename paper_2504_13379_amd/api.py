@@ -181,6 +181,69 @@ class Problem:
         return _dev_buffer(L.lib().nfr_integrate_workspace_size(self.handle, B, form), self.ctx.device)
 
 
+class Batch:
+    """Problems of one context time-stepped together (nfr_batch_*): one persistent
+    pair-sum launch and one combine launch per RK4 stage for all of them."""
+
+    def __init__(self, ctx: Context, problems, kernels, firings, Bs):
+        P = len(problems)
+        if not (P == len(kernels) == len(firings) == len(Bs)) or P == 0:
+            raise ValueError("problems, kernels, firings and Bs must have the same non-zero length")
+        self.ctx, self.problems, self.Bs = ctx, list(problems), [int(b) for b in Bs]
+        self._firings = list(firings)
+        ph = (c_void_p * P)(*[p.handle.value for p in problems])
+        ks = (L.NfrKernel * P)(*kernels)
+        fs = (L.NfrFiring * P)(*[f.struct(ctx.device) for f in firings])
+        bs = (c_int * P)(*self.Bs)
+        h = c_void_p()
+        L.check(L.lib().nfr_batch_create(ctx.handle, P, ph, ks, fs, bs, byref(h)))
+        self.handle = h
+
+    def _states(self, states):
+        if len(states) != len(self.problems):
+            raise ValueError("one state tensor per problem")
+        for p, u, B in zip(self.problems, states, self.Bs):
+            if p._check_state(u) != B:
+                raise ValueError("state of problem with B=%d has %d rows" % (B, u.shape[0]))
+        return (c_void_p * len(states))(*[u.data_ptr() for u in states])
+
+    def workspace(self) -> torch.Tensor:
+        return _dev_buffer(L.lib().nfr_batch_workspace_size(self.handle), self.ctx.device)
+
+    @property
+    def config(self):
+        c, w = ctypes.c_int64(), c_int()
+        L.check(L.lib().nfr_batch_get_config(self.handle, byref(c), byref(w)))
+        return int(c.value), int(w.value)
+
+    @config.setter
+    def config(self, cw):
+        L.check(L.lib().nfr_batch_set_config(self.handle, int(cw[0]), int(cw[1])))
+
+    def tune(self, states, ws: torch.Tensor | None = None) -> float:
+        ws = self.workspace() if ws is None else ws
+        best = c_double()
+        L.check(L.lib().nfr_batch_tune(self.handle, self._states(states), ws.data_ptr(), ws.numel(), byref(best)))
+        return best.value
+
+    def integrate(self, states, dt: float, steps: int, use_graph: bool = False, ws: torch.Tensor | None = None):
+        ptrs = self._states(states)
+        ws = self.workspace() if ws is None else ws
+        L.check(L.lib().nfr_batch_integrate(self.handle, ptrs, float(dt), int(steps), int(bool(use_graph)),
+                                            ws.data_ptr(), ws.numel()))
+
+    def close(self):
+        if self.handle:
+            L.lib().nfr_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class NeuralFieldRK4(torch.autograd.Function):
     """u(T) = RK4^steps(u0; A_e, s_e, A_i, s_i, theta) on a packed problem, single state.
 

@@ -67,15 +67,11 @@ __global__ __launch_bounds__(kWG) void k_source_prep(const double* __restrict__ 
 // of kWG sources in FP32 (e and i parts separately), then folds the tile sum
 // into FP64 accumulators: A_e * sum_e - A_i * sum_i.
 template <int KIND, int TPT, int BS>
-__global__ __launch_bounds__(kWG) void k_otf_pair_sum(const float4* __restrict__ src, const float* __restrict__ g,
-                                                      int64_t npad, int B, int64_t chunk, PairParams pp,
-                                                      double* __restrict__ part) {
-  __shared__ float4 s_src[kWG];
-  __shared__ float s_g[BS][kWG];
+__device__ inline void otf_tile(const float4* __restrict__ src, const float* __restrict__ g, int64_t npad, int B,
+                                int64_t chunk, const PairParams& pp, double* __restrict__ part, int64_t tile,
+                                int split, int b0, float4* s_src, float (*s_g)[kWG]) {
   const int tid = threadIdx.x;
-  const int64_t tbase = (int64_t)blockIdx.x * (kWG * TPT);
-  const int split = blockIdx.y;
-  const int b0 = blockIdx.z * BS;
+  const int64_t tbase = tile * (kWG * TPT);
 
   float xi[TPT], yi[TPT], zi[TPT];
 #pragma unroll
@@ -150,6 +146,15 @@ __global__ __launch_bounds__(kWG) void k_otf_pair_sum(const float4* __restrict__
     for (int b = 0; b < BS; ++b)
       if (b0 + b < B) part[((int64_t)split * B + b0 + b) * npad + t] = acc[k][b];
   }
+}
+
+template <int KIND, int TPT, int BS>
+__global__ __launch_bounds__(kWG) void k_otf_pair_sum(const float4* __restrict__ src, const float* __restrict__ g,
+                                                      int64_t npad, int B, int64_t chunk, PairParams pp,
+                                                      double* __restrict__ part) {
+  __shared__ float4 s_src[kWG];
+  __shared__ float s_g[BS][kWG];
+  otf_tile<KIND, TPT, BS>(src, g, npad, B, chunk, pp, part, blockIdx.x, blockIdx.y, blockIdx.z * BS, s_src, s_g);
 }
 
 // ------------------------------------------------------------------ reductions

@@ -16,6 +16,9 @@
 #include "kernels_mfma.h"
 #include "kernels_probe.h"
 #include "kernels_adjoint.h"
+#include "kernels_batch.h"
+
+#include <algorithm>
 
 using namespace nfr;
 
@@ -776,6 +779,326 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
   NFR_HIP(hipMemcpyAsync(pbar_host, a.pbar, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
   NFR_HIP(hipStreamSynchronize(s));
   return NFR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- uneven batch
+
+struct nfr_batch {
+  nfr_context* ctx = nullptr;
+  std::vector<nfr_problem*> probs;
+  std::vector<nfr_kernel> kernels;
+  std::vector<nfr_firing> firings;
+  std::vector<int> B;
+  int64_t chunk = 2048;
+  int wgs_per_cu = 4;
+  std::vector<BatchProblemDev> table;
+  std::vector<BatchItem> items;
+};
+
+namespace {
+
+constexpr int64_t kBatchChunks[] = {1024, 2048, 4096, 8192};
+constexpr int kBatchWgs[] = {2, 4, 8};
+constexpr int64_t kBatchMinChunk = 1024;
+
+struct BatchLayout {
+  size_t table_off = 0, items_off = 0, bytes = 0;
+  std::vector<size_t> g_off, part_off, v_off, ksum_off;
+  size_t max_items = 0;
+};
+
+int64_t batch_items_for(const nfr_problem* p, int B, int64_t chunk) {
+  const int64_t npad = p->view.npad;
+  const int bs = B == 1 ? 1 : 4;
+  return ceil_div(npad, (int64_t)kWG * kBatchTPT) * ceil_div(npad, chunk) * ceil_div(B, bs);
+}
+
+BatchLayout batch_layout(const nfr_batch* b) {
+  BatchLayout L;
+  const int P = (int)b->probs.size();
+  size_t off = 0;
+  L.table_off = off;
+  off += align256(sizeof(BatchProblemDev) * P);
+  for (int p = 0; p < P; ++p) L.max_items += batch_items_for(b->probs[p], b->B[p], kBatchMinChunk);
+  L.items_off = off;
+  off += align256(sizeof(BatchItem) * L.max_items);
+  for (int p = 0; p < P; ++p) {
+    const ProblemView& pv = b->probs[p]->view;
+    const int Bp = b->B[p];
+    L.g_off.push_back(off);
+    off += align256(size_t(pv.npad) * Bp * sizeof(float));
+    L.part_off.push_back(off);
+    off += align256(size_t(ceil_div(pv.npad, kBatchMinChunk)) * Bp * pv.npad * sizeof(double));
+    L.v_off.push_back(off);
+    off += align256(size_t(pv.n) * Bp * sizeof(double));
+    L.ksum_off.push_back(off);
+    off += align256(size_t(pv.n) * Bp * sizeof(double));
+  }
+  L.bytes = off;
+  return L;
+}
+
+// Fills the host table and the sorted item list for the batch's current chunk.
+void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_devs) {
+  const int P = (int)b->probs.size();
+  b->table.assign(P, BatchProblemDev{});
+  b->items.clear();
+  std::vector<double> cost;
+  int64_t eoff = 0, goff = 0;
+  for (int p = 0; p < P; ++p) {
+    const ProblemView& pv = b->probs[p]->view;
+    const int Bp = b->B[p];
+    BatchProblemDev& d = b->table[p];
+    d.src = pv.src;
+    d.q = pv.q;
+    d.n = pv.n;
+    d.npad = pv.npad;
+    d.B = Bp;
+    d.bs = Bp == 1 ? 1 : 4;
+    d.kind = b->kernels[p].kind;
+    d.chunk = b->chunk;
+    d.nsplit = (int)ceil_div(pv.npad, b->chunk);
+    d.pp = pair_params(b->kernels[p]);
+    d.fr = firing_of(b->firings[p]);
+    d.g = reinterpret_cast<float*>(ws + L.g_off[p]);
+    d.part = reinterpret_cast<double*>(ws + L.part_off[p]);
+    d.u = u_devs ? u_devs[p] : nullptr;
+    d.v = reinterpret_cast<double*>(ws + L.v_off[p]);
+    d.ksum = reinterpret_cast<double*>(ws + L.ksum_off[p]);
+    d.elem_off = eoff;
+    d.gel_off = goff;
+    eoff += pv.n * Bp;
+    goff += pv.npad * Bp;
+    const int64_t tiles = ceil_div(pv.npad, (int64_t)kWG * kBatchTPT);
+    const int sbs = (int)ceil_div(Bp, d.bs);
+    for (int64_t t = 0; t < tiles; ++t)
+      for (int sp = 0; sp < d.nsplit; ++sp)
+        for (int sb = 0; sb < sbs; ++sb) {
+          const double tg = (double)std::min<int64_t>(kWG * kBatchTPT, pv.npad - t * kWG * kBatchTPT);
+          const double sc = (double)std::min<int64_t>(b->chunk, pv.npad - sp * b->chunk);
+          const double st = (double)std::min(d.bs, Bp - sb * d.bs);
+          const double per_pair = (d.kind == NFR_KERNEL_EXP_MH ? 1.3 : 1.0) + 0.25 * (st - 1.0);
+          b->items.push_back(BatchItem{p, (int)t, sp, sb});
+          cost.push_back(tg * sc * per_pair);
+        }
+  }
+  std::vector<size_t> order(b->items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+  std::vector<BatchItem> sorted(order.size());
+  for (size_t i = 0; i < order.size(); ++i) sorted[i] = b->items[order[i]];
+  b->items.swap(sorted);
+}
+
+int64_t batch_total(const nfr_batch* b, bool padded) {
+  int64_t t = 0;
+  for (size_t p = 0; p < b->probs.size(); ++p)
+    t += (padded ? b->probs[p]->view.npad : b->probs[p]->view.n) * b->B[p];
+  return t;
+}
+
+int batch_upload(nfr_batch* b, const BatchLayout& L, char* ws, hipStream_t s) {
+  NFR_HIP(hipMemcpyAsync(ws + L.table_off, b->table.data(), sizeof(BatchProblemDev) * b->table.size(),
+                         hipMemcpyHostToDevice, s));
+  NFR_HIP(hipMemcpyAsync(ws + L.items_off, b->items.data(), sizeof(BatchItem) * b->items.size(),
+                         hipMemcpyHostToDevice, s));
+  // the host vectors are reused by the next call: finish the copies first
+  NFR_HIP(hipStreamSynchronize(s));
+  return NFR_OK;
+}
+
+void batch_launch_pairs(const nfr_batch* b, const BatchLayout& L, char* ws, hipStream_t s) {
+  const int nitems = (int)b->items.size();
+  int grid = b->ctx->cu_count * b->wgs_per_cu;
+  if (grid > nitems) grid = nitems;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_batch_pairs, dim3((unsigned)grid), dim3(kWG), 0, s,
+                     reinterpret_cast<const BatchProblemDev*>(ws + L.table_off),
+                     reinterpret_cast<const BatchItem*>(ws + L.items_off), nitems);
+}
+
+int check_batch_states(const nfr_batch* b, double* const* u_devs) {
+  if (!u_devs) return fail(NFR_ERR_INVALID_ARG, "u_devs is NULL");
+  for (size_t p = 0; p < b->probs.size(); ++p)
+    if (!u_devs[p]) return fail(NFR_ERR_INVALID_ARG, "state pointer %zu is NULL", p);
+  return NFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nfr_batch_create(nfr_context* ctx, int P, nfr_problem* const* probs, const nfr_kernel* kernels,
+                     const nfr_firing* firings, const int* B, nfr_batch** out) {
+  if (!out) return fail(NFR_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx || !probs || !kernels || !firings || !B) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
+  if (P < 1 || P > 65536) return fail(NFR_ERR_INVALID_ARG, "P = %d outside [1, 65536]", P);
+  int st;
+  for (int p = 0; p < P; ++p) {
+    if ((st = check_problem(probs[p]))) return st;
+    if (probs[p]->ctx != ctx) return fail(NFR_ERR_INVALID_ARG, "problem %d belongs to another context", p);
+    if ((st = check_kernel(&kernels[p])) || (st = check_firing(&firings[p]))) return st;
+    if (B[p] < 1 || B[p] > kMaxB) return fail(NFR_ERR_INVALID_ARG, "B[%d] = %d outside [1, %d]", p, B[p], kMaxB);
+  }
+  nfr_batch* b = new (std::nothrow) nfr_batch;
+  if (!b) return fail(NFR_ERR_INTERNAL, "out of host memory");
+  b->ctx = ctx;
+  b->probs.assign(probs, probs + P);
+  b->kernels.assign(kernels, kernels + P);
+  b->firings.assign(firings, firings + P);
+  b->B.assign(B, B + P);
+  *out = b;
+  return NFR_OK;
+}
+
+int nfr_batch_destroy(nfr_batch* b) {
+  delete b;
+  return NFR_OK;
+}
+
+size_t nfr_batch_workspace_size(const nfr_batch* b) { return b ? batch_layout(b).bytes : 0; }
+
+int nfr_batch_set_config(nfr_batch* b, int64_t chunk, int wgs_per_cu) {
+  if (!b) return fail(NFR_ERR_INVALID_ARG, "batch is NULL");
+  if (chunk < kBatchMinChunk || chunk % kWG || chunk > (int64_t(1) << 24))
+    return fail(NFR_ERR_INVALID_ARG, "chunk must be a multiple of %d, >= %lld", kWG, (long long)kBatchMinChunk);
+  if (wgs_per_cu < 1 || wgs_per_cu > 64) return fail(NFR_ERR_INVALID_ARG, "wgs_per_cu outside [1, 64]");
+  b->chunk = chunk;
+  b->wgs_per_cu = wgs_per_cu;
+  return NFR_OK;
+}
+
+int nfr_batch_get_config(const nfr_batch* b, int64_t* chunk, int* wgs_per_cu) {
+  if (!b || !chunk || !wgs_per_cu) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
+  *chunk = b->chunk;
+  *wgs_per_cu = b->wgs_per_cu;
+  return NFR_OK;
+}
+
+int nfr_batch_tune(nfr_batch* b, double* const* u_devs, void* ws_dev, size_t ws_bytes, double* best_ms) {
+  if (!b) return fail(NFR_ERR_INVALID_ARG, "batch is NULL");
+  int st;
+  if ((st = check_batch_states(b, u_devs))) return st;
+  const BatchLayout L = batch_layout(b);
+  if (!ws_dev || ws_bytes < L.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.bytes);
+  NFR_HIP(hipSetDevice(b->ctx->device));
+  hipStream_t s = b->ctx->stream;
+  char* ws = static_cast<char*>(ws_dev);
+  hipEvent_t e0, e1;
+  NFR_HIP(hipEventCreate(&e0));
+  NFR_HIP(hipEventCreate(&e1));
+  double best = 1e300;
+  int64_t best_chunk = b->chunk;
+  int best_wgs = b->wgs_per_cu;
+  for (int64_t chunk : kBatchChunks) {
+    for (int wgs : kBatchWgs) {
+      b->chunk = chunk;
+      b->wgs_per_cu = wgs;
+      batch_build(b, L, ws, u_devs);
+      if ((st = batch_upload(b, L, ws, s))) return st;
+      const int64_t gtot = batch_total(b, true);
+      hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)ceil_div(gtot, kWG)), dim3(kWG), 0, s,
+                         reinterpret_cast<const BatchProblemDev*>(ws + L.table_off), (int)b->probs.size(), gtot);
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {
+        NFR_HIP(hipEventRecord(e0, s));
+        batch_launch_pairs(b, L, ws, s);
+        NFR_HIP(hipEventRecord(e1, s));
+        NFR_HIP(hipEventSynchronize(e1));
+        NFR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      }
+      NFR_HIP_LAUNCH();
+      if (ms < best) {
+        best = ms;
+        best_chunk = chunk;
+        best_wgs = wgs;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->chunk = best_chunk;
+  b->wgs_per_cu = best_wgs;
+  if (best_ms) *best_ms = best;
+  return NFR_OK;
+}
+
+int nfr_batch_integrate(nfr_batch* b, double* const* u_devs, double dt, int64_t steps, int use_graph, void* ws_dev,
+                        size_t ws_bytes) {
+  if (!b) return fail(NFR_ERR_INVALID_ARG, "batch is NULL");
+  int st;
+  if ((st = check_batch_states(b, u_devs))) return st;
+  if (!is_finite_d(dt)) return fail(NFR_ERR_NONFINITE, "dt must be finite");
+  if (!(dt > 0.0)) return fail(NFR_ERR_INVALID_ARG, "dt must be > 0");
+  if (steps < 0) return fail(NFR_ERR_INVALID_ARG, "steps must be >= 0");
+  const BatchLayout L = batch_layout(b);
+  if (!ws_dev || ws_bytes < L.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.bytes);
+  if (use_graph && b->ctx->stream == nullptr) return fail(NFR_ERR_INVALID_ARG, "graph replay needs a non-default stream");
+  NFR_HIP(hipSetDevice(b->ctx->device));
+  hipStream_t s = b->ctx->stream;
+  char* ws = static_cast<char*>(ws_dev);
+  batch_build(b, L, ws, u_devs);
+  if ((st = batch_upload(b, L, ws, s))) return st;
+  if (steps == 0) return NFR_OK;
+  const int P = (int)b->probs.size();
+  const auto* table = reinterpret_cast<const BatchProblemDev*>(ws + L.table_off);
+  const int64_t gtot = batch_total(b, true);
+  const int64_t etot = batch_total(b, false);
+  hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)ceil_div(gtot, kWG)), dim3(kWG), 0, s, table, P, gtot);
+  NFR_HIP_LAUNCH();
+
+  auto one_step = [&]() -> int {
+    for (int stage = 1; stage <= 4; ++stage) {
+      int r;
+      if ((r = timing_mark(b->ctx))) return r;
+      batch_launch_pairs(b, L, ws, s);
+      NFR_HIP_LAUNCH();
+      if ((r = timing_mark(b->ctx))) return r;
+      hipLaunchKernelGGL(k_batch_combine, dim3((unsigned)ceil_div(etot, kWG)), dim3(kWG), 0, s, table, P, etot, stage,
+                         dt);
+      NFR_HIP_LAUNCH();
+    }
+    return NFR_OK;
+  };
+
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    NFR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    b->ctx->capturing = true;
+    const int r = one_step();
+    b->ctx->capturing = false;
+    const hipError_t e_end = hipStreamEndCapture(s, &graph);
+    if (r) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r;
+    }
+    if (e_end != hipSuccess) return fail(NFR_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e_end));
+    const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e_inst != hipSuccess) return fail(NFR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e_inst));
+  }
+  int result = NFR_OK;
+  for (int64_t step = 0; step < steps; ++step) {
+    if (exec) {
+      const hipError_t e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) {
+        result = fail(NFR_ERR_HIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
+        break;
+      }
+    } else if ((result = one_step())) {
+      break;
+    }
+  }
+  if (exec) {
+    const hipError_t e = hipStreamSynchronize(s);
+    (void)hipGraphExecDestroy(exec);
+    if (e != hipSuccess && result == NFR_OK) result = fail(NFR_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+  }
+  return result;
 }
 
 }  // extern "C"
