@@ -28,7 +28,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
-VALU_LANES_PER_S = 256 * 64 * 2.4e9   # FP32 lane-operations/s, non-packed (256 CUs x 4 SIMD x 16 lanes x 2.4 GHz)
+# FP32 vector issue: 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes/clock x 2 flop (FMA) x 2.4 GHz,
+# i.e. 78.6e12 full-rate lane-operations/s; transcendental instructions (exp2, sqrt)
+# issue at a quarter of that rate, so each costs 4 full-rate slots.
+VALU_LANES_PER_S = 256 * 128 * 2.4e9
+TRANS_COST = 4.0
+# lane-operation slots per pair of the on-the-fly kernel (per kernel kind):
+#   both: 3 sub + 1 mul + 2 fma (r^2), 1 mul (rho t), 2 fma (accumulate)  = 9 full-rate
+#   Gaussian: + 2 exp2;  exponential: + sqrt + 2 exp2
+SLOTS_PER_PAIR = {0: 9 + 2 * TRANS_COST, 1: 9 + 3 * TRANS_COST}
 
 
 def parse():
@@ -42,6 +50,10 @@ def parse():
     ap.add_argument("--probes", action="store_true", help="also run the roofline microbenchmarks")
     ap.add_argument("--ens-rk4-steps", type=int, default=10,
                     help="RK4 steps of the ellipsoid-ensemble comparison leg (0 = skip it)")
+    ap.add_argument("--batch-rk4-steps", type=int, default=20,
+                    help="RK4 steps of the 48-problem uneven-batch leg (0 = skip it)")
+    ap.add_argument("--adjoint-rk4-steps", type=int, default=400,
+                    help="RK4 steps of the torus adjoint leg (0 = skip it)")
     return ap.parse_args()
 
 
@@ -96,9 +108,8 @@ def roofline(form_name, res, n, npad):
         ach = bytes_per_launch / avg_s
         return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": ach / HBM_PEAK, "traffic": None, "kernel": "k_w_gemv_f32<1>"}
-    # on-the-fly: 12 FP32 lane-operations per pair for the exponential kernel
-    # (3 sub, 1 mul + 2 fma for r^2, sqrt, 1 mul, 2 exp2, 2 fma accumulates)
-    ops = 12.0 * float(npad) * npad
+    # on-the-fly (exponential kernel): lane-operation slots per pair x pairs per launch
+    ops = SLOTS_PER_PAIR[1] * float(npad) * npad
     ach = ops / avg_s
     return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tlane-op/s",
             "frac": ach / VALU_LANES_PER_S, "traffic": None, "kernel": "k_otf_pair_sum<1,4,1>"}
@@ -162,6 +173,94 @@ def ensemble_leg(P, torch, args):
         out[nm]["max_rel_linf_vs_otf_fp32"] = float(np.max(np.max(np.abs(finals[nm] - ref), axis=1) /
                                                             np.max(np.abs(ref), axis=1)))
     return out
+
+
+def batch_leg(P, torch, args):
+    """The 48-problem uneven batch (N log-uniform in [1000, 40000], B in {1, 4, 16}):
+    tuned persistent launches with graph-captured steps."""
+    import ctypes
+
+    from workloads import configs as C
+    ws_list = C.uneven_batch(steps=args.batch_rk4_steps)
+    stream = torch.cuda.Stream()
+    ctx = P.Context(0, stream)
+    probs, ks, fs, Bs, u0s = [], [], [], [], []
+    with torch.cuda.stream(stream):
+        for w in ws_list:
+            q = C.area_share_weights(w.surface)
+            probs.append(P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda()))
+            ks.append(P.kernel_struct(w.kernel_kind, *w.kernel))
+            fs.append(P.Firing(w.beta, torch.from_numpy(w.theta).cuda()))
+            Bs.append(w.b)
+            u0s.append(torch.from_numpy(w.u0.copy()).cuda())
+    torch.cuda.synchronize()
+    batch = P.Batch(ctx, probs, ks, fs, Bs)
+    ws = batch.workspace()
+    states = [u.clone() for u in u0s]
+    t0 = time.perf_counter()
+    best = batch.tune(states, ws)
+    t_tune = time.perf_counter() - t0
+    batch.integrate(states, 0.05, 1, use_graph=True, ws=ws)       # warm-up
+    for s_, u in zip(states, u0s):
+        s_.copy_(u)
+    torch.cuda.synchronize()
+    L = P.lib()
+    t0 = time.perf_counter()
+    batch.integrate(states, 0.05, args.batch_rk4_steps, use_graph=True, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pair_ints = sum(4.0 * args.batch_rk4_steps * float(w.n) ** 2 * w.b for w in ws_list)
+    chunk, wgs = batch.config
+    return {"workload": "48 problems, N log-uniform [1000, 40000], sphere/torus/ellipsoid/bumpy, Gauss Mexican hat, "
+                        "B in {1,4,16}, RK4 dt=0.05 x %d steps, graph-captured" % args.batch_rk4_steps,
+            "value": pair_ints / (t1 - t0), "unit": "pair-interactions/s", "ms_per_integration": (t1 - t0) * 1e3,
+            "tuned": {"chunk": chunk, "wgs_per_cu": wgs, "best_stage_ms": best, "tune_ms": t_tune * 1e3},
+            "launches_per_rk4_step": 1}
+
+
+def adjoint_leg(P, torch, args):
+    """Torus adjoint workload: N = 16384, RK4 dt = 0.02, checkpoints every 40 steps;
+    forward with checkpoints + discrete adjoint (gradients w.r.t. u0 and 5 parameters)."""
+    import ctypes
+
+    import numpy as np
+
+    from workloads import configs as C
+    w = C.torus_adjoint(16384, args.adjoint_rk4_steps)
+    q = C.area_share_weights(w.surface)
+    ctx = P.Context(0)
+    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
+    u0 = torch.from_numpy(w.u0[0].copy()).cuda()
+    target = torch.zeros_like(u0)
+    params = torch.tensor(list(w.kernel) + [float(w.theta[0])], dtype=torch.float64)
+    every = w.extra["ckpt_every"]
+
+    def run():
+        x0 = u0.clone().requires_grad_(True)
+        pp = params.clone().requires_grad_(True)
+        uT = P.NeuralFieldRK4.apply(x0, pp, prob, w.kernel_kind, w.beta, w.dt, w.steps, every)
+        loss = ((uT - target) ** 2).sum()
+        loss.backward()
+        return x0.grad, pp.grad
+
+    run()
+    torch.cuda.synchronize()
+    L = P.lib()
+    L.nfr_context_set_timing(ctx.handle, 1)
+    t0 = time.perf_counter()
+    gu, gp = run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, tot = ctypes.c_int64(), ctypes.c_double()
+    P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot)))
+    L.nfr_context_set_timing(ctx.handle, 0)
+    evals = 3 * 4.0 * w.steps * float(w.n) ** 2        # forward, segment recompute, adjoint sweep
+    return {"workload": "torus N=16384, exp Mexican hat, RK4 dt=0.02 x %d steps, checkpoints every %d, "
+                        "loss |u(T)|^2" % (w.steps, every),
+            "value": evals / (t1 - t0), "unit": "pair-evaluations/s (forward + recompute + adjoint)",
+            "ms_forward_plus_gradient": (t1 - t0) * 1e3, "pair_kernel_launches": int(launches.value),
+            "pair_kernel_avg_ms": tot.value / max(1, launches.value),
+            "grad_norm_u0": float(gu.norm()), "grad_params": [float(v) for v in gp]}
 
 
 def cpu_baseline(w, q, gpu_y_rows, rows):
@@ -273,6 +372,12 @@ def main():
         line["rel_err_vs_fp64_sampled_apply"] = err
     if args.ens_rk4_steps > 0:
         line["ensemble"] = ensemble_leg(P, torch, args)
+    if args.batch_rk4_steps > 0:
+        print("bench: uneven batch", file=sys.stderr, flush=True)
+        line["batch"] = batch_leg(P, torch, args)
+    if args.adjoint_rk4_steps > 0:
+        print("bench: adjoint", file=sys.stderr, flush=True)
+        line["adjoint"] = adjoint_leg(P, torch, args)
     if args.probes:
         line["probes"] = probes(P, torch, ctx)
     print(json.dumps(line), flush=True)
