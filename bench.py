@@ -33,10 +33,12 @@ HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
 # issue at a quarter of that rate, so each costs 4 full-rate slots.
 VALU_LANES_PER_S = 256 * 128 * 2.4e9
 TRANS_COST = 4.0
-# lane-operation slots per pair of the on-the-fly kernel (per kernel kind):
-#   both: 3 sub + 1 mul + 2 fma (r^2), 1 mul (rho t), 2 fma (accumulate)  = 9 full-rate
-#   Gaussian: + 2 exp2;  exponential: + sqrt + 2 exp2
-SLOTS_PER_PAIR = {0: 9 + 2 * TRANS_COST, 1: 9 + 3 * TRANS_COST}
+# Algorithmic lane-operation slots per unordered pair {i, j} of the B = 1
+# on-the-fly kernel (the kernel is radial, so one evaluation serves y_i and y_j):
+#   evaluation: 3 sub + 1 mul + 2 fma (r^2) + 1 mul (rho t) = 7 full-rate, plus
+#   2 exp2 (Gaussian) or sqrt + 2 exp2 (exponential) at 4 slots each;
+#   accumulation: 2 fma into y_i and 2 fma into y_j.
+SLOTS_PER_UNORDERED_PAIR = {0: 7 + 2 * TRANS_COST + 4, 1: 7 + 3 * TRANS_COST + 4}
 
 
 def parse():
@@ -46,6 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rk4-steps", type=int, default=500)
     ap.add_argument("--forms", default="otf,w32")
+    ap.add_argument("--no-graph", action="store_true", help="launch every kernel instead of replaying graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="also run the roofline microbenchmarks")
     ap.add_argument("--ens-rk4-steps", type=int, default=10,
@@ -74,18 +77,22 @@ def run_form(P, torch, prob, w, q_t, form, args, u0_t):
         u.copy_(u0_t)
         if Wbuf is not None:
             P._lib.check(L.nfr_w_build(prob.handle, __import__("ctypes").byref(k), form, Wbuf.data_ptr(), wbytes))
-        prob.integrate(k, f, u, w.dt, args.rk4_steps, form=form, W=Wbuf, ws=ws)
+        prob.integrate(k, f, u, w.dt, args.rk4_steps, form=form, W=Wbuf, ws=ws, use_graph=not args.no_graph)
 
     for _ in range(args.warmup):
         one()
     torch.cuda.synchronize()
     import ctypes
-    L.nfr_context_set_timing(ctx.handle, 1)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         one()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # dominant-kernel duration: HIP events around every pair-sum launch of one
+    # more integration (events are not recorded inside replayed graphs)
+    L.nfr_context_set_timing(ctx.handle, 1)
+    u.copy_(u0_t)
+    prob.integrate(k, f, u, w.dt, args.rk4_steps, form=form, W=Wbuf, ws=ws, use_graph=False)
     launches = ctypes.c_int64()
     tot_ms = ctypes.c_double()
     P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot_ms)))
@@ -108,11 +115,11 @@ def roofline(form_name, res, n, npad):
         ach = bytes_per_launch / avg_s
         return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": ach / HBM_PEAK, "traffic": None, "kernel": "k_w_gemv_f32<1>"}
-    # on-the-fly (exponential kernel): lane-operation slots per pair x pairs per launch
-    ops = SLOTS_PER_PAIR[1] * float(npad) * npad
+    # on-the-fly (exponential kernel): slots per unordered pair x npad^2 / 2 pairs per launch
+    ops = SLOTS_PER_UNORDERED_PAIR[1] * float(npad) * npad / 2.0
     ach = ops / avg_s
     return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tlane-op/s",
-            "frac": ach / VALU_LANES_PER_S, "traffic": None, "kernel": "k_otf_pair_sum<1,4,1>"}
+            "frac": ach / VALU_LANES_PER_S, "traffic": None, "kernel": "k_otf_sym<1>"}
 
 
 def ensemble_leg(P, torch, args):
@@ -318,7 +325,9 @@ def main():
 
     w = C.torus_exp(32768, steps=args.rk4_steps)
     q = C.area_share_weights(w.surface)
-    ctx = P.Context(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = P.Context(0, stream)
     xyz_t = torch.from_numpy(w.surface.xyz).cuda()
     q_t = torch.from_numpy(q).cuda()
     prob = P.Problem(ctx, xyz_t, q_t)

@@ -10,7 +10,7 @@ import os
 from ctypes import POINTER, c_char_p, c_double, c_int, c_int64, c_size_t, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libnfr.so")
+LIB_PATH = os.environ.get("NFR_LIBRARY") or os.path.join(HERE, "libnfr.so")
 
 NFR_OK = 0
 NFR_ERR_INVALID_ARG = -1

@@ -157,6 +157,141 @@ __global__ __launch_bounds__(kWG) void k_otf_pair_sum(const float4* __restrict__
   otf_tile<KIND, TPT, BS>(src, g, npad, B, chunk, pp, part, blockIdx.x, blockIdx.y, blockIdx.z * BS, s_src, s_g);
 }
 
+// ------------------------------------------------------------------ symmetric on-the-fly pair sum
+
+// The kernel is radial, so w_ij = w_ji: one evaluation of a pair can feed both
+// y_i (weight g_j) and y_j (weight g_i).  Nodes are cut into tiles of kSymTile;
+// workgroup p handles the tile pair (I, J), I <= J, decoded from p = J (J+1)/2 + I.
+// Off-diagonal pairs (I < J) produce the row sums of tile I over sources in J
+// and the column sums of tile J over sources in I; diagonal pairs only row sums.
+// Slots: the row sums of (I, J) go to slot J of the nodes of I, the column
+// sums to slot I of the nodes of J, so every node receives exactly one
+// contribution per tile index and the combine adds slots 0..nt-1 in order.
+//
+// Each lane keeps kSymTPT targets in registers.  A group of 64 sources is
+// loaded one per lane and rotated around the wave 64 times (DPP wave rotate
+// by one lane); each source carries its own column accumulators, so after a
+// full turn they hold the sum over the wave's 64 * kSymTPT targets and the
+// source is back in its lane.  Row sums: FP32 per group of 64 sources, folded
+// into FP64; column sums: FP32 over the wave, FP64 across waves.
+#ifndef NFR_SYM_WAVES
+#define NFR_SYM_WAVES 2
+#endif
+#ifndef NFR_SYM_TPT
+#define NFR_SYM_TPT 3
+#endif
+constexpr int kSymWaves = NFR_SYM_WAVES;
+constexpr int kSymTPT = NFR_SYM_TPT;
+constexpr int kSymThreads = 64 * kSymWaves;
+constexpr int kSymTile = kSymThreads * kSymTPT;   // 384 nodes by default
+
+__device__ inline float wave_ror1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, false));
+}
+
+__host__ __device__ inline int64_t sym_pairs(int64_t nt) { return nt * (nt + 1) / 2; }
+
+__device__ inline void sym_decode(int64_t p, int64_t* I, int64_t* J) {
+  int64_t j = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while (j * (j + 1) / 2 > p) --j;
+  while ((j + 1) * (j + 2) / 2 <= p) ++j;
+  *J = j;
+  *I = p - j * (j + 1) / 2;
+}
+
+template <int KIND, bool COLS>
+__device__ inline void sym_tile(const float4* __restrict__ src, const float* __restrict__ g, int64_t npad,
+                                const PairParams& pp, double* __restrict__ part, int64_t I, int64_t J,
+                                double (*colsum)[kSymTile]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const float rho = pp.rho;
+  float xi[kSymTPT], yi[kSymTPT], zi[kSymTPT], gi[kSymTPT];
+#pragma unroll
+  for (int k = 0; k < kSymTPT; ++k) {
+    const int64_t t = I * kSymTile + (int64_t)wave * 64 * kSymTPT + k * 64 + lane;
+    const int64_t tc = t < npad ? t : npad - 1;
+    const float4 p = src[tc];
+    xi[k] = p.x * pp.sig;
+    yi[k] = p.y * pp.sig;
+    zi[k] = p.z * pp.sig;
+    gi[k] = t < npad ? g[t] : 0.0f;
+  }
+  double racc[kSymTPT];
+#pragma unroll
+  for (int k = 0; k < kSymTPT; ++k) racc[k] = 0.0;
+
+  int64_t nsrc = npad - J * kSymTile;
+  if (nsrc > kSymTile) nsrc = kSymTile;
+  const int ngroups = (int)(nsrc / 64);
+  for (int grp = 0; grp < ngroups; ++grp) {
+    const int64_t j = J * kSymTile + grp * 64 + lane;
+    const float4 s4 = src[j];
+    float sx = s4.x * pp.sig, sy = s4.y * pp.sig, sz = s4.z * pp.sig, sg = g[j];
+    float ce = 0.0f, ci = 0.0f;
+    float ae[kSymTPT], ai[kSymTPT];
+#pragma unroll
+    for (int k = 0; k < kSymTPT; ++k) ae[k] = ai[k] = 0.0f;
+#pragma unroll 2
+    for (int step = 0; step < 64; ++step) {
+#pragma unroll
+      for (int k = 0; k < kSymTPT; ++k) {
+        const float dx = xi[k] - sx;
+        const float dy = yi[k] - sy;
+        const float dz = zi[k] - sz;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float t = (KIND == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+        const float e1 = __builtin_amdgcn_exp2f(-t);
+        const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
+        ae[k] = fmaf(e1, sg, ae[k]);
+        ai[k] = fmaf(e2, sg, ai[k]);
+        if (COLS) {
+          ce = fmaf(e1, gi[k], ce);
+          ci = fmaf(e2, gi[k], ci);
+        }
+      }
+      sx = wave_ror1(sx);
+      sy = wave_ror1(sy);
+      sz = wave_ror1(sz);
+      sg = wave_ror1(sg);
+      if (COLS) {
+        ce = wave_ror1(ce);
+        ci = wave_ror1(ci);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kSymTPT; ++k) racc[k] += pp.Ae * (double)ae[k] - pp.Ai * (double)ai[k];
+    if (COLS) colsum[wave][grp * 64 + lane] = pp.Ae * (double)ce - pp.Ai * (double)ci;
+  }
+#pragma unroll
+  for (int k = 0; k < kSymTPT; ++k) {
+    const int64_t t = I * kSymTile + (int64_t)wave * 64 * kSymTPT + k * 64 + lane;
+    if (t < npad) part[J * npad + t] = racc[k];
+  }
+  if (COLS) {
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < nsrc; jj += kSymThreads) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < kSymWaves; ++w) sum += colsum[w][jj];
+      part[I * npad + J * kSymTile + jj] = sum;
+    }
+  }
+}
+
+// part[s * npad + i]: slot s of node i (see above); nt = ceil(npad / kSymTile).
+template <int KIND>
+__global__ __launch_bounds__(kSymThreads) void k_otf_sym(const float4* __restrict__ src, const float* __restrict__ g,
+                                                         int64_t npad, PairParams pp, double* __restrict__ part) {
+  __shared__ double colsum[kSymWaves][kSymTile];
+  int64_t I, J;
+  sym_decode(blockIdx.x, &I, &J);
+  if (I == J)
+    sym_tile<KIND, false>(src, g, npad, pp, part, I, J, colsum);
+  else
+    sym_tile<KIND, true>(src, g, npad, pp, part, I, J, colsum);
+}
+
 // ------------------------------------------------------------------ reductions
 
 // y[b*n + i] = sum over splits (in order) of part[(s*B + b)*npad + i], FP64.

@@ -166,7 +166,12 @@ int resolve_form(int form, int64_t n, int B) {
   return NFR_FORM_ONTHEFLY_FP32;
 }
 
+// B = 1 on the fly uses the symmetric kernel: one slot per tile.
+bool use_sym(int form, int B) { return form == NFR_FORM_ONTHEFLY_FP32 && B == 1; }
+int64_t sym_tiles(int64_t npad) { return ceil_div(npad, kSymTile); }
+
 int nsplit_for(const ProblemView& pv, int B, int form) {
+  if (use_sym(form, B)) return (int)sym_tiles(pv.npad);
   if (form == NFR_FORM_ONTHEFLY_FP32) return plan_otf(pv.npad, B).nsplit;
   if (form == NFR_FORM_W_FP32) return plan_gemv(pv.n, pv.npad, B).nsplit;
   return mfma_nsplit(pv.n, pv.npad, B);
@@ -254,7 +259,14 @@ int timing_mark(nfr_context* ctx) {
 
 int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B, const void* W, const Workspace& w,
                      hipStream_t s) {
-  if (form == NFR_FORM_ONTHEFLY_FP32) {
+  if (use_sym(form, B)) {
+    const PairParams pp = pair_params(k);
+    const unsigned grid = (unsigned)sym_pairs(sym_tiles(pv.npad));
+    if (k.kind == NFR_KERNEL_GAUSS_MH)
+      hipLaunchKernelGGL(k_otf_sym<0>, dim3(grid), dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part);
+    else
+      hipLaunchKernelGGL(k_otf_sym<1>, dim3(grid), dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part);
+  } else if (form == NFR_FORM_ONTHEFLY_FP32) {
     const OtfPlan pl = plan_otf(pv.npad, B);
     const PairParams pp = pair_params(k);
     if (k.kind == NFR_KERNEL_GAUSS_MH)
