@@ -211,6 +211,16 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
                   double* ckpt_dev, int64_t ckpt_every, int use_graph,
                   void* ws_dev, size_t ws_bytes);
 
+/* Adams-Bashforth 5 with fixed step dt for `steps` steps of u' = -u + K(u), the
+ * stepper the paper's section 5.1 showcase uses: one operator application per
+ * step, u_{n+1} = u_n + dt/720 (1901 F_n - 2774 F_{n-1} + 2616 F_{n-2}
+ * - 1274 F_{n-3} + 251 F_{n-4}), F(u) = -u + K(u), state updates in FP64.  The
+ * first four steps are classical RK4 (whose first stage gives F(u_n)).
+ * Arguments as nfr_integrate (no checkpoints, no graph replay). */
+size_t nfr_integrate_ab5_workspace_size(const nfr_problem* prob, int B, int form);
+int nfr_integrate_ab5(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, double* u_dev,
+                      double dt, int64_t steps, int form, const void* w_dev, void* ws_dev, size_t ws_bytes);
+
 /* ---------------------------------------------------------------- uneven batch */
 
 /* Groups P problems of one context (any mix of node counts, kernels, firing

@@ -157,6 +157,29 @@ def rk4(op: DenseOperator, u0, beta, theta, dt, steps, save_every=0):
     return (u, saved) if save_every else u
 
 
+# Adams-Bashforth 5 weights of F_n, F_{n-1}, ..., F_{n-4} (times dt).
+AB5_WEIGHTS = (1901.0 / 720.0, -2774.0 / 720.0, 2616.0 / 720.0, -1274.0 / 720.0, 251.0 / 720.0)
+
+
+def ab5(op: DenseOperator, u0, beta, theta, dt, steps):
+    """Adams-Bashforth 5, the stepper of the paper's section 5.1 showcase:
+    u_{n+1} = u_n + dt sum_k a_k F(u_{n-k}), F(u) = -u + K(u), one operator
+    application per step.  The paper does not say how the multistep method is
+    started; here the first four steps are classical RK4, and F(u_n) of those
+    steps is the first RK4 stage.
+    """
+    u = np.array(np.atleast_2d(u0), dtype=np.float64)
+    hist = []
+    for n in range(steps):
+        F = op.rhs(u, beta, theta)
+        hist = (hist + [F])[-5:]
+        if n < 4:
+            u = rk4_step(op, u, beta, theta, dt)
+        else:
+            u = u + dt * sum(a * hist[-1 - k] for k, a in enumerate(AB5_WEIGHTS))
+    return u
+
+
 def rk4_rhs_dense(op: DenseOperator, beta, theta):
     """Right-hand side as a plain function of a flat state (for scipy's integrators)."""
     def fun(_t, y):

@@ -157,6 +157,18 @@ class Problem:
         self._last_ws = ws
         return ck
 
+    def integrate_ab5(self, kernel: L.NfrKernel, firing: Firing, u: torch.Tensor, dt: float, steps: int,
+                      form: int = L.FORM_ONTHEFLY_FP32, W: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+        """Advances u in place by `steps` Adams-Bashforth 5 steps (RK4 start-up)."""
+        B = self._check_state(u)
+        ws_bytes = L.lib().nfr_integrate_ab5_workspace_size(self.handle, B, form)
+        if ws is None or ws.numel() < ws_bytes:
+            ws = _dev_buffer(ws_bytes, self.ctx.device)
+        fs = firing.struct(self.ctx.device)
+        L.check(L.lib().nfr_integrate_ab5(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), float(dt),
+                                          int(steps), form, _ptr(W), ws.data_ptr(), ws_bytes))
+        self._last_ws = ws
+
     def adjoint(self, kernel: L.NfrKernel, firing: Firing, ckpt: torch.Tensor, ckpt_every: int, steps: int,
                 dt: float, ubarT: torch.Tensor):
         """Discrete-adjoint gradients of L(u(T)) for a single state: (dL/du0 (N,), dL/dp (5,) float64)."""

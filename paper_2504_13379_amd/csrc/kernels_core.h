@@ -313,11 +313,13 @@ __global__ __launch_bounds__(kWG) void k_reduce_partials(const double* __restric
 //   s=3: ksum += 2k,      v <- u + dt k
 //   s=4: u <- u + dt/6 (ksum + k),  v <- u
 // then g[b*npad + i] = s_i f_b(v) for the next stage (s_i = q_i or 1).
+// k1_out (may be null) receives k_1 = F(u_n) at stage 1 (the Adams-Bashforth start-up records it).
 __global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ part, int nsplit, int64_t n,
                                                      int64_t npad, int B, int stage, double dt,
                                                      double* __restrict__ u, double* __restrict__ v,
                                                      double* __restrict__ ksum, const double* __restrict__ qd,
-                                                     int with_q, Firing fr, float* __restrict__ g) {
+                                                     int with_q, Firing fr, float* __restrict__ g,
+                                                     double* __restrict__ k1_out) {
   const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (idx >= n * (int64_t)B) return;
   const int b = (int)(idx / n);
@@ -328,6 +330,7 @@ __global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ 
   double ui = u[idx];
   double vn;
   if (stage == 1) {
+    if (k1_out) k1_out[idx] = k;
     ksum[idx] = k;
     vn = ui + 0.5 * dt * k;
   } else if (stage == 2) {
@@ -344,6 +347,41 @@ __global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ 
   v[idx] = vn;
   const double s = with_q ? qd[i] : 1.0;
   g[(int64_t)b * npad + i] = (float)(s * sigmoid(vn, fr.beta, state_theta(fr, b)));
+}
+
+// ------------------------------------------------------------------ Adams-Bashforth 5
+
+// Weights of F_n, F_{n-1}, ..., F_{n-4} (times dt) of the five-step Adams-Bashforth method.
+struct Ab5Weights {
+  double a[5];
+};
+
+// One AB5 step (one thread per (i, b), i < n), all FP64:
+//   F_n = -u_n + y (y = sum of partials),  hist[slot(n)] = F_n,
+//   u_{n+1} = u_n + dt sum_k a_k hist[slot(n - k)],
+// then g[b*npad + i] = s_i f_b(u_{n+1}).  hist holds 5 arrays of n*B; slots[k]
+// is the array holding F_{n-k}.
+__global__ __launch_bounds__(kWG) void k_ab5_combine(const double* __restrict__ part, int nsplit, int64_t n,
+                                                     int64_t npad, int B, double dt, Ab5Weights wt, int4 slots03,
+                                                     int slot4, double* __restrict__ u, double* __restrict__ hist,
+                                                     const double* __restrict__ qd, int with_q, Firing fr,
+                                                     float* __restrict__ g) {
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  const int64_t nb = n * (int64_t)B;
+  if (idx >= nb) return;
+  const int b = (int)(idx / n);
+  const int64_t i = idx - (int64_t)b * n;
+  double y = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  const double ui = u[idx];
+  const double F = -ui + y;
+  hist[slots03.x * nb + idx] = F;
+  const double incr = wt.a[0] * F + wt.a[1] * hist[slots03.y * nb + idx] + wt.a[2] * hist[slots03.z * nb + idx] +
+                      wt.a[3] * hist[slots03.w * nb + idx] + wt.a[4] * hist[(int64_t)slot4 * nb + idx];
+  const double un = ui + dt * incr;
+  u[idx] = un;
+  const double s = with_q ? qd[i] : 1.0;
+  g[(int64_t)b * npad + i] = (float)(s * sigmoid(un, fr.beta, state_theta(fr, b)));
 }
 
 // ------------------------------------------------------------------ W form (FP32)

@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__
                                                       int64_t npad, int B, int stage, double dt,
                                                       double* __restrict__ u, double* __restrict__ v,
                                                       double* __restrict__ ksum, Firing fr, T* __restrict__ Ghi,
-                                                      T* __restrict__ Glo) {
+                                                      T* __restrict__ Glo, double* __restrict__ k1_out) {
   const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (idx >= n * (int64_t)B) return;
   const int b = (int)(idx / n);
@@ -310,6 +310,7 @@ __global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__
   double ui = u[idx];
   double vn;
   if (stage == 1) {
+    if (k1_out) k1_out[idx] = k;
     ksum[idx] = k;
     vn = ui + 0.5 * dt * k;
   } else if (stage == 2) {
@@ -326,6 +327,34 @@ __global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__
   v[idx] = vn;
   T hi, lo;
   split_hi_lo<T>(sigmoid(vn, fr.beta, state_theta(fr, b)), hi, lo);
+  Ghi[(int64_t)b * npad + i] = hi;
+  Glo[(int64_t)b * npad + i] = lo;
+}
+
+// One Adams-Bashforth 5 step for the split forms (see k_ab5_combine); the next
+// sources are written as Ghi/Glo.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_mfma_ab5_combine(const double* __restrict__ part, int nsplit, int64_t n,
+                                                          int64_t npad, int B, double dt, Ab5Weights wt,
+                                                          int4 slots03, int slot4, double* __restrict__ u,
+                                                          double* __restrict__ hist, Firing fr,
+                                                          T* __restrict__ Ghi, T* __restrict__ Glo) {
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  const int64_t nb = n * (int64_t)B;
+  if (idx >= nb) return;
+  const int b = (int)(idx / n);
+  const int64_t i = idx - (int64_t)b * n;
+  double y = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  const double ui = u[idx];
+  const double F = -ui + y;
+  hist[slots03.x * nb + idx] = F;
+  const double incr = wt.a[0] * F + wt.a[1] * hist[slots03.y * nb + idx] + wt.a[2] * hist[slots03.z * nb + idx] +
+                      wt.a[3] * hist[slots03.w * nb + idx] + wt.a[4] * hist[(int64_t)slot4 * nb + idx];
+  const double un = ui + dt * incr;
+  u[idx] = un;
+  T hi, lo;
+  split_hi_lo<T>(sigmoid(un, fr.beta, state_theta(fr, b)), hi, lo);
   Ghi[(int64_t)b * npad + i] = hi;
   Glo[(int64_t)b * npad + i] = lo;
 }
@@ -418,21 +447,41 @@ inline void launch_mfma_apply(const ProblemView& pv, int form, int B, const void
 template <typename T>
 inline void launch_mfma_combine_t(const ProblemView& pv, int B, int stage, double dt, double* u, double* v,
                                   double* ksum, const double* part, int nsplit, const Firing& fr, void* g,
-                                  hipStream_t s) {
+                                  double* k1_out, hipStream_t s) {
   void *ghi, *glo;
   mfma_g_split(g, pv.npad, B, &ghi, &glo);
   const int64_t total = pv.n * (int64_t)B;
   hipLaunchKernelGGL(k_mfma_combine<T>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit, pv.n,
-                     pv.npad, B, stage, dt, u, v, ksum, fr, static_cast<T*>(ghi), static_cast<T*>(glo));
+                     pv.npad, B, stage, dt, u, v, ksum, fr, static_cast<T*>(ghi), static_cast<T*>(glo), k1_out);
 }
 
 inline void launch_mfma_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, double* v,
                                 double* ksum, const double* part, int nsplit, const Firing& fr, float* g,
-                                hipStream_t s) {
+                                double* k1_out, hipStream_t s) {
   if (form == 2)
-    launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, s);
+    launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, s);
   else
-    launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, s);
+    launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, s);
+}
+
+template <typename T>
+inline void launch_mfma_ab5_t(const ProblemView& pv, int B, double dt, const Ab5Weights& wt, int4 s03, int s4,
+                              double* u, double* hist, const double* part, int nsplit, const Firing& fr, void* g,
+                              hipStream_t s) {
+  void *ghi, *glo;
+  mfma_g_split(g, pv.npad, B, &ghi, &glo);
+  const int64_t total = pv.n * (int64_t)B;
+  hipLaunchKernelGGL(k_mfma_ab5_combine<T>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit,
+                     pv.n, pv.npad, B, dt, wt, s03, s4, u, hist, fr, static_cast<T*>(ghi), static_cast<T*>(glo));
+}
+
+inline void launch_mfma_ab5(const ProblemView& pv, int form, int B, double dt, const Ab5Weights& wt, int4 s03, int s4,
+                            double* u, double* hist, const double* part, int nsplit, const Firing& fr, float* g,
+                            hipStream_t s) {
+  if (form == 2)
+    launch_mfma_ab5_t<__bf16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, g, s);
+  else
+    launch_mfma_ab5_t<_Float16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, g, s);
 }
 
 inline void launch_mfma_reduce(const ProblemView& pv, int, int B, const double* part, int nsplit, double* y,

@@ -292,15 +292,35 @@ int launch_pairs(nfr_context* ctx, const ProblemView& pv, const nfr_kernel& k, i
 }
 
 int launch_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, const Workspace& w,
-                   const Firing& fr, hipStream_t s) {
+                   const Firing& fr, hipStream_t s, double* k1_out = nullptr) {
   const int nsplit = nsplit_for(pv, B, form);
   const int64_t total = pv.n * (int64_t)B;
   if (is_mfma_form(form)) {
-    launch_mfma_combine(pv, form, B, stage, dt, u, w.v, w.ksum, w.part, nsplit, fr, w.g, s);
+    launch_mfma_combine(pv, form, B, stage, dt, u, w.v, w.ksum, w.part, nsplit, fr, w.g, k1_out, s);
   } else {
     const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
     hipLaunchKernelGGL(k_rk4_combine, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
-                       pv.npad, B, stage, dt, u, w.v, w.ksum, pv.q, with_q, fr, w.g);
+                       pv.npad, B, stage, dt, u, w.v, w.ksum, pv.q, with_q, fr, w.g, k1_out);
+  }
+  NFR_HIP_LAUNCH();
+  return NFR_OK;
+}
+
+// One Adams-Bashforth 5 step from the partial sums of K(u_n); n_step >= 4.
+int launch_ab5(const ProblemView& pv, int form, int B, int64_t n_step, double dt, double* u, double* hist,
+               const Workspace& w, const Firing& fr, hipStream_t s) {
+  const Ab5Weights wt{{1901.0 / 720.0, -2774.0 / 720.0, 2616.0 / 720.0, -1274.0 / 720.0, 251.0 / 720.0}};
+  auto slot = [&](int64_t m) { return (int)(m % 5); };
+  const int4 s03 = make_int4(slot(n_step), slot(n_step - 1), slot(n_step - 2), slot(n_step - 3));
+  const int s4 = slot(n_step - 4);
+  const int nsplit = nsplit_for(pv, B, form);
+  const int64_t total = pv.n * (int64_t)B;
+  if (is_mfma_form(form)) {
+    launch_mfma_ab5(pv, form, B, dt, wt, s03, s4, u, hist, w.part, nsplit, fr, w.g, s);
+  } else {
+    const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
+    hipLaunchKernelGGL(k_ab5_combine, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
+                       pv.npad, B, dt, wt, s03, s4, u, hist, pv.q, with_q, fr, w.g);
   }
   NFR_HIP_LAUNCH();
   return NFR_OK;
@@ -1111,6 +1131,56 @@ int nfr_batch_integrate(nfr_batch* b, double* const* u_devs, double dt, int64_t 
     if (e != hipSuccess && result == NFR_OK) result = fail(NFR_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
   }
   return result;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- Adams-Bashforth 5
+
+extern "C" {
+
+size_t nfr_integrate_ab5_workspace_size(const nfr_problem* prob, int B, int form) {
+  if (!prob || B < 1 || B > kMaxB) return 0;
+  form = resolve_form(form, prob->view.n, B);
+  return carve(nullptr, prob->view, B, form, true).bytes + align256(size_t(5) * prob->view.n * B * sizeof(double));
+}
+
+int nfr_integrate_ab5(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, double* u_dev,
+                      double dt, int64_t steps, int form, const void* w_dev, void* ws_dev, size_t ws_bytes) {
+  int st;
+  if ((st = check_problem(prob)) || (st = check_kernel(kernel)) || (st = check_firing(firing)) || (st = check_form(form)))
+    return st;
+  if (B < 1 || B > kMaxB) return fail(NFR_ERR_INVALID_ARG, "B = %d outside [1, %d]", B, kMaxB);
+  if (!u_dev) return fail(NFR_ERR_INVALID_ARG, "u_dev is NULL");
+  if (!is_finite_d(dt)) return fail(NFR_ERR_NONFINITE, "dt must be finite");
+  if (!(dt > 0.0)) return fail(NFR_ERR_INVALID_ARG, "dt must be > 0");
+  if (steps < 0) return fail(NFR_ERR_INVALID_ARG, "steps must be >= 0");
+  const ProblemView& pv = prob->view;
+  form = resolve_form(form, pv.n, B);
+  if ((st = check_w(prob, form, w_dev))) return st;
+  const Workspace w = carve(ws_dev, pv, B, form, true);
+  const size_t need = nfr_integrate_ab5_workspace_size(prob, B, form);
+  if (!ws_dev || ws_bytes < need) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  double* hist = reinterpret_cast<double*>(static_cast<char*>(ws_dev) + w.bytes);
+  NFR_HIP(hipSetDevice(prob->ctx->device));
+  hipStream_t s = prob->ctx->stream;
+  const Firing fr = firing_of(*firing);
+  if (steps == 0) return NFR_OK;
+  if ((st = launch_prep(pv, form, B, u_dev, fr, w, w.v, s))) return st;
+  const int64_t nb = pv.n * (int64_t)B;
+  for (int64_t n = 0; n < steps; ++n) {
+    if (n < 4) {
+      // classical RK4 start-up; its first stage is F(u_n), kept for the multistep formula
+      for (int stage = 1; stage <= 4; ++stage) {
+        if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return st;
+        if ((st = launch_combine(pv, form, B, stage, dt, u_dev, w, fr, s, hist + (n % 5) * nb))) return st;
+      }
+    } else {
+      if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return st;
+      if ((st = launch_ab5(pv, form, B, n, dt, u_dev, hist, w, fr, s))) return st;
+    }
+  }
+  return NFR_OK;
 }
 
 }  // extern "C"

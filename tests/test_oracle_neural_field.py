@@ -187,3 +187,56 @@ def test_fd_step_1e4_second_order_is_truncation_limited():
     worst = np.argmax(np.abs(fd2 - gp) / np.abs(gp))
     ratio = abs(fd2b[worst] - gp[worst]) / abs(fd2[worst] - gp[worst])
     assert 50 < ratio < 200
+
+
+def test_ab5_weights_integrate_the_interpolating_polynomial():
+    """a_k = int_0^1 L_k(s) ds with L_k the Lagrange basis on the nodes s = 0, -1, ..., -4
+    (the defining property of Adams-Bashforth weights), in exact rational arithmetic."""
+    from fractions import Fraction
+    nodes = [0, -1, -2, -3, -4]
+    for k, a in enumerate(NF.AB5_WEIGHTS):
+        poly = [Fraction(1)]                       # coefficients, lowest degree first
+        denom = Fraction(1)
+        for m, sm in enumerate(nodes):
+            if m == k:
+                continue
+            poly = [Fraction(0)] + poly            # multiply by s
+            for d in range(len(poly) - 1):
+                poly[d] -= sm * poly[d + 1]        # ... minus s_m
+            denom *= nodes[k] - sm
+        integral = sum(c / (d + 1) for d, c in enumerate(poly)) / denom
+        assert abs(float(integral) - a) < 1e-15
+
+
+def test_ab5_fifth_order_against_dop853():
+    s = S.sphere(120)
+    q = np.full(120, 4 * math.pi / 120)
+    op = NF.DenseOperator(s.xyz, q, NF.GAUSS_MH, GAUSS)
+    u0 = C.bump(s.xyz, s.xyz[5])[None, :]
+    T = 2.0
+    ref = solve_ivp(NF.rk4_rhs_dense(op, 20.0, 0.2), (0, T), u0.ravel(), method="DOP853",
+                    rtol=1e-13, atol=1e-13).y[:, -1]
+    errs = [np.max(np.abs(NF.ab5(op, u0, 20.0, 0.2, dt, int(round(T / dt))).ravel() - ref))
+            for dt in (0.04, 0.02, 0.01)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 24 < r1 < 40 and 24 < r2 < 40, (r1, r2)
+
+
+def test_ab5_beta_zero_matches_companion_matrix():
+    """beta = 0: e_n = u_n - b obeys e_{n+1} = e_n - dt sum_k a_k e_{n-k} after an RK4 start;
+    the state after n steps is a power of the 5 x 5 companion matrix applied to the start."""
+    x, q, U, p = _problem(n=25, seed=4, kind=NF.EXP_MH)
+    op = NF.DenseOperator(x, q, NF.EXP_MH, p)
+    dt, steps = 0.05, 23
+    b = 0.5 * (op.w @ q)
+    R = pins.rk4_amplification(-dt)
+    e0 = U[0] - b
+    start = [R ** n * e0 for n in range(5)]        # e_0 .. e_4 from the RK4 start
+    Cm = np.zeros((5, 5))
+    Cm[0, 0] = 1 - dt * NF.AB5_WEIGHTS[0]
+    Cm[0, 1:] = [-dt * a for a in NF.AB5_WEIGHTS[1:]]
+    Cm[1:, :4] = np.eye(4)
+    state = np.stack(start[::-1])                  # rows: e_4, e_3, ..., e_0
+    state = np.linalg.matrix_power(Cm, steps - 4) @ state
+    got = NF.ab5(op, U[:1], 0.0, 0.3, dt, steps)[0]
+    np.testing.assert_allclose(got, b + state[0], rtol=1e-11, atol=1e-13)
