@@ -221,6 +221,16 @@ size_t nfr_integrate_ab5_workspace_size(const nfr_problem* prob, int B, int form
 int nfr_integrate_ab5(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, double* u_dev,
                       double dt, int64_t steps, int form, const void* w_dev, void* ws_dev, size_t ws_bytes);
 
+/* Neural field with synaptic depression (paper section 5.2, eq. nfsyndep), the
+ * efficacy a acting on the presynaptic side of the integral:
+ *   u' = -u + sum_j w_ij q_j a_j f(u_j),    tau a' = 1 - a - beta_d a f(u),
+ * classical RK4 on the pair, on-the-fly FP32 pair sums, FP64 state updates.
+ * u_dev and a_dev: n x B FP64 (device), advanced in place. */
+size_t nfr_integrate_syndep_workspace_size(const nfr_problem* prob, int B);
+int nfr_integrate_syndep(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, double* u_dev,
+                         double* a_dev, double tau, double beta_d, double dt, int64_t steps, void* ws_dev,
+                         size_t ws_bytes);
+
 /* ---------------------------------------------------------------- uneven batch */
 
 /* Groups P problems of one context (any mix of node counts, kernels, firing

@@ -180,6 +180,30 @@ def ab5(op: DenseOperator, u0, beta, theta, dt, steps):
     return u
 
 
+def syndep_rhs(op: DenseOperator, U, A, beta, theta, tau, beta_d):
+    """Neural field with synaptic depression (paper section 5.2, eq. nfsyndep),
+    discretised like eq. NFODETilde with the efficacy as a presynaptic field:
+      u_i' = -u_i + sum_j w_ij q_j a_j f(u_j),    tau a_i' = 1 - a_i - beta_d a_i f(u_i).
+    """
+    f = firing(U, beta, theta)
+    Ku = (op.q[None, :] * A * f) @ op.w.T
+    return -U + Ku, (1.0 - A - beta_d * A * f) / tau
+
+
+def syndep_rk4(op: DenseOperator, u0, a0, beta, theta, tau, beta_d, dt, steps):
+    """Classical RK4 for the coupled (u, a) system of `syndep_rhs`."""
+    U = np.array(np.atleast_2d(u0), dtype=np.float64)
+    A = np.array(np.atleast_2d(a0), dtype=np.float64)
+    for _ in range(steps):
+        k1u, k1a = syndep_rhs(op, U, A, beta, theta, tau, beta_d)
+        k2u, k2a = syndep_rhs(op, U + 0.5 * dt * k1u, A + 0.5 * dt * k1a, beta, theta, tau, beta_d)
+        k3u, k3a = syndep_rhs(op, U + 0.5 * dt * k2u, A + 0.5 * dt * k2a, beta, theta, tau, beta_d)
+        k4u, k4a = syndep_rhs(op, U + dt * k3u, A + dt * k3a, beta, theta, tau, beta_d)
+        U = U + dt / 6.0 * (k1u + 2 * k2u + 2 * k3u + k4u)
+        A = A + dt / 6.0 * (k1a + 2 * k2a + 2 * k3a + k4a)
+    return U, A
+
+
 def rk4_rhs_dense(op: DenseOperator, beta, theta):
     """Right-hand side as a plain function of a flat state (for scipy's integrators)."""
     def fun(_t, y):

@@ -80,6 +80,9 @@ def _declare(lib):
         "nfr_integrate_ab5_workspace_size": (c_size_t, [P, c_int, c_int]),
         "nfr_integrate_ab5": (c_int, [P, POINTER(NfrKernel), POINTER(NfrFiring), c_int, P, c_double, c_int64, c_int,
                                       P, P, c_size_t]),
+        "nfr_integrate_syndep_workspace_size": (c_size_t, [P, c_int]),
+        "nfr_integrate_syndep": (c_int, [P, POINTER(NfrKernel), POINTER(NfrFiring), c_int, P, P, c_double, c_double,
+                                         c_double, c_int64, P, c_size_t]),
         "nfr_batch_workspace_size": (c_size_t, [P]),
         "nfr_batch_create": (c_int, [P, c_int, POINTER(P), POINTER(NfrKernel), POINTER(NfrFiring), POINTER(c_int),
                                      POINTER(P)]),

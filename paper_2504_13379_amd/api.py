@@ -169,6 +169,21 @@ class Problem:
                                           int(steps), form, _ptr(W), ws.data_ptr(), ws_bytes))
         self._last_ws = ws
 
+    def integrate_syndep(self, kernel: L.NfrKernel, firing: Firing, u: torch.Tensor, a: torch.Tensor, tau: float,
+                         beta_d: float, dt: float, steps: int, ws: torch.Tensor | None = None):
+        """Advances (u, a) in place: neural field with synaptic depression, RK4."""
+        B = self._check_state(u)
+        if self._check_state(a) != B:
+            raise ValueError("u and a must have the same shape")
+        ws_bytes = L.lib().nfr_integrate_syndep_workspace_size(self.handle, B)
+        if ws is None or ws.numel() < ws_bytes:
+            ws = _dev_buffer(ws_bytes, self.ctx.device)
+        fs = firing.struct(self.ctx.device)
+        L.check(L.lib().nfr_integrate_syndep(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), a.data_ptr(),
+                                             float(tau), float(beta_d), float(dt), int(steps), ws.data_ptr(),
+                                             ws_bytes))
+        self._last_ws = ws
+
     def adjoint(self, kernel: L.NfrKernel, firing: Firing, ckpt: torch.Tensor, ckpt_every: int, steps: int,
                 dt: float, ubarT: torch.Tensor):
         """Discrete-adjoint gradients of L(u(T)) for a single state: (dL/du0 (N,), dL/dp (5,) float64)."""

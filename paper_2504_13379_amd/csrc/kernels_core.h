@@ -384,6 +384,76 @@ __global__ __launch_bounds__(kWG) void k_ab5_combine(const double* __restrict__ 
   g[(int64_t)b * npad + i] = (float)(s * sigmoid(un, fr.beta, state_theta(fr, b)));
 }
 
+// ------------------------------------------------------------------ synaptic depression
+
+// Neural field with synaptic depression (paper section 5.2, eq. nfsyndep): the
+// sources carry the presynaptic efficacy a,
+//   u' = -u + K(u, a),  K_i = sum_j w_ij q_j a_j f(u_j),   tau a' = 1 - a - beta_d a f(u).
+// g[b*npad + j] = q_j a_j f_b(u_j) (zero on padding); copies u, a into the stage inputs.
+__global__ __launch_bounds__(kWG) void k_syndep_prep(const double* __restrict__ u, const double* __restrict__ a,
+                                                     int64_t n, int64_t npad, int B, const double* __restrict__ qd,
+                                                     Firing fr, float* __restrict__ g, double* __restrict__ vu,
+                                                     double* __restrict__ va) {
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (idx >= npad * (int64_t)B) return;
+  const int b = (int)(idx / npad);
+  const int64_t j = idx - (int64_t)b * npad;
+  float out = 0.0f;
+  if (j < n) {
+    const int64_t e = (int64_t)b * n + j;
+    const double uj = u[e], aj = a[e];
+    vu[e] = uj;
+    va[e] = aj;
+    out = (float)(qd[j] * aj * sigmoid(uj, fr.beta, state_theta(fr, b)));
+  }
+  g[idx] = out;
+}
+
+// RK4 stage combination of the coupled (u, a) system, all FP64; next sources
+// g = q a f(u) at the new stage input.
+__global__ __launch_bounds__(kWG) void k_syndep_combine(const double* __restrict__ part, int nsplit, int64_t n,
+                                                        int64_t npad, int B, int stage, double dt, double inv_tau,
+                                                        double beta_d, double* __restrict__ u, double* __restrict__ a,
+                                                        double* __restrict__ vu, double* __restrict__ va,
+                                                        double* __restrict__ ku_sum, double* __restrict__ ka_sum,
+                                                        const double* __restrict__ qd, Firing fr,
+                                                        float* __restrict__ g) {
+  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (idx >= n * (int64_t)B) return;
+  const int b = (int)(idx / n);
+  const int64_t i = idx - (int64_t)b * n;
+  const double th = state_theta(fr, b);
+  double y = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  const double cu = vu[idx], ca = va[idx];
+  const double ku = -cu + y;
+  const double ka = (1.0 - ca - beta_d * ca * sigmoid(cu, fr.beta, th)) * inv_tau;
+  double ui = u[idx], ai = a[idx];
+  double nu, na;
+  if (stage == 1) {
+    ku_sum[idx] = ku;
+    ka_sum[idx] = ka;
+    nu = ui + 0.5 * dt * ku;
+    na = ai + 0.5 * dt * ka;
+  } else if (stage == 2 || stage == 3) {
+    ku_sum[idx] += 2.0 * ku;
+    ka_sum[idx] += 2.0 * ka;
+    const double c = stage == 2 ? 0.5 * dt : dt;
+    nu = ui + c * ku;
+    na = ai + c * ka;
+  } else {
+    ui = ui + (dt / 6.0) * (ku_sum[idx] + ku);
+    ai = ai + (dt / 6.0) * (ka_sum[idx] + ka);
+    u[idx] = ui;
+    a[idx] = ai;
+    nu = ui;
+    na = ai;
+  }
+  vu[idx] = nu;
+  va[idx] = na;
+  g[(int64_t)b * npad + i] = (float)(qd[i] * na * sigmoid(nu, fr.beta, th));
+}
+
 // ------------------------------------------------------------------ W form (FP32)
 
 struct KernelF64 {

@@ -1184,3 +1184,55 @@ int nfr_integrate_ab5(nfr_problem* prob, const nfr_kernel* kernel, const nfr_fir
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- synaptic depression
+
+extern "C" {
+
+size_t nfr_integrate_syndep_workspace_size(const nfr_problem* prob, int B) {
+  if (!prob || B < 1 || B > kMaxB) return 0;
+  return carve(nullptr, prob->view, B, NFR_FORM_ONTHEFLY_FP32, true).bytes +
+         2 * align256(size_t(prob->view.n) * B * sizeof(double));
+}
+
+int nfr_integrate_syndep(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, double* u_dev,
+                         double* a_dev, double tau, double beta_d, double dt, int64_t steps, void* ws_dev,
+                         size_t ws_bytes) {
+  int st;
+  if ((st = check_problem(prob)) || (st = check_kernel(kernel)) || (st = check_firing(firing))) return st;
+  if (B < 1 || B > kMaxB) return fail(NFR_ERR_INVALID_ARG, "B = %d outside [1, %d]", B, kMaxB);
+  if (!u_dev || !a_dev) return fail(NFR_ERR_INVALID_ARG, "NULL state pointer");
+  if (!is_finite_d(dt) || !is_finite_d(tau) || !is_finite_d(beta_d)) return fail(NFR_ERR_NONFINITE, "dt, tau and beta_d must be finite");
+  if (!(dt > 0.0) || !(tau > 0.0)) return fail(NFR_ERR_INVALID_ARG, "dt and tau must be > 0");
+  if (beta_d < 0.0) return fail(NFR_ERR_INVALID_ARG, "beta_d must be >= 0");
+  if (steps < 0) return fail(NFR_ERR_INVALID_ARG, "steps must be >= 0");
+  const ProblemView& pv = prob->view;
+  const int form = NFR_FORM_ONTHEFLY_FP32;
+  const Workspace w = carve(ws_dev, pv, B, form, true);
+  const size_t need = nfr_integrate_syndep_workspace_size(prob, B);
+  if (!ws_dev || ws_bytes < need) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  char* extra = static_cast<char*>(ws_dev) + w.bytes;
+  double* va = reinterpret_cast<double*>(extra);
+  double* ka_sum = reinterpret_cast<double*>(extra + align256(size_t(pv.n) * B * sizeof(double)));
+  NFR_HIP(hipSetDevice(prob->ctx->device));
+  hipStream_t s = prob->ctx->stream;
+  const Firing fr = firing_of(*firing);
+  if (steps == 0) return NFR_OK;
+  hipLaunchKernelGGL(k_syndep_prep, dim3((unsigned)ceil_div(pv.npad * (int64_t)B, kWG)), dim3(kWG), 0, s, u_dev, a_dev,
+                     pv.n, pv.npad, B, pv.q, fr, w.g, w.v, va);
+  NFR_HIP_LAUNCH();
+  const int nsplit = nsplit_for(pv, B, form);
+  const int64_t total = pv.n * (int64_t)B;
+  for (int64_t n = 0; n < steps; ++n) {
+    for (int stage = 1; stage <= 4; ++stage) {
+      if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, nullptr, w))) return st;
+      hipLaunchKernelGGL(k_syndep_combine, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
+                         pv.npad, B, stage, dt, 1.0 / tau, beta_d, u_dev, a_dev, w.v, va, w.ksum, ka_sum, pv.q, fr,
+                         w.g);
+      NFR_HIP_LAUNCH();
+    }
+  }
+  return NFR_OK;
+}
+
+}  // extern "C"

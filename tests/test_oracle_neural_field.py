@@ -240,3 +240,47 @@ def test_ab5_beta_zero_matches_companion_matrix():
     state = np.linalg.matrix_power(Cm, steps - 4) @ state
     got = NF.ab5(op, U[:1], 0.0, 0.3, dt, steps)[0]
     np.testing.assert_allclose(got, b + state[0], rtol=1e-11, atol=1e-13)
+
+
+def test_syndep_without_depression_reduces_to_plain_model():
+    """beta_d = 0 and a(0) = 1: the efficacy stays 1 and u follows the plain RK4 exactly."""
+    x, q, U, p = _problem(n=35, seed=6)
+    op = NF.DenseOperator(x, q, NF.GAUSS_MH, p)
+    u, a = NF.syndep_rk4(op, U, np.ones_like(U), 20.0, np.array([0.2, 0.3]), 20.0, 0.0, 0.05, 17)
+    np.testing.assert_array_equal(a, np.ones_like(U))
+    np.testing.assert_allclose(u, NF.rk4(op, U, 20.0, np.array([0.2, 0.3]), 0.05, 17), rtol=1e-14, atol=1e-15)
+
+
+def test_syndep_efficacy_closed_form_at_beta_zero():
+    """beta = 0 (f = 1/2): tau a' = 1 - a (1 + beta_d/2), so the RK4 efficacy is
+    a_n = a* + R(-dt (1 + beta_d/2) / tau)^n (a0 - a*),  a* = 1 / (1 + beta_d/2)."""
+    x, q, U, p = _problem(n=20, seed=7)
+    op = NF.DenseOperator(x, q, NF.EXP_MH, EXPK)
+    rng = np.random.default_rng(1)
+    a0 = rng.uniform(0.2, 1.0, size=U.shape)
+    tau, bd, dt, n = 15.0, 1.3, 0.1, 31
+    _, a = NF.syndep_rk4(op, U, a0, 0.0, 0.2, tau, bd, dt, n)
+    astar = 1.0 / (1.0 + bd / 2.0)
+    R = pins.rk4_amplification(-dt * (1.0 + bd / 2.0) / tau)
+    np.testing.assert_allclose(a, astar + R ** n * (a0 - astar), rtol=1e-13)
+
+
+def test_syndep_fourth_order_against_dop853():
+    s = S.bumpy_sphere(140)
+    q = np.full(140, 4 * math.pi / 140)
+    op = NF.DenseOperator(s.xyz, q, NF.GAUSS_MH, GAUSS)
+    u0 = C.bump(s.xyz, s.xyz[9])[None, :]
+    a0 = np.full_like(u0, 0.9)
+    beta, theta, tau, bd = 20.0, 0.2, 5.0, 2.0
+
+    def fun(_t, y):
+        du, da = NF.syndep_rhs(op, y[:140][None, :], y[140:][None, :], beta, theta, tau, bd)
+        return np.concatenate([du.ravel(), da.ravel()])
+    T = 2.0
+    ref = solve_ivp(fun, (0, T), np.concatenate([u0.ravel(), a0.ravel()]), method="DOP853",
+                    rtol=1e-13, atol=1e-13).y[:, -1]
+    errs = []
+    for dt in (0.1, 0.05, 0.025):
+        u, a = NF.syndep_rk4(op, u0, a0, beta, theta, tau, bd, dt, int(round(T / dt)))
+        errs.append(np.max(np.abs(np.concatenate([u.ravel(), a.ravel()]) - ref)))
+    assert 13 < errs[0] / errs[1] < 19 and 13 < errs[1] / errs[2] < 19

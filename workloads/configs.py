@@ -183,5 +183,22 @@ def torus_adjoint(n: int = 16384, steps: int = 400, ckpt_every: int = 40) -> Wor
     return w
 
 
+def bumpy_syndep(n: int = 20000, steps: int = 200) -> Workload:
+    """Bumpy sphere with synaptic depression (the travelling-spot setting of the
+    paper's section 5.2): the paper's normalised-Gaussian lateral inhibition
+    A_e = 5, A_i = 7, sigma_e = .05, sigma_i = .1 rewritten as A exp(-r^2/s^2)
+    (A = A_paper / (2 pi sigma^2), s = sqrt(2) sigma).  Not given in the paper,
+    chosen here: sigmoid gain 20 and threshold 0.3, tau = 20, beta_d = 1,
+    dt = 0.02, a(0) = 1, one bump of width 0.15 and height 1."""
+    rng = np.random.default_rng(5)
+    surf = S.bumpy_sphere(n)
+    c = surf.xyz[rng.integers(n)]
+    u0 = bump(surf.xyz, c, width=0.15)
+    A_e, A_i, se, si = 5.0, 7.0, 0.05, 0.1
+    kern = (A_e / (2 * math.pi * se * se), math.sqrt(2) * se, A_i / (2 * math.pi * si * si), math.sqrt(2) * si)
+    return Workload("bumpy-syndep-n%d" % n, surf, GAUSS_MH, kern, 20.0, np.array([0.3]), u0[None, :].copy(), 0.02,
+                    steps, extra={"tau": 20.0, "beta_d": 1.0, "a0": np.ones((1, n))})
+
+
 def by_index(k: int, **kw):
     return [sphere_small, torus_exp, ellipsoid_ensemble, uneven_batch, torus_adjoint][k](**kw)
