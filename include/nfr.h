@@ -211,6 +211,16 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
                   double* ckpt_dev, int64_t ckpt_every, int use_graph,
                   void* ws_dev, size_t ws_bytes);
 
+/* RK4 for the forced equation u' = -u + K(u) + gamma(t) (paper eq. NFODETilde
+ * with its forcing term gamma_i(t) = g(t, x_i); used with manufactured
+ * solutions, eq. manufactured_system).  forcing_dev (device, FP64) holds, for
+ * every step n, gamma at t_n, t_n + dt/2 and t_n + dt: layout
+ * [steps][3][B][n].  The workspace is nfr_integrate_workspace_size's; other
+ * arguments as nfr_integrate (no checkpoints, no graph replay). */
+int nfr_integrate_forced(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, double* u_dev,
+                         double dt, int64_t steps, const double* forcing_dev, int form, const void* w_dev,
+                         void* ws_dev, size_t ws_bytes);
+
 /* Adams-Bashforth 5 with fixed step dt for `steps` steps of u' = -u + K(u), the
  * stepper the paper's section 5.1 showcase uses: one operator application per
  * step, u_{n+1} = u_n + dt/720 (1901 F_n - 2774 F_{n-1} + 2616 F_{n-2}

@@ -204,6 +204,20 @@ def syndep_rk4(op: DenseOperator, u0, a0, beta, theta, tau, beta_d, dt, steps):
     return U, A
 
 
+def rk4_forced(op: DenseOperator, u0, beta, theta, dt, steps, gamma):
+    """Classical RK4 for u' = -u + K(u) + gamma(t) (eq. NFODETilde with forcing);
+    gamma(n, c) returns the forcing at t_n + c dt for c in (0, 1/2, 1)."""
+    u = np.array(np.atleast_2d(u0), dtype=np.float64)
+    for n in range(steps):
+        g0, gh, g1 = gamma(n, 0.0), gamma(n, 0.5), gamma(n, 1.0)
+        k1 = op.rhs(u, beta, theta) + g0
+        k2 = op.rhs(u + 0.5 * dt * k1, beta, theta) + gh
+        k3 = op.rhs(u + 0.5 * dt * k2, beta, theta) + gh
+        k4 = op.rhs(u + dt * k3, beta, theta) + g1
+        u = u + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    return u
+
+
 def rk4_rhs_dense(op: DenseOperator, beta, theta):
     """Right-hand side as a plain function of a flat state (for scipy's integrators)."""
     def fun(_t, y):

@@ -77,6 +77,8 @@ def _declare(lib):
         "nfr_adjoint_workspace_size": (c_size_t, [P, c_int64, c_int64]),
         "nfr_adjoint": (c_int, [P, POINTER(NfrKernel), POINTER(NfrFiring), P, c_int64, c_int64, c_double, P, P,
                                 POINTER(c_double), P, c_size_t]),
+        "nfr_integrate_forced": (c_int, [P, POINTER(NfrKernel), POINTER(NfrFiring), c_int, P, c_double, c_int64, P,
+                                         c_int, P, P, c_size_t]),
         "nfr_integrate_ab5_workspace_size": (c_size_t, [P, c_int, c_int]),
         "nfr_integrate_ab5": (c_int, [P, POINTER(NfrKernel), POINTER(NfrFiring), c_int, P, c_double, c_int64, c_int,
                                       P, P, c_size_t]),

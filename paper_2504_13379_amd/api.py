@@ -157,6 +157,20 @@ class Problem:
         self._last_ws = ws
         return ck
 
+    def integrate_forced(self, kernel: L.NfrKernel, firing: Firing, u: torch.Tensor, dt: float, steps: int,
+                         forcing: torch.Tensor, form: int = L.FORM_ONTHEFLY_FP32, W: torch.Tensor | None = None):
+        """RK4 with forcing; forcing is (steps, 3, B, N) float64: gamma at t_n, t_n + dt/2, t_n + dt."""
+        B = self._check_state(u)
+        if tuple(forcing.shape) != (steps, 3, B, self.n) or forcing.dtype != torch.float64:
+            raise ValueError("forcing must be a (steps, 3, B, N) float64 tensor")
+        forcing = forcing.to(self.ctx.device).contiguous()
+        ws_bytes = L.lib().nfr_integrate_workspace_size(self.handle, B, form)
+        ws = _dev_buffer(ws_bytes, self.ctx.device)
+        fs = firing.struct(self.ctx.device)
+        L.check(L.lib().nfr_integrate_forced(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), float(dt),
+                                             int(steps), forcing.data_ptr(), form, _ptr(W), ws.data_ptr(), ws_bytes))
+        self._last_ws = (ws, forcing)
+
     def integrate_ab5(self, kernel: L.NfrKernel, firing: Firing, u: torch.Tensor, dt: float, steps: int,
                       form: int = L.FORM_ONTHEFLY_FP32, W: torch.Tensor | None = None, ws: torch.Tensor | None = None):
         """Advances u in place by `steps` Adams-Bashforth 5 steps (RK4 start-up)."""

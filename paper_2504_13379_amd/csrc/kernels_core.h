@@ -313,20 +313,21 @@ __global__ __launch_bounds__(kWG) void k_reduce_partials(const double* __restric
 //   s=3: ksum += 2k,      v <- u + dt k
 //   s=4: u <- u + dt/6 (ksum + k),  v <- u
 // then g[b*npad + i] = s_i f_b(v) for the next stage (s_i = q_i or 1).
-// k1_out (may be null) receives k_1 = F(u_n) at stage 1 (the Adams-Bashforth start-up records it).
+// k1_out (may be null) receives k_1 = F(u_n) at stage 1 (the Adams-Bashforth start-up records it);
+// gamma (may be null) is a forcing term added to k (B x n, at this stage's time).
 __global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ part, int nsplit, int64_t n,
                                                      int64_t npad, int B, int stage, double dt,
                                                      double* __restrict__ u, double* __restrict__ v,
                                                      double* __restrict__ ksum, const double* __restrict__ qd,
                                                      int with_q, Firing fr, float* __restrict__ g,
-                                                     double* __restrict__ k1_out) {
+                                                     double* __restrict__ k1_out, const double* __restrict__ gamma) {
   const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (idx >= n * (int64_t)B) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
   double y = 0.0;
   for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
-  const double k = -v[idx] + y;
+  const double k = -v[idx] + y + (gamma ? gamma[idx] : 0.0);
   double ui = u[idx];
   double vn;
   if (stage == 1) {

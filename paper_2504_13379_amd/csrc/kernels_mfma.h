@@ -299,14 +299,15 @@ __global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__
                                                       int64_t npad, int B, int stage, double dt,
                                                       double* __restrict__ u, double* __restrict__ v,
                                                       double* __restrict__ ksum, Firing fr, T* __restrict__ Ghi,
-                                                      T* __restrict__ Glo, double* __restrict__ k1_out) {
+                                                      T* __restrict__ Glo, double* __restrict__ k1_out,
+                                                      const double* __restrict__ gamma) {
   const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (idx >= n * (int64_t)B) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
   double y = 0.0;
   for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
-  const double k = -v[idx] + y;
+  const double k = -v[idx] + y + (gamma ? gamma[idx] : 0.0);
   double ui = u[idx];
   double vn;
   if (stage == 1) {
@@ -447,21 +448,22 @@ inline void launch_mfma_apply(const ProblemView& pv, int form, int B, const void
 template <typename T>
 inline void launch_mfma_combine_t(const ProblemView& pv, int B, int stage, double dt, double* u, double* v,
                                   double* ksum, const double* part, int nsplit, const Firing& fr, void* g,
-                                  double* k1_out, hipStream_t s) {
+                                  double* k1_out, const double* gamma, hipStream_t s) {
   void *ghi, *glo;
   mfma_g_split(g, pv.npad, B, &ghi, &glo);
   const int64_t total = pv.n * (int64_t)B;
   hipLaunchKernelGGL(k_mfma_combine<T>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit, pv.n,
-                     pv.npad, B, stage, dt, u, v, ksum, fr, static_cast<T*>(ghi), static_cast<T*>(glo), k1_out);
+                     pv.npad, B, stage, dt, u, v, ksum, fr, static_cast<T*>(ghi), static_cast<T*>(glo), k1_out,
+                     gamma);
 }
 
 inline void launch_mfma_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, double* v,
                                 double* ksum, const double* part, int nsplit, const Firing& fr, float* g,
-                                double* k1_out, hipStream_t s) {
+                                double* k1_out, const double* gamma, hipStream_t s) {
   if (form == 2)
-    launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, s);
+    launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, gamma, s);
   else
-    launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, s);
+    launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, gamma, s);
 }
 
 template <typename T>

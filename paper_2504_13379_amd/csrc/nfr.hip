@@ -292,15 +292,15 @@ int launch_pairs(nfr_context* ctx, const ProblemView& pv, const nfr_kernel& k, i
 }
 
 int launch_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, const Workspace& w,
-                   const Firing& fr, hipStream_t s, double* k1_out = nullptr) {
+                   const Firing& fr, hipStream_t s, double* k1_out = nullptr, const double* gamma = nullptr) {
   const int nsplit = nsplit_for(pv, B, form);
   const int64_t total = pv.n * (int64_t)B;
   if (is_mfma_form(form)) {
-    launch_mfma_combine(pv, form, B, stage, dt, u, w.v, w.ksum, w.part, nsplit, fr, w.g, k1_out, s);
+    launch_mfma_combine(pv, form, B, stage, dt, u, w.v, w.ksum, w.part, nsplit, fr, w.g, k1_out, gamma, s);
   } else {
     const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
     hipLaunchKernelGGL(k_rk4_combine, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
-                       pv.npad, B, stage, dt, u, w.v, w.ksum, pv.q, with_q, fr, w.g, k1_out);
+                       pv.npad, B, stage, dt, u, w.v, w.ksum, pv.q, with_q, fr, w.g, k1_out, gamma);
   }
   NFR_HIP_LAUNCH();
   return NFR_OK;
@@ -1230,6 +1230,45 @@ int nfr_integrate_syndep(nfr_problem* prob, const nfr_kernel* kernel, const nfr_
                          pv.npad, B, stage, dt, 1.0 / tau, beta_d, u_dev, a_dev, w.v, va, w.ksum, ka_sum, pv.q, fr,
                          w.g);
       NFR_HIP_LAUNCH();
+    }
+  }
+  return NFR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- forcing
+
+extern "C" {
+
+int nfr_integrate_forced(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, double* u_dev,
+                         double dt, int64_t steps, const double* forcing_dev, int form, const void* w_dev,
+                         void* ws_dev, size_t ws_bytes) {
+  int st;
+  if ((st = check_problem(prob)) || (st = check_kernel(kernel)) || (st = check_firing(firing)) || (st = check_form(form)))
+    return st;
+  if (B < 1 || B > kMaxB) return fail(NFR_ERR_INVALID_ARG, "B = %d outside [1, %d]", B, kMaxB);
+  if (!u_dev || !forcing_dev) return fail(NFR_ERR_INVALID_ARG, "NULL device pointer");
+  if (!is_finite_d(dt)) return fail(NFR_ERR_NONFINITE, "dt must be finite");
+  if (!(dt > 0.0)) return fail(NFR_ERR_INVALID_ARG, "dt must be > 0");
+  if (steps < 0) return fail(NFR_ERR_INVALID_ARG, "steps must be >= 0");
+  const ProblemView& pv = prob->view;
+  form = resolve_form(form, pv.n, B);
+  if ((st = check_w(prob, form, w_dev))) return st;
+  const Workspace w = carve(ws_dev, pv, B, form, true);
+  if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
+  NFR_HIP(hipSetDevice(prob->ctx->device));
+  hipStream_t s = prob->ctx->stream;
+  const Firing fr = firing_of(*firing);
+  if (steps == 0) return NFR_OK;
+  if ((st = launch_prep(pv, form, B, u_dev, fr, w, w.v, s))) return st;
+  const int64_t nb = pv.n * (int64_t)B;
+  static const int slot_of_stage[5] = {0, 0, 1, 1, 2};
+  for (int64_t n = 0; n < steps; ++n) {
+    for (int stage = 1; stage <= 4; ++stage) {
+      if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return st;
+      const double* gam = forcing_dev + (n * 3 + slot_of_stage[stage]) * nb;
+      if ((st = launch_combine(pv, form, B, stage, dt, u_dev, w, fr, s, nullptr, gam))) return st;
     }
   }
   return NFR_OK;

@@ -284,3 +284,26 @@ def test_syndep_fourth_order_against_dop853():
         u, a = NF.syndep_rk4(op, u0, a0, beta, theta, tau, bd, dt, int(round(T / dt)))
         errs.append(np.max(np.abs(np.concatenate([u.ravel(), a.ravel()]) - ref)))
     assert 13 < errs[0] / errs[1] < 19 and 13 < errs[1] / errs[2] < 19
+
+
+def test_funk_hecke_constant_matches_closed_form():
+    from workloads import mms
+    for kind, p in ((NF.GAUSS_MH, GAUSS), (NF.EXP_MH, EXPK)):
+        assert abs(mms.funk_hecke(kind, p, 0) - pins.sphere_kernel_integral(kind, p)) < 1e-11
+
+
+def test_manufactured_solution_converges_with_quadrature():
+    """The forced discrete system reproduces the manufactured solution; its error
+    (quadrature of the operator + RK4) falls >= 4x from N = 1000 to 4000."""
+    from workloads import mms
+    errs = []
+    for n in (1000, 4000):
+        m = mms.SphereMMS(n)
+        q = Q.surface_weights(m.surface)
+        op = NF.DenseOperator(m.surface.xyz, q, m.kind, m.kernel)
+        dt, steps = 0.02, 25
+        F = m.stage_forcing(dt, steps)
+        u = NF.rk4_forced(op, m.u(0.0)[None, :], m.beta, m.theta, dt, steps,
+                          lambda k, c: F[k, {0.0: 0, 0.5: 1, 1.0: 2}[c]])
+        errs.append(np.max(np.abs(u[0] - m.u(dt * steps))) / np.max(np.abs(m.u(dt * steps))))
+    assert errs[1] < errs[0] / 4 and errs[1] < 1e-5, errs
