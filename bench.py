@@ -41,6 +41,26 @@ TRANS_COST = 4.0
 SLOTS_PER_UNORDERED_PAIR = {0: 7 + 2 * TRANS_COST + 4, 1: 7 + 3 * TRANS_COST + 4}
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
+    or None when the HIP sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2504_13379_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("csrc_sha256") or kernel not in rec:
+        return None
+    return rec[kernel]["bytes"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,12 +134,12 @@ def roofline(form_name, res, n, npad):
         bytes_per_launch = float(n) * npad * 4.0          # every W element once per application
         ach = bytes_per_launch / avg_s
         return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": ach / HBM_PEAK, "traffic": None, "kernel": "k_w_gemv_f32<1>"}
+                "frac": ach / HBM_PEAK, "traffic": measured_traffic("k_w_gemv_f32<1>"), "kernel": "k_w_gemv_f32<1>"}
     # on-the-fly (exponential kernel): slots per unordered pair x npad^2 / 2 pairs per launch
     ops = SLOTS_PER_UNORDERED_PAIR[1] * float(npad) * npad / 2.0
     ach = ops / avg_s
     return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tlane-op/s",
-            "frac": ach / VALU_LANES_PER_S, "traffic": None, "kernel": "k_otf_sym<1>"}
+            "frac": ach / VALU_LANES_PER_S, "traffic": measured_traffic("k_otf_sym<1>"), "kernel": "k_otf_sym<1>"}
 
 
 def ensemble_leg(P, torch, args):
@@ -168,8 +188,10 @@ def ensemble_leg(P, torch, args):
                  "w_build_ms": t_build * 1e3, "kernel_avg_ms": avg * 1e3}
         if W is not None:
             wbytes = 2.0 * 2 * prob.npad * prob.npad     # hi + lo, 2 bytes each, every element once
+            kname = "k_mfma_apply<%s,2>" % ("bf16" if nm == "bf16x3" else "fp16")
             entry["roofline"] = {"bound": "hbm", "achieved": wbytes / avg / 1e9, "peak": HBM_PEAK / 1e9,
-                                 "unit": "GB/s", "frac": wbytes / avg / HBM_PEAK}
+                                 "unit": "GB/s", "frac": wbytes / avg / HBM_PEAK,
+                                 "traffic": measured_traffic(kname), "kernel": kname}
         out[nm] = entry
         finals[nm] = u.cpu().numpy()
         del W
