@@ -8,7 +8,9 @@ What it computes (paper section 2.2, eq. NFODETilde, without forcing):
     u_i'(t) = -u_i + K_i(u),     K_i(u) = sum_j w(|x_i - x_j|) q_j f(u_j),
 
 with q the quadrature weights, the sum over every node j including j = i, and
-chordal (Euclidean R^3) distance.  Kernels are Mexican hats
+chordal (Euclidean R^3) distance; or, on the flat domains of the paper's
+section 4, the doubly periodic distance of eq. dist (period L in x and in y):
+the smallest Euclidean length of x - y + L (i, j, 0) over i, j in {-1, 0, 1}.  Kernels are Mexican hats
 
     Gaussian:     w(r) = A_e exp(-r^2 / s_e^2) - A_i exp(-r^2 / s_i^2)
     exponential:  w(r) = A_e exp(-r / s_e)     - A_i exp(-r / s_i)
@@ -72,9 +74,22 @@ def firing_prime(u: np.ndarray, beta: float, theta) -> np.ndarray:
     return beta * f * (1.0 - f)
 
 
-def distances(x: np.ndarray, rows) -> np.ndarray:
-    d = x[rows, None, :] - x[None, :, :]
-    return np.sqrt(np.sum(d * d, axis=2))
+def distances(x: np.ndarray, rows, period=None) -> np.ndarray:
+    """|x_i - x_j| for i in rows, every j; with a period L, eq. dist: the minimum
+    over the nine lattice shifts L (i, j, 0), i, j in {-1, 0, 1}."""
+    if not period:
+        d = x[rows, None, :] - x[None, :, :]
+        return np.sqrt(np.sum(d * d, axis=2))
+    dx = x[rows, None, 0] - x[None, :, 0]
+    dy = x[rows, None, 1] - x[None, :, 1]
+    dz = x[rows, None, 2] - x[None, :, 2]
+    sx = [(dx + i * period) ** 2 for i in (-1, 0, 1)]
+    sy = [(dy + j * period) ** 2 for j in (-1, 0, 1)]
+    best = None
+    for a in sx:
+        for b in sy:
+            best = a + b if best is None else np.minimum(best, a + b)
+    return np.sqrt(best + dz * dz)
 
 
 def _panels(n_rows: int, n_cols: int):
@@ -83,16 +98,16 @@ def _panels(n_rows: int, n_cols: int):
         yield lo, min(n_rows, lo + step)
 
 
-def kernel_matrix(x: np.ndarray, kind: int, p, rows=None) -> np.ndarray:
+def kernel_matrix(x: np.ndarray, kind: int, p, rows=None, period=None) -> np.ndarray:
     """w(|x_i - x_j|) for i in rows (default: all), every j."""
     rows = np.arange(x.shape[0]) if rows is None else np.asarray(rows)
     out = np.empty((rows.size, x.shape[0]))
     for lo, hi in _panels(rows.size, x.shape[0]):
-        out[lo:hi] = kernel_w(kind, distances(x, rows[lo:hi]), p)
+        out[lo:hi] = kernel_w(kind, distances(x, rows[lo:hi], period), p)
     return out
 
 
-def apply_K(x, q, U, kind, p, beta, theta, rows=None) -> np.ndarray:
+def apply_K(x, q, U, kind, p, beta, theta, rows=None, period=None) -> np.ndarray:
     """K(U) at target rows: sum_j w(|x_i - x_j|) q_j f_b(U[b, j]); shape (B, len(rows)).
 
     Computed panel by panel from the definition (no stored matrix).
@@ -102,7 +117,7 @@ def apply_K(x, q, U, kind, p, beta, theta, rows=None) -> np.ndarray:
     G = q[None, :] * firing(U, beta, theta)          # (B, N)
     out = np.empty((U.shape[0], rows.size))
     for lo, hi in _panels(rows.size, x.shape[0]):
-        Wp = kernel_w(kind, distances(x, rows[lo:hi]), p)
+        Wp = kernel_w(kind, distances(x, rows[lo:hi], period), p)
         out[:, lo:hi] = G @ Wp.T
     return out
 
@@ -110,11 +125,12 @@ def apply_K(x, q, U, kind, p, beta, theta, rows=None) -> np.ndarray:
 class DenseOperator:
     """K with the kernel matrix w_ij stored once (FP64, N x N)."""
 
-    def __init__(self, x, q, kind, p):
+    def __init__(self, x, q, kind, p, period=None):
         self.x = np.asarray(x, dtype=np.float64)
         self.q = np.asarray(q, dtype=np.float64)
         self.kind, self.p = kind, tuple(float(v) for v in p)
-        self.w = kernel_matrix(self.x, kind, self.p)
+        self.period = period
+        self.w = kernel_matrix(self.x, kind, self.p, period=period)
 
     @property
     def n(self):
@@ -231,9 +247,9 @@ def rk4_rhs_dense(op: DenseOperator, beta, theta):
 class ParamOperator(DenseOperator):
     """DenseOperator plus the four kernel-derivative matrices dw/dp."""
 
-    def __init__(self, x, q, kind, p):
-        super().__init__(x, q, kind, p)
-        r = distances(self.x, np.arange(self.n))
+    def __init__(self, x, q, kind, p, period=None):
+        super().__init__(x, q, kind, p, period)
+        r = distances(self.x, np.arange(self.n), period)
         self.dw = kernel_dw(kind, r, self.p)      # (4, N, N)
 
 
@@ -284,12 +300,12 @@ def adjoint_gradients(op: ParamOperator, u0, beta, theta, dt, steps, target):
     return L, ubar, pbar
 
 
-def _loss_at(x, q, kind, p, u0, beta, theta, dt, steps, target):
-    op = DenseOperator(x, q, kind, p)
+def _loss_at(x, q, kind, p, u0, beta, theta, dt, steps, target, period=None):
+    op = DenseOperator(x, q, kind, p, period)
     return loss(rk4(op, u0, beta, theta, dt, steps), target)
 
 
-def fd_param_gradients(x, q, kind, p, u0, beta, theta, dt, steps, target, h=1e-4, order=2):
+def fd_param_gradients(x, q, kind, p, u0, beta, theta, dt, steps, target, h=1e-4, order=2, period=None):
     """Central finite differences of L in (A_e, s_e, A_i, s_i, theta), absolute step h."""
     base = np.array(list(p) + [theta], dtype=np.float64)
     out = np.zeros(5)
@@ -297,7 +313,7 @@ def fd_param_gradients(x, q, kind, p, u0, beta, theta, dt, steps, target, h=1e-4
         def L_at(delta):
             v = base.copy()
             v[m] += delta
-            return _loss_at(x, q, kind, tuple(v[:4]), u0, beta, v[4], dt, steps, target)
+            return _loss_at(x, q, kind, tuple(v[:4]), u0, beta, v[4], dt, steps, target, period)
         if order == 2:
             out[m] = (L_at(h) - L_at(-h)) / (2 * h)
         else:
@@ -306,8 +322,8 @@ def fd_param_gradients(x, q, kind, p, u0, beta, theta, dt, steps, target, h=1e-4
 
 
 def fd_u0_directional(x, q, kind, p, u0, beta, theta, dt, steps, target, direction,
-                      h=1e-4, order=2):
-    op = DenseOperator(x, q, kind, p)
+                      h=1e-4, order=2, period=None):
+    op = DenseOperator(x, q, kind, p, period)
 
     def L_at(delta):
         return loss(rk4(op, u0 + delta * direction, beta, theta, dt, steps), target)

@@ -34,13 +34,17 @@ Readings where the paper is silent or garbled:
 * the Jacobian that eq. integral carries is applied to the planar weights,
   evaluated at each stencil node's pre-image;
 * stencil ties are broken by (distance, index).
+
+Flat domains (the squares of the paper's section 4) use the planar rule of
+section 3.2 directly: a Delaunay triangulation of the nodes, the same stencils
+and element weights, no projection and no Jacobian.
 """
 from __future__ import annotations
 
 import math
 
 import numpy as np
-from scipy.spatial import ConvexHull, cKDTree
+from scipy.spatial import ConvexHull, Delaunay, cKDTree
 
 # ------------------------------------------------------------- triangulation
 
@@ -348,4 +352,42 @@ def surface_weights(surface, k: int = 32, deg: int = 2, chunk: int = 8192,
     if return_info:
         return q, {"triangles": m, "orthogonal_fallbacks": n_orth, "min_cos": min_cos,
                    "tris": tris}
+    return q
+
+
+def plane_weights(xy: np.ndarray, k: int = 32, chunk: int = 8192, return_info: bool = False):
+    """Planar RBF-QF weights (paper section 3.2, eq. functional_stencil) for a
+    convex planar domain covered by the Delaunay triangulation of its nodes.
+
+    xy: (N, 2) nodes (or (N, 3) with the plane z = const).  Per triangle E_j
+    the stencil is the k nodes nearest to its centroid c_j; in coordinates
+    (x - c_j) / h_j, h_j the stencil radius, the weights solve
+      [A  Pi; Pi^T 0] [w; gamma] = [int_E r^3 ; int_E pi]
+    and w_r h_j^2 is added to q at stencil node r.  Triangles with area below
+    1e-14 of the domain's bounding box (collinear boundary nodes) are dropped.
+    """
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64)[:, :2])
+    n = xy.shape[0]
+    if k < 6:
+        raise ValueError("stencil too small: k >= 6 is required for degree 2")
+    tris = Delaunay(xy).simplices
+    a, b, c = xy[tris[:, 0]], xy[tris[:, 1]], xy[tris[:, 2]]
+    area = 0.5 * np.abs((b - a)[:, 0] * (c - a)[:, 1] - (b - a)[:, 1] * (c - a)[:, 0])
+    box = np.prod(xy.max(axis=0) - xy.min(axis=0))
+    keep = area > 1e-14 * box
+    tris, a, b, c = tris[keep], a[keep], b[keep], c[keep]
+    m = tris.shape[0]
+    cen = (a + b + c) / 3.0
+    st = stencils(xy, cen, k)
+    q = np.zeros(n)
+    for lo in range(0, m, chunk):
+        sl = slice(lo, min(m, lo + chunk))
+        rel = xy[st[sl]] - cen[sl][:, None, :]
+        h = np.max(np.linalg.norm(rel, axis=2), axis=1)
+        s2 = rel / h[:, None, None]
+        verts = [(v[sl] - cen[sl]) / h[:, None] for v in (a, b, c)]
+        w = planar_element_weights(s2, verts[0], verts[1], verts[2]) * (h * h)[:, None]
+        q += np.bincount(st[sl].ravel(), weights=w.ravel(), minlength=n)
+    if return_info:
+        return q, {"triangles": m, "tris": tris, "area": float(area[keep].sum())}
     return q

@@ -79,3 +79,73 @@ class SphereMMS:
             out[k, 1, 0] = self.forcing(t + 0.5 * dt)
             out[k, 2, 0] = self.forcing(t + dt)
         return out
+
+
+class FlatMMS:
+    """A manufactured solution on the doubly periodic square [-L/2, L/2]^2 (the
+    flat setting of the paper's section 4, eq. manufactured_system, with the
+    periodic distance of eq. dist and the normalised Gaussian of eq. gauss).
+
+    The firing-rate field is a trigonometric polynomial whose centre circles
+    like the paper's x_0(t) = (cos t / 5, sin t / 5):
+        phi(t, x) = c0 + c1 (1 + cos(x - X(t))) (1 + cos(y - Y(t))),
+    with L = 2 pi.  For the Gaussian Gauss(x, y; sigma) of total mass one, each
+    Fourier mode exp(i k.y) is mapped to exp(-sigma^2 |k|^2 / 2) exp(i k.x)
+    (the part of the Gaussian beyond the half period, exp(-pi^2 / (2 sigma^2)),
+    is below FP64 resolution for sigma <= 1/4), so
+        int w phi dy = c0 + c1 (1 + g1 (cos a + cos b) + g2 cos a cos b),
+        a = x - X, b = y - Y, g1 = exp(-sigma^2 / 2), g2 = exp(-sigma^2).
+    The paper's firing rate has gain 5 and threshold 1/2.  The kernel in the
+    library's form: A_e = 1 / (2 pi sigma^2), s_e = sqrt(2) sigma, A_i = 0.
+    """
+
+    L = 2.0 * math.pi
+
+    def __init__(self, n: int, sigma: float = 0.25, beta: float = 5.0, theta: float = 0.5,
+                 c0: float = 0.1, c1: float = 0.2, rng: np.random.Generator | None = None, jitter: float = 0.0):
+        if sigma > 0.25:
+            raise ValueError("sigma above 1/4: the periodic wrap of the Gaussian is no longer negligible")
+        self.surface = S.flat_square(n, self.L, rng, jitter)
+        self.sigma, self.beta, self.theta, self.c0, self.c1 = sigma, beta, theta, c0, c1
+        self.kind = 0
+        self.kernel = (1.0 / (2.0 * math.pi * sigma * sigma), math.sqrt(2.0) * sigma, 0.0, 1.0)
+        self.g1 = math.exp(-sigma * sigma / 2.0)
+        self.g2 = math.exp(-sigma * sigma)
+        self.x = self.surface.xyz[:, 0]
+        self.y = self.surface.xyz[:, 1]
+
+    @staticmethod
+    def centre(t):
+        return math.cos(t) / 5.0, math.sin(t) / 5.0, -math.sin(t) / 5.0, math.cos(t) / 5.0
+
+    def phi(self, t):
+        X, Y, _, _ = self.centre(t)
+        return self.c0 + self.c1 * (1.0 + np.cos(self.x - X)) * (1.0 + np.cos(self.y - Y))
+
+    def u(self, t):
+        ph = self.phi(t)
+        return self.theta + np.log(ph / (1.0 - ph)) / self.beta
+
+    def K_phi(self, t):
+        """The exact nonlocal term int_D w(dist(x, y)) phi(t, y) dy at the nodes."""
+        X, Y, _, _ = self.centre(t)
+        ca, cb = np.cos(self.x - X), np.cos(self.y - Y)
+        return self.c0 + self.c1 * (1.0 + self.g1 * (ca + cb) + self.g2 * ca * cb)
+
+    def forcing(self, t):
+        X, Y, dX, dY = self.centre(t)
+        a, b = self.x - X, self.y - Y
+        ph = self.phi(t)
+        dph = self.c1 * (np.sin(a) * dX * (1.0 + np.cos(b)) + (1.0 + np.cos(a)) * np.sin(b) * dY)
+        ut = dph / (self.beta * ph * (1.0 - ph))
+        return ut + self.u(t) - self.K_phi(t)
+
+    def stage_forcing(self, dt: float, steps: int) -> np.ndarray:
+        """(steps, 3, 1, N): F at t_n, t_n + dt/2, t_n + dt for each RK4 step."""
+        out = np.empty((steps, 3, 1, self.surface.n))
+        for k in range(steps):
+            t = k * dt
+            out[k, 0, 0] = self.forcing(t)
+            out[k, 1, 0] = self.forcing(t + 0.5 * dt)
+            out[k, 2, 0] = self.forcing(t + dt)
+        return out

@@ -99,6 +99,9 @@ def surface_normal(kind: str, params: dict, x: np.ndarray) -> np.ndarray:
                       k * 14 * uz * (ux * ux - uy * uy)], axis=1)
         g_t = g - np.sum(g * u, axis=1, keepdims=True) * u
         nrm = u - g_t / rad
+    elif kind == "flat":
+        nrm = np.zeros_like(x)
+        nrm[:, 2] = 1.0
     else:
         raise ValueError(kind)
     return nrm / np.linalg.norm(nrm, axis=1, keepdims=True)
@@ -168,6 +171,39 @@ def torus(n: int, rng: np.random.Generator, R: float = 1.0, r: float = 0.4) -> S
     p = {"R": float(R), "r": float(r)}
     return Surface("torus", x, surface_normal("torus", p, x), p, False,
                    ring=ring, angles=np.stack([phi, theta], axis=1))
+
+
+def flat_square(n: int, L: float = 2.0 * math.pi, rng: np.random.Generator | None = None,
+                jitter: float = 0.0) -> Surface:
+    """Nodes on the square [-L/2, L/2]^2 in the plane z = 0 (the flat domains of
+    the paper's section 4): equispaced boundary nodes (corners included) and
+    interior nodes on a near-equilateral triangular lattice, rows offset by half
+    a spacing.  With rng and jitter > 0 every interior node moves by
+    U(-jitter, jitter) of a spacing in x and in y (drawn in that order).
+    The node count is close to n, not equal to it.
+    """
+    c = 2.0 / math.sqrt(3.0)
+    m = (-4.0 + math.sqrt(16.0 + 4.0 * c * n)) / (2.0 * c)      # L / h for ~n nodes
+    nb = max(2, int(round(m)))                                 # boundary segments per side
+    nr = max(1, int(round(m * c)))                             # interior rows
+    nc = max(1, int(round(m)))                                 # interior columns
+    hx, hy = L / nc, L / nr
+    k = np.repeat(np.arange(nr), nc)
+    j = np.tile(np.arange(nc), nr)
+    xi = -L / 2 + (j + 0.25 + 0.5 * (k % 2)) * hx
+    yi = -L / 2 + (k + 0.5) * hy
+    if rng is not None and jitter > 0:
+        xi = xi + rng.uniform(-jitter, jitter, size=xi.size) * hx
+        yi = yi + rng.uniform(-jitter, jitter, size=yi.size) * hy
+    t = -L / 2 + L * np.arange(nb) / nb
+    edge = np.concatenate([np.stack([t, np.full(nb, -L / 2)], 1),          # bottom, left to right
+                           np.stack([np.full(nb, L / 2), t], 1),           # right, bottom to top
+                           np.stack([-t, np.full(nb, L / 2)], 1),          # top, right to left
+                           np.stack([np.full(nb, -L / 2), -t], 1)])        # left, top to bottom
+    xy = np.concatenate([edge, np.stack([xi, yi], 1)])
+    x = np.concatenate([xy, np.zeros((xy.shape[0], 1))], axis=1)
+    p = {"L": float(L), "n_boundary": int(edge.shape[0])}
+    return Surface("flat", x, surface_normal("flat", p, x), p, False)
 
 
 def make_surface(kind: str, n: int, rng: np.random.Generator, **kw) -> Surface:
