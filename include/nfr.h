@@ -158,6 +158,23 @@ size_t nfr_problem_bytes(int64_t n);
  * must stay allocated until nfr_problem_destroy. */
 int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev,
                        void* pack_dev, size_t pack_bytes, nfr_problem** out);
+
+/* As nfr_problem_create, for a node set on a doubly periodic plane: the flat
+ * domains of the paper's section 4 with the distance of eq. dist, the length
+ * of x - y + L (i, j, 0) minimised over i, j in {-1, 0, 1}, L = `period`.
+ * Every pair kernel, W build and adjoint of this problem then uses that
+ * distance; z enters unchanged (the paper's flat domains have z = 0).  The
+ * packed x and y are reduced by whole periods to [-L/2, L/2] (the same points
+ * of the periodic plane), so the nine shifts find the nearest image for any
+ * input coordinates.  period = 0 is nfr_problem_create; period < 0 or
+ * non-finite is NFR_ERR_INVALID_ARG / NFR_ERR_NONFINITE.  Distances are
+ * evaluated in FP32 from FP32 coordinates on the on-the-fly path, so the
+ * rounding of a coordinate is about L 2^-25: keep L / s_e moderate (the
+ * kernel's relative error grows like (r / s_e) (L / s_e) 2^-24). */
+int nfr_problem_create_periodic(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev,
+                                double period, void* pack_dev, size_t pack_bytes, nfr_problem** out);
+/* The period of a problem (0: not periodic; -1 for NULL). */
+double nfr_problem_period(const nfr_problem* prob);
 int nfr_problem_destroy(nfr_problem* prob);
 int64_t nfr_problem_n(const nfr_problem* prob);
 /* Padded node count (multiple of 256): the row stride of a W matrix. */

@@ -62,6 +62,8 @@ def _declare(lib):
         "nfr_probe": (c_int, [P, c_int, c_int64, P, c_size_t, POINTER(c_double)]),
         "nfr_problem_bytes": (c_size_t, [c_int64]),
         "nfr_problem_create": (c_int, [P, c_int64, P, P, P, c_size_t, POINTER(P)]),
+        "nfr_problem_create_periodic": (c_int, [P, c_int64, P, P, c_double, P, c_size_t, POINTER(P)]),
+        "nfr_problem_period": (c_double, [P]),
         "nfr_problem_destroy": (c_int, [P]),
         "nfr_problem_n": (c_int64, [P]),
         "nfr_problem_npad": (c_int64, [P]),

@@ -76,9 +76,10 @@ class Context:
 
 
 class Problem:
-    """Packed node set: xyz (N, 3) and q (N,) float64 CUDA tensors."""
+    """Packed node set: xyz (N, 3) and q (N,) float64 CUDA tensors.  With
+    period L > 0 the (x, y) plane is doubly periodic (nfr_problem_create_periodic)."""
 
-    def __init__(self, ctx: Context, xyz: torch.Tensor, q: torch.Tensor):
+    def __init__(self, ctx: Context, xyz: torch.Tensor, q: torch.Tensor, period: float = 0.0):
         if xyz.dim() != 2 or xyz.shape[1] != 3 or q.shape != (xyz.shape[0],):
             raise ValueError("xyz must be (N, 3) and q (N,)")
         self.ctx = ctx
@@ -91,11 +92,12 @@ class Problem:
         self.pack = _dev_buffer(nbytes, ctx.device)
         h = c_void_p()
         with torch.cuda.stream(ctx.stream):
-            L.check(L.lib().nfr_problem_create(ctx.handle, self.n, xyz.data_ptr(), q.data_ptr(),
-                                               self.pack.data_ptr(), nbytes, byref(h)))
+            L.check(L.lib().nfr_problem_create_periodic(ctx.handle, self.n, xyz.data_ptr(), q.data_ptr(),
+                                                        float(period), self.pack.data_ptr(), nbytes, byref(h)))
         self._keep = (xyz, q)            # the pack kernel reads them asynchronously
         self.handle = h
         self.npad = int(L.lib().nfr_problem_npad(h))
+        self.period = float(L.lib().nfr_problem_period(h))
 
     def close(self):
         if self.handle:

@@ -16,8 +16,12 @@ constexpr double kLog2e = 1.4426950408889634074;
 //   float4 src[npad]   (x, y, z, 0) in FP32
 //   double q[npad]     quadrature weights, 0 on padding nodes
 //   double xyz[3*npad] FP64 coordinates (row-major), 0 on padding nodes
+// A periodic problem (period > 0) has its (x, y) plane doubly periodic with
+// that period (the flat domains of the paper's section 4, eq. dist); its x and
+// y are stored reduced to [-period/2, period/2].
 struct ProblemView {
   int64_t n = 0, npad = 0;
+  double period = 0.0;
   const float4* src = nullptr;
   const double* q = nullptr;
   const double* xyz = nullptr;
@@ -28,12 +32,32 @@ struct ProblemView {
 //   Gaussian:    t = |sig (x_i - x_j)|^2,  sig = sqrt(log2 e) / s_e,  rho = s_e^2 / s_i^2
 //   exponential: t = |sig (x_i - x_j)|,    sig = log2 e / s_e,        rho = s_e / s_i
 // and the inhibitory one exp2(-rho t); w = A_e exp2(-t) - A_i exp2(-rho t).
+// `per` is the scaled period sig * L of a periodic problem (0 otherwise).
+//
+// Pair kernels take KIND = kernel kind (bit 0: 0 Gaussian, 1 exponential)
+// plus 2 for a periodic problem.
 struct PairParams {
   float sig;
   float rho;
   double Ae;
   double Ai;
+  float per;
 };
+
+// Squared scaled distance of a pair from its coordinate differences.  For a
+// periodic problem both points lie in one period window, so |d| <= per along
+// x and y and the nearest of the lattice images (eq. dist: shifts by -L, 0, L
+// per axis) is at distance min(|d|, per - |d|) along each axis independently.
+template <int KIND>
+__device__ __forceinline__ float pair_r2(float dx, float dy, float dz, float per) {
+  if (KIND & 2) {
+    dx = fabsf(dx);
+    dx = fminf(dx, per - dx);
+    dy = fabsf(dy);
+    dy = fminf(dy, per - dy);
+  }
+  return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
 
 // Sigmoid firing rate; FP64.
 struct Firing {

@@ -64,11 +64,8 @@ __global__ __launch_bounds__(kWG) void k_otf_adjoint(const float4* __restrict__ 
       const float4 s = s_src[jj];
 #pragma unroll
       for (int k = 0; k < kAdjTPT; ++k) {
-        const float dx = xi[k] - s.x;
-        const float dy = yi[k] - s.y;
-        const float dz = zi[k] - s.z;
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float t = (KIND == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+        const float r2 = pair_r2<KIND>(xi[k] - s.x, yi[k] - s.y, zi[k] - s.z, pp.per);
+        const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
         const float e1 = __builtin_amdgcn_exp2f(-t);
         const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
         const float l1 = e1 * s.w;

@@ -17,7 +17,7 @@ struct BatchProblemDev {
   const float4* src;
   const double* q;
   int64_t n, npad;
-  int B, bs, kind, nsplit;
+  int B, bs, kind, nsplit;   // kind: pair-kernel code (kernel kind, + 2 if periodic)
   int64_t chunk;
   PairParams pp;
   Firing fr;
@@ -39,6 +39,15 @@ struct BatchItem {
 
 constexpr int kBatchTPT = 4;
 
+template <int KIND>
+__device__ inline void batch_item(const BatchProblemDev& P, const BatchItem& w, float4* s_src, float (*s_g)[kWG]) {
+  if (P.bs == 1)
+    otf_tile<KIND, kBatchTPT, 1>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb, s_src, s_g);
+  else
+    otf_tile<KIND, kBatchTPT, 4>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 4, s_src,
+                                 s_g);
+}
+
 __global__ __launch_bounds__(kWG) void k_batch_pairs(const BatchProblemDev* __restrict__ probs,
                                                      const BatchItem* __restrict__ items, int nitems) {
   __shared__ float4 s_src[kWG];
@@ -46,18 +55,11 @@ __global__ __launch_bounds__(kWG) void k_batch_pairs(const BatchProblemDev* __re
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const BatchItem w = items[it];
     const BatchProblemDev& P = probs[w.p];
-    if (P.kind == 0) {
-      if (P.bs == 1)
-        otf_tile<0, kBatchTPT, 1>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb, s_src, s_g);
-      else
-        otf_tile<0, kBatchTPT, 4>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 4, s_src,
-                                  s_g);
-    } else {
-      if (P.bs == 1)
-        otf_tile<1, kBatchTPT, 1>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb, s_src, s_g);
-      else
-        otf_tile<1, kBatchTPT, 4>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 4, s_src,
-                                  s_g);
+    switch (P.kind) {
+      case 0: batch_item<0>(P, w, s_src, s_g); break;
+      case 1: batch_item<1>(P, w, s_src, s_g); break;
+      case 2: batch_item<2>(P, w, s_src, s_g); break;
+      default: batch_item<3>(P, w, s_src, s_g); break;
     }
   }
 }

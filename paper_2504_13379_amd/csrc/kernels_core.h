@@ -14,9 +14,11 @@ namespace nfr {
 
 // xyz (n x 3 FP64) and q (n FP64) -> FP32 float4 coordinates, FP64 weights and
 // FP64 coordinates, each padded to npad with zeros (weight 0: padding sources
-// never contribute; padding targets are computed and discarded).
+// never contribute; padding targets are computed and discarded).  With
+// period > 0, x and y are first reduced by whole periods to [-period/2,
+// period/2] (the same points of the periodic plane).
 __global__ __launch_bounds__(kWG) void k_pack(const double* __restrict__ xyz, const double* __restrict__ q,
-                                              int64_t n, int64_t npad, float4* __restrict__ src,
+                                              int64_t n, int64_t npad, double period, float4* __restrict__ src,
                                               double* __restrict__ qd, double* __restrict__ xyz64) {
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (i >= npad) return;
@@ -26,6 +28,10 @@ __global__ __launch_bounds__(kWG) void k_pack(const double* __restrict__ xyz, co
     y = xyz[3 * i + 1];
     z = xyz[3 * i + 2];
     w = q[i];
+    if (period > 0.0) {
+      x -= period * rint(x / period);
+      y -= period * rint(y / period);
+    }
   }
   src[i] = make_float4((float)x, (float)y, (float)z, 0.0f);
   qd[i] = w;
@@ -117,11 +123,8 @@ __device__ inline void otf_tile(const float4* __restrict__ src, const float* __r
       for (int b = 0; b < BS; ++b) gv[b] = s_g[b][jj];
 #pragma unroll
       for (int k = 0; k < TPT; ++k) {
-        const float dx = xi[k] - s.x;
-        const float dy = yi[k] - s.y;
-        const float dz = zi[k] - s.z;
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float t = (KIND == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+        const float r2 = pair_r2<KIND>(xi[k] - s.x, yi[k] - s.y, zi[k] - s.z, pp.per);
+        const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
         const float e1 = __builtin_amdgcn_exp2f(-t);
         const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
 #pragma unroll
@@ -236,11 +239,8 @@ __device__ inline void sym_tile(const float4* __restrict__ src, const float* __r
     for (int step = 0; step < 64; ++step) {
 #pragma unroll
       for (int k = 0; k < kSymTPT; ++k) {
-        const float dx = xi[k] - sx;
-        const float dy = yi[k] - sy;
-        const float dz = zi[k] - sz;
-        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float t = (KIND == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+        const float r2 = pair_r2<KIND>(xi[k] - sx, yi[k] - sy, zi[k] - sz, pp.per);
+        const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
         const float e1 = __builtin_amdgcn_exp2f(-t);
         const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
         ae[k] = fmaf(e1, sg, ae[k]);
@@ -460,7 +460,19 @@ __global__ __launch_bounds__(kWG) void k_syndep_combine(const double* __restrict
 struct KernelF64 {
   int kind;
   double Ae, se, Ai, si;
+  double period;   // > 0: periodic problem (x, y reduced to one period window)
 };
+
+// Squared distance in FP64, with the per-axis nearest image of a periodic problem.
+__device__ inline double pair_r2_64(const KernelF64& k, double dx, double dy, double dz) {
+  if (k.period > 0.0) {
+    dx = fabs(dx);
+    dx = fmin(dx, k.period - dx);
+    dy = fabs(dy);
+    dy = fmin(dy, k.period - dy);
+  }
+  return dx * dx + dy * dy + dz * dz;
+}
 
 __device__ inline double kernel_w64(const KernelF64& k, double r2) {
   if (k.kind == 0) return k.Ae * exp(-r2 / (k.se * k.se)) - k.Ai * exp(-r2 / (k.si * k.si));
@@ -476,10 +488,8 @@ __global__ __launch_bounds__(kWG) void k_w_build_f32(const double* __restrict__ 
   const int64_t i = blockIdx.x;
   const int64_t j = (int64_t)blockIdx.y * kWG + threadIdx.x;
   if (i >= n || j >= npad) return;
-  const double dx = xyz64[3 * i] - xyz64[3 * j];
-  const double dy = xyz64[3 * i + 1] - xyz64[3 * j + 1];
-  const double dz = xyz64[3 * i + 2] - xyz64[3 * j + 2];
-  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double r2 = pair_r2_64(kp, xyz64[3 * i] - xyz64[3 * j], xyz64[3 * i + 1] - xyz64[3 * j + 1],
+                               xyz64[3 * i + 2] - xyz64[3 * j + 2]);
   const double wq = qd[j] == 0.0 ? 0.0 : kernel_w64(kp, r2) * qd[j];
   W[i * npad + j] = (float)wq;
 }

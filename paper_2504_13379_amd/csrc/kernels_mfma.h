@@ -110,10 +110,9 @@ __global__ __launch_bounds__(kWG) void k_mfma_w_build(const double* __restrict__
     const int64_t j = 8 * g + e;
     double wq = 0.0;
     if (i < n && qd[j] != 0.0) {
-      const double dx = xyz64[3 * i] - xyz64[3 * j];
-      const double dy = xyz64[3 * i + 1] - xyz64[3 * j + 1];
-      const double dz = xyz64[3 * i + 2] - xyz64[3 * j + 2];
-      wq = kernel_w64(kp, dx * dx + dy * dy + dz * dz) * qd[j] * scale;
+      const double r2 = pair_r2_64(kp, xyz64[3 * i] - xyz64[3 * j], xyz64[3 * i + 1] - xyz64[3 * j + 1],
+                                   xyz64[3 * i + 2] - xyz64[3 * j + 2]);
+      wq = kernel_w64(kp, r2) * qd[j] * scale;
     }
     split_hi_lo<T>(wq, hi[e], lo[e]);
   }

@@ -94,7 +94,7 @@ int check_form(int form) {
   return NFR_OK;
 }
 
-PairParams pair_params(const nfr_kernel& k) {
+PairParams pair_params(const nfr_kernel& k, const ProblemView& pv) {
   PairParams p;
   if (k.kind == NFR_KERNEL_GAUSS_MH) {
     p.sig = (float)(std::sqrt(kLog2e) / k.s_e);
@@ -105,10 +105,16 @@ PairParams pair_params(const nfr_kernel& k) {
   }
   p.Ae = k.A_e;
   p.Ai = k.A_i;
+  p.per = (float)(pv.period * (double)p.sig);
   return p;
 }
 
-KernelF64 kernel64(const nfr_kernel& k) { return KernelF64{k.kind, k.A_e, k.s_e, k.A_i, k.s_i}; }
+// Template code of the pair kernels: kernel kind, + 2 for a periodic problem.
+int kind_code(const nfr_kernel& k, const ProblemView& pv) { return k.kind + (pv.period > 0.0 ? 2 : 0); }
+
+KernelF64 kernel64(const nfr_kernel& k, const ProblemView& pv) {
+  return KernelF64{k.kind, k.A_e, k.s_e, k.A_i, k.s_i, pv.period};
+}
 
 Firing firing_of(const nfr_firing& f) { return Firing{f.beta, f.theta, f.theta_dev}; }
 
@@ -260,19 +266,23 @@ int timing_mark(nfr_context* ctx) {
 int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B, const void* W, const Workspace& w,
                      hipStream_t s) {
   if (use_sym(form, B)) {
-    const PairParams pp = pair_params(k);
-    const unsigned grid = (unsigned)sym_pairs(sym_tiles(pv.npad));
-    if (k.kind == NFR_KERNEL_GAUSS_MH)
-      hipLaunchKernelGGL(k_otf_sym<0>, dim3(grid), dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part);
-    else
-      hipLaunchKernelGGL(k_otf_sym<1>, dim3(grid), dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part);
+    const PairParams pp = pair_params(k, pv);
+    const dim3 grid((unsigned)sym_pairs(sym_tiles(pv.npad)));
+    switch (kind_code(k, pv)) {
+      case 0: hipLaunchKernelGGL(k_otf_sym<0>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
+      case 1: hipLaunchKernelGGL(k_otf_sym<1>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
+      case 2: hipLaunchKernelGGL(k_otf_sym<2>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
+      default: hipLaunchKernelGGL(k_otf_sym<3>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
+    }
   } else if (form == NFR_FORM_ONTHEFLY_FP32) {
     const OtfPlan pl = plan_otf(pv.npad, B);
-    const PairParams pp = pair_params(k);
-    if (k.kind == NFR_KERNEL_GAUSS_MH)
-      launch_otf_kind<0>(pv, pp, B, w.g, w.part, pl, s);
-    else
-      launch_otf_kind<1>(pv, pp, B, w.g, w.part, pl, s);
+    const PairParams pp = pair_params(k, pv);
+    switch (kind_code(k, pv)) {
+      case 0: launch_otf_kind<0>(pv, pp, B, w.g, w.part, pl, s); break;
+      case 1: launch_otf_kind<1>(pv, pp, B, w.g, w.part, pl, s); break;
+      case 2: launch_otf_kind<2>(pv, pp, B, w.g, w.part, pl, s); break;
+      default: launch_otf_kind<3>(pv, pp, B, w.g, w.part, pl, s); break;
+    }
   } else if (form == NFR_FORM_W_FP32) {
     launch_gemv(pv, static_cast<const float*>(W), B, w.g, w.part, plan_gemv(pv.n, pv.npad, B), s);
   } else {
@@ -480,10 +490,12 @@ size_t nfr_problem_bytes(int64_t n) {
   return align256(npad * sizeof(float4)) + align256(npad * sizeof(double)) + align256(3 * npad * sizeof(double));
 }
 
-int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev, void* pack_dev,
-                       size_t pack_bytes, nfr_problem** out) {
+int nfr_problem_create_periodic(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev,
+                                double period, void* pack_dev, size_t pack_bytes, nfr_problem** out) {
   if (!out) return fail(NFR_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
+  if (!is_finite_d(period)) return fail(NFR_ERR_NONFINITE, "period must be finite");
+  if (period < 0.0) return fail(NFR_ERR_INVALID_ARG, "period must be >= 0 (0: no periodicity)");
   if (!ctx) return fail(NFR_ERR_INVALID_ARG, "context is NULL");
   if (n < 1 || n > kMaxN) return fail(NFR_ERR_INVALID_ARG, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxN);
   if (!xyz_dev || !q_dev || !pack_dev) return fail(NFR_ERR_INVALID_ARG, "NULL device pointer");
@@ -499,10 +511,11 @@ int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const
   p->pack = pack_dev;
   p->view.n = n;
   p->view.npad = npad;
+  p->view.period = period;
   p->view.src = reinterpret_cast<const float4*>(base);
   p->view.q = reinterpret_cast<const double*>(base + align256(npad * sizeof(float4)));
   p->view.xyz = reinterpret_cast<const double*>(base + align256(npad * sizeof(float4)) + align256(npad * sizeof(double)));
-  hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, ctx->stream, xyz_dev, q_dev, n, npad,
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, ctx->stream, xyz_dev, q_dev, n, npad, period,
                      const_cast<float4*>(p->view.src), const_cast<double*>(p->view.q), const_cast<double*>(p->view.xyz));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -512,6 +525,13 @@ int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const
   *out = p;
   return NFR_OK;
 }
+
+int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev, void* pack_dev,
+                       size_t pack_bytes, nfr_problem** out) {
+  return nfr_problem_create_periodic(ctx, n, xyz_dev, q_dev, 0.0, pack_dev, pack_bytes, out);
+}
+
+double nfr_problem_period(const nfr_problem* prob) { return prob ? prob->view.period : -1.0; }
 
 int nfr_problem_destroy(nfr_problem* prob) {
   delete prob;
@@ -543,9 +563,9 @@ int nfr_w_build(nfr_problem* prob, const nfr_kernel* kernel, int form, void* w_d
   hipStream_t s = prob->ctx->stream;
   if (form == NFR_FORM_W_FP32) {
     hipLaunchKernelGGL(k_w_build_f32, dim3((unsigned)pv.n, (unsigned)ceil_div(pv.npad, kWG)), dim3(kWG), 0, s, pv.xyz,
-                       pv.q, pv.n, pv.npad, kernel64(*kernel), static_cast<float*>(w_dev));
+                       pv.q, pv.n, pv.npad, kernel64(*kernel, pv), static_cast<float*>(w_dev));
   } else {
-    launch_mfma_w_build(pv, form, kernel64(*kernel), w_dev, s);
+    launch_mfma_w_build(pv, form, kernel64(*kernel, pv), w_dev, s);
   }
   NFR_HIP_LAUNCH();
   return NFR_OK;
@@ -759,7 +779,7 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
   nfr_context* ctx = prob->ctx;
   hipStream_t s = ctx->stream;
   const Firing fr = firing_of(*firing);
-  const PairParams pp = pair_params(*kernel);
+  const PairParams pp = pair_params(*kernel, pv);
   const AdjCoef co = adj_coef(*kernel);
   const OtfPlan pl = plan_otf(pv.npad, 1);
   const int64_t n = pv.n;
@@ -790,12 +810,13 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
     for (int64_t l = len - 1; l >= 0; --l) {
       for (int stage = 4; stage >= 1; --stage) {
         if ((st = timing_mark(ctx))) return st;
-        if (kernel->kind == NFR_KERNEL_GAUSS_MH)
-          hipLaunchKernelGGL(k_otf_adjoint<0>, dim3((unsigned)pl.tiles, (unsigned)pl.nsplit), dim3(kWG), 0, s, pv.src,
-                             a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart);
-        else
-          hipLaunchKernelGGL(k_otf_adjoint<1>, dim3((unsigned)pl.tiles, (unsigned)pl.nsplit), dim3(kWG), 0, s, pv.src,
-                             a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart);
+        const dim3 agrid((unsigned)pl.tiles, (unsigned)pl.nsplit);
+        switch (kind_code(*kernel, pv)) {
+          case 0: hipLaunchKernelGGL(k_otf_adjoint<0>, agrid, dim3(kWG), 0, s, pv.src, a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart); break;
+          case 1: hipLaunchKernelGGL(k_otf_adjoint<1>, agrid, dim3(kWG), 0, s, pv.src, a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart); break;
+          case 2: hipLaunchKernelGGL(k_otf_adjoint<2>, agrid, dim3(kWG), 0, s, pv.src, a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart); break;
+          default: hipLaunchKernelGGL(k_otf_adjoint<3>, agrid, dim3(kWG), 0, s, pv.src, a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart); break;
+        }
         NFR_HIP_LAUNCH();
         if ((st = timing_mark(ctx))) return st;
         hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)nblocks), dim3(kWG), 0, s, a.apart, pl.nsplit, n, pv.npad,
@@ -889,10 +910,10 @@ void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_
     d.npad = pv.npad;
     d.B = Bp;
     d.bs = Bp == 1 ? 1 : 4;
-    d.kind = b->kernels[p].kind;
+    d.kind = kind_code(b->kernels[p], pv);
     d.chunk = b->chunk;
     d.nsplit = (int)ceil_div(pv.npad, b->chunk);
-    d.pp = pair_params(b->kernels[p]);
+    d.pp = pair_params(b->kernels[p], pv);
     d.fr = firing_of(b->firings[p]);
     d.g = reinterpret_cast<float*>(ws + L.g_off[p]);
     d.part = reinterpret_cast<double*>(ws + L.part_off[p]);
@@ -911,7 +932,7 @@ void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_
           const double tg = (double)std::min<int64_t>(kWG * kBatchTPT, pv.npad - t * kWG * kBatchTPT);
           const double sc = (double)std::min<int64_t>(b->chunk, pv.npad - sp * b->chunk);
           const double st = (double)std::min(d.bs, Bp - sb * d.bs);
-          const double per_pair = (d.kind == NFR_KERNEL_EXP_MH ? 1.3 : 1.0) + 0.25 * (st - 1.0);
+          const double per_pair = ((d.kind & 1) ? 1.3 : 1.0) + ((d.kind & 2) ? 0.2 : 0.0) + 0.25 * (st - 1.0);
           b->items.push_back(BatchItem{p, (int)t, sp, sb});
           cost.push_back(tg * sc * per_pair);
         }

@@ -63,6 +63,18 @@ def test_null_arguments_rejected_before_device_work(L):
     assert L.nfr_problem_create(None, 10, None, None, None, 0, ctypes.byref(out)) == _lib.NFR_ERR_INVALID_ARG
 
 
+def test_periodic_problem_rejects_bad_period(L):
+    from paper_2504_13379_amd import _lib
+    out = ctypes.c_void_p()
+    st = L.nfr_problem_create_periodic(None, 10, None, None, -1.0, None, 0, ctypes.byref(out))
+    assert st == _lib.NFR_ERR_INVALID_ARG and b"period" in L.nfr_last_error()
+    st = L.nfr_problem_create_periodic(None, 10, None, None, float("nan"), None, 0, ctypes.byref(out))
+    assert st == _lib.NFR_ERR_NONFINITE
+    st = L.nfr_problem_create_periodic(None, 10, None, None, 6.0, None, 0, ctypes.byref(out))
+    assert st == _lib.NFR_ERR_INVALID_ARG and b"context" in L.nfr_last_error()
+    assert L.nfr_problem_period(None) == -1.0
+
+
 def test_context_without_gpu_reports_no_device(L):
     import torch
     if torch.cuda.is_available():

@@ -1,0 +1,186 @@
+"""GPU parity on the doubly periodic plane (the flat domains of the paper's
+section 4 with the distance of eq. dist) against the FP64 oracle.
+
+Tolerances: as for closed surfaces, |dy_i| <= 1e-5 S_i on the on-the-fly path
+(S_i = sum_j |w_ij q_j f(u_j)|) and 2e-6 S_i for W_FP32.  The periodic case
+adds the FP32 rounding of coordinates up to L/2 = pi: a pair term moves by at
+most about ln2 2 sqrt(2) t^(1/2) (L sig) 2^-24 relative (Gaussian, scaled
+distance t^(1/2) <= 3 where the kernel matters), which for the kernels below
+(L sig <= 13) stays under 5e-6.  Trajectories: u(T) to 1e-5 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import neural_field as NF
+from oracle import quadrature as Q
+from workloads import mms
+from workloads import surfaces as S
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2504_13379_amd")
+
+L = 2.0 * math.pi
+GAUSS_WIDE = (1.0, 0.6, 0.5, 1.2)
+EXP_WIDE = (2.0, 0.5, 1.0, 1.5)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return P.Context(0)
+
+
+def _flat(n, seed):
+    rng = np.random.default_rng(seed)
+    surf = S.flat_square(n, L, rng, 0.3)
+    q = Q.plane_weights(surf.xyz) if surf.n <= 20000 else np.full(surf.n, L * L / surf.n)
+    return surf, q, rng
+
+
+def _apply(ctx, x, q, U, kind, p, beta, theta, form, period=L):
+    prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda(), period=period)
+    assert prob.period == period
+    k = P.kernel_struct(kind, *p)
+    th = torch.from_numpy(np.asarray(theta, dtype=np.float64)).cuda() if np.ndim(theta) else float(theta)
+    W = prob.w_build(k, form) if form != P.FORM_ONTHEFLY_FP32 else None
+    y = prob.apply(k, P.Firing(beta, th), torch.from_numpy(np.ascontiguousarray(U)).cuda(), form=form, W=W)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def _scale(x, q, U, kind, p, beta, theta, rows=None):
+    G = q[None, :] * NF.firing(U, beta, theta)
+    return np.abs(G) @ np.abs(NF.kernel_matrix(x, kind, p, rows=rows, period=L)).T
+
+
+@pytest.mark.parametrize("n,B", [(300, 1), (1000, 1), (1500, 3), (2500, 1)])
+@pytest.mark.parametrize("kind", [NF.GAUSS_MH, NF.EXP_MH])
+@pytest.mark.parametrize("form", [0, 1])
+def test_periodic_apply_matches_oracle(ctx, n, B, kind, form):
+    surf, q, rng = _flat(n, 100 * n + 10 * B + kind)
+    U = rng.normal(0.3, 0.4, size=(B, surf.n))
+    theta = rng.uniform(0.1, 0.4, size=B) if B > 1 else 0.25
+    p = GAUSS_WIDE if kind == NF.GAUSS_MH else EXP_WIDE
+    y = _apply(ctx, surf.xyz, q, U, kind, p, 5.0, theta, form)
+    ref = NF.apply_K(surf.xyz, q, U, kind, p, 5.0, theta, period=L)
+    err = np.max(np.abs(y - ref) / _scale(surf.xyz, q, U, kind, p, 5.0, theta))
+    assert err <= (1e-5 if form == 0 else 2e-6), err
+    # the wrap matters: the open-plane operator is far away
+    open_ref = NF.apply_K(surf.xyz, q, U, kind, p, 5.0, theta)
+    assert np.max(np.abs(open_ref - ref)) > 1e-2 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("form", [2, 3])
+def test_periodic_split_precision_forms(ctx, form):
+    surf, q, rng = _flat(2000, 7 + form)
+    B = 8
+    U = rng.normal(0.3, 0.4, size=(B, surf.n))
+    theta = rng.uniform(0.1, 0.4, size=B)
+    y = _apply(ctx, surf.xyz, q, U, NF.GAUSS_MH, GAUSS_WIDE, 5.0, theta, form)
+    ref = NF.apply_K(surf.xyz, q, U, NF.GAUSS_MH, GAUSS_WIDE, 5.0, theta, period=L)
+    err = np.max(np.abs(y - ref) / _scale(surf.xyz, q, U, NF.GAUSS_MH, GAUSS_WIDE, 5.0, theta))
+    assert err <= 1e-5, err
+
+
+def test_periodic_coordinates_outside_the_window(ctx):
+    """Nodes given anywhere on the lattice (shifted by whole periods) are the
+    same points of the periodic plane: the operator does not change."""
+    surf, q, rng = _flat(1200, 3)
+    U = rng.normal(0.3, 0.4, size=(1, surf.n))
+    shifted = surf.xyz.copy()
+    shifted[:, 0] += L * rng.integers(-3, 4, size=surf.n)
+    shifted[:, 1] += L * rng.integers(-3, 4, size=surf.n)
+    for form in (0, 1):
+        a = _apply(ctx, surf.xyz, q, U, NF.GAUSS_MH, GAUSS_WIDE, 5.0, 0.25, form)
+        b = _apply(ctx, shifted, q, U, NF.GAUSS_MH, GAUSS_WIDE, 5.0, 0.25, form)
+        assert np.max(np.abs(a - b)) <= 1e-6 * np.max(np.abs(a))
+
+
+def test_periodic_apply_large_sampled_rows(ctx):
+    """N ~ 100k on the periodic square (many symmetric tiles and a ragged tail): 48 sampled rows."""
+    surf, q, rng = _flat(100000, 11)
+    U = rng.normal(0.3, 0.4, size=(1, surf.n))
+    y = _apply(ctx, surf.xyz, q, U, NF.GAUSS_MH, GAUSS_WIDE, 5.0, 0.25, 0)
+    rows = rng.choice(surf.n, 48, replace=False)
+    ref = NF.apply_K(surf.xyz, q, U, NF.GAUSS_MH, GAUSS_WIDE, 5.0, 0.25, rows=rows, period=L)
+    sc = _scale(surf.xyz, q, U, NF.GAUSS_MH, GAUSS_WIDE, 5.0, 0.25, rows=rows)
+    assert np.max(np.abs(y[:, rows] - ref) / sc) <= 1e-5
+
+
+@pytest.mark.parametrize("form", [0, 1, 3])
+def test_forced_mms_flat_periodic(ctx, form):
+    m = mms.FlatMMS(4000)
+    q = Q.plane_weights(m.surface.xyz)
+    dt, steps = 0.01, 10
+    F = m.stage_forcing(dt, steps)
+    ref = NF.rk4_forced(NF.DenseOperator(m.surface.xyz, q, m.kind, m.kernel, period=L), m.u(0.0)[None, :],
+                        m.beta, m.theta, dt, steps, lambda k, c: F[k, {0.0: 0, 0.5: 1, 1.0: 2}[c]])
+    prob = P.Problem(ctx, torch.from_numpy(m.surface.xyz).cuda(), torch.from_numpy(q).cuda(), period=L)
+    k = P.kernel_struct(m.kind, *m.kernel)
+    W = prob.w_build(k, form) if form else None
+    u = torch.from_numpy(m.u(0.0)[None, :].copy()).cuda()
+    prob.integrate_forced(k, P.Firing(m.beta, m.theta), u, dt, steps, torch.from_numpy(F).cuda(), form=form, W=W)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    assert np.all(NF.rel_linf(got, ref) <= 1e-5)
+    exact = m.u(dt * steps)
+    oracle_err = np.max(np.abs(ref[0] - exact)) / np.max(np.abs(exact))
+    assert np.max(np.abs(got[0] - exact)) / np.max(np.abs(exact)) <= oracle_err + 1e-5
+
+
+def test_periodic_adjoint_matches_oracle(ctx):
+    surf, q, rng = _flat(600, 21)
+    p = GAUSS_WIDE
+    beta, theta, dt, steps = 5.0, 0.3, 0.05, 12
+    u0 = rng.normal(0.3, 0.3, size=(1, surf.n))
+    tp = np.array(list(p) + [theta]) * (1 + 0.05 * rng.uniform(-1, 1, size=5))
+    target = NF.rk4(NF.DenseOperator(surf.xyz, q, NF.GAUSS_MH, tp[:4], period=L), u0, beta, tp[4], dt, steps)
+    prob = P.Problem(ctx, torch.from_numpy(surf.xyz).cuda(), torch.from_numpy(q).cuda(), period=L)
+    k = P.kernel_struct(NF.GAUSS_MH, *p)
+    f = P.Firing(beta, theta)
+    u = torch.from_numpy(u0.copy()).cuda()
+    ck = prob.integrate(k, f, u, dt, steps, ckpt_every=4)
+    uT = u.cpu().numpy()
+    gu, gp = prob.adjoint(k, f, ck, 4, steps, dt, torch.from_numpy(2.0 * (uT - target)).cuda())
+    gu, gp = gu.cpu().numpy(), gp.numpy()
+    op = NF.ParamOperator(surf.xyz, q, NF.GAUSS_MH, p, period=L)
+    _, gu_ref, gp_ref = NF.adjoint_gradients(op, u0, beta, theta, dt, steps, target)
+    assert np.max(np.abs(gu - gu_ref[0])) <= 1e-4 * np.max(np.abs(gu_ref))
+    floor = 1e-3 * np.max(np.abs(gp_ref))
+    assert np.max(np.abs(gp - gp_ref) / np.maximum(np.abs(gp_ref), floor)) <= 1e-4
+
+
+def test_batch_with_periodic_and_closed_problems(ctx):
+    rng = np.random.default_rng(31)
+    specs = []
+    for kind, n, B, kk in (("flat", 900, 1, 0), ("sphere", 700, 4, 1), ("flat", 1400, 3, 1), ("torus", 500, 1, 0)):
+        if kind == "flat":
+            surf = S.flat_square(n, L, rng, 0.3)
+            q = Q.plane_weights(surf.xyz)
+            kern, per = (GAUSS_WIDE if kk == 0 else EXP_WIDE), L
+        else:
+            surf = S.make_surface(kind, n, rng)
+            q = Q.surface_weights(surf, k=24)
+            kern, per = ((1.0, 0.15, 0.5, 0.4) if kk == 0 else (2.0, 0.1, 1.0, 0.3)), 0.0
+        theta = rng.uniform(0.15, 0.3, size=B)
+        u0 = rng.normal(0.3, 0.3, size=(B, surf.n))
+        specs.append((surf, q, kk, kern, theta, u0, per))
+    dt, steps, beta = 0.05, 8, 5.0
+    probs, ks, fs, Bs, states = [], [], [], [], []
+    with torch.cuda.stream(ctx.stream):
+        for surf, q, kk, kern, theta, u0, per in specs:
+            probs.append(P.Problem(ctx, torch.from_numpy(surf.xyz).cuda(), torch.from_numpy(q).cuda(), period=per))
+            ks.append(P.kernel_struct(kk, *kern))
+            fs.append(P.Firing(beta, torch.from_numpy(theta).cuda()))
+            Bs.append(u0.shape[0])
+            states.append(torch.from_numpy(u0.copy()).cuda())
+    torch.cuda.synchronize()
+    P.Batch(ctx, probs, ks, fs, Bs).integrate(states, dt, steps, use_graph=False)
+    torch.cuda.synchronize()
+    for (surf, q, kk, kern, theta, u0, per), u in zip(specs, states):
+        ref = NF.rk4(NF.DenseOperator(surf.xyz, q, kk, kern, period=per or None), u0, beta, theta, dt, steps)
+        assert np.all(NF.rel_linf(u.cpu().numpy(), ref) <= 1e-5), (surf.kind, surf.n)
