@@ -41,74 +41,17 @@ and element weights, no projection and no Jacobian.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
-from scipy.spatial import ConvexHull, Delaunay, cKDTree
+from scipy.spatial import Delaunay, cKDTree
+
+from workloads import meshes
 
 # ------------------------------------------------------------- triangulation
 
-
-def triangulate(surface) -> np.ndarray:
-    """Flat triangulation {E_j} whose vertices are exactly the nodes.
-
-    Star-shaped surfaces: convex hull of the node directions.  Torus: strips
-    between consecutive node rings, closed in both angles.  Triangles are
-    oriented so that (b - a) x (c - a) points along the outward normal.
-    """
-    x = surface.xyz
-    if surface.star_shaped:
-        u = x / np.linalg.norm(x, axis=1, keepdims=True)
-        tris = ConvexHull(u).simplices.astype(np.int64)
-    elif surface.kind == "torus":
-        tris = _torus_strips(surface)
-    else:
-        raise ValueError("no triangulation for %s" % surface.kind)
-    a, b, c = x[tris[:, 0]], x[tris[:, 1]], x[tris[:, 2]]
-    nrm = np.cross(b - a, c - a)
-    ref = surface.normal_at((a + b + c) / 3.0)
-    flip = np.sum(nrm * ref, axis=1) < 0
-    tris[flip] = tris[flip][:, [0, 2, 1]]
-    return tris
-
-
-def _torus_strips(surface) -> np.ndarray:
-    ring = surface.ring
-    phi = surface.angles[:, 0]
-    n_rings = int(ring.max()) + 1
-    members = []
-    for k in range(n_rings):
-        idx = np.nonzero(ring == k)[0]
-        members.append(idx[np.argsort(phi[idx], kind="stable")])
-    out = []
-    two_pi = 2.0 * math.pi
-    for k in range(n_rings):
-        A = members[k]
-        B = members[(k + 1) % n_rings]
-        a_ang = phi[A]
-        b_ang = phi[B]
-        ma, mb = len(A), len(B)
-        d = np.abs(np.angle(np.exp(1j * (b_ang - a_ang[0]))))
-        j0 = int(np.argmin(d))
-        b0 = b_ang[j0]
-        if b0 - a_ang[0] > math.pi:
-            b0 -= two_pi
-        elif a_ang[0] - b0 > math.pi:
-            b0 += two_pi
-        sa = np.arange(ma + 1)
-        A_u = a_ang[sa % ma] + two_pi * (sa // ma)
-        tb = np.arange(mb + 1)
-        jb = (j0 + tb) % mb
-        B_u = b_ang[jb] + two_pi * ((j0 + tb) // mb) - b_ang[j0] + b0
-        s = t = 0
-        while s < ma or t < mb:
-            if s < ma and (t == mb or A_u[s + 1] <= B_u[t + 1]):
-                out.append((A[s % ma], A[(s + 1) % ma], B[jb[t]]))
-                s += 1
-            else:
-                out.append((A[s % ma], B[jb[t + 1]], B[jb[t]]))
-                t += 1
-    return np.asarray(out, dtype=np.int64)
+# The flat triangulation {E_j} (section 3.3: a planar triangulation whose
+# vertices are the nodes) is an input of the method, built with the node sets
+# in workloads/meshes.py; it is re-exported here for the oracle's callers.
+triangulate = meshes.triangulate
 
 
 def edges_of(tris: np.ndarray):
@@ -263,19 +206,42 @@ def planar_element_weights(s2, v0, v1, v2):
 
 
 
+def squared_distances(points: np.ndarray, centre: np.ndarray) -> np.ndarray:
+    """|p - c|^2 summed over the coordinates in order, every operation an FP64
+    rounding (no fused multiply-add): the exact quantity stencils are ranked by."""
+    diff = points - centre
+    acc = diff[..., 0] * diff[..., 0]
+    for a in range(1, diff.shape[-1]):
+        acc = acc + diff[..., a] * diff[..., a]
+    return acc
+
+
 def stencils(xyz: np.ndarray, centres: np.ndarray, k: int) -> np.ndarray:
-    """k nearest nodes to every centre, ordered by (distance, index)."""
-    if k > xyz.shape[0]:
+    """The k nodes nearest to every centre (section 3.3), ordered by the pair
+    (squared distance as `squared_distances` evaluates it, node index).
+
+    A k-d tree proposes k + 8 candidates per centre; the ranking uses the exact
+    FP64 squared distances above.  A centre whose k-th exact distance is not
+    safely below the tree's last proposal is ranked over all nodes instead.
+    """
+    n = xyz.shape[0]
+    if k > n:
         raise ValueError("stencil larger than the node set")
-    tree = cKDTree(xyz)
-    kq = min(xyz.shape[0], k + 4)          # a few extra so ties at the k-th place resolve by index
-    dist, idx = tree.query(centres, k=kq)
-    dist = np.round(dist, 14)
-    srt = np.argsort(idx, axis=1, kind="stable")
-    idx_s = np.take_along_axis(idx, srt, axis=1)
-    dist_s = np.take_along_axis(dist, srt, axis=1)
-    srt2 = np.argsort(dist_s, axis=1, kind="stable")
-    return np.take_along_axis(idx_s, srt2, axis=1)[:, :k].astype(np.int64)
+    m = min(n, k + 8)
+    dist, idx = cKDTree(xyz).query(centres, k=m)
+    idx = np.asarray(idx, dtype=np.int64).reshape(centres.shape[0], m)
+    d2 = squared_distances(xyz[idx], centres[:, None, :])
+    order = np.lexsort((idx, d2), axis=-1)
+    idx = np.take_along_axis(idx, order, axis=1)
+    d2 = np.take_along_axis(d2, order, axis=1)
+    out = idx[:, :k].copy()
+    if m < n:
+        last = np.asarray(dist, dtype=np.float64).reshape(centres.shape[0], m)[:, -1]
+        unsure = np.nonzero(d2[:, k - 1] >= last * last * (1.0 - 1e-12))[0]
+        for c in unsure:
+            full = squared_distances(xyz, centres[c])
+            out[c] = np.lexsort((np.arange(n), full))[:k]
+    return out
 
 
 def surface_weights(surface, k: int = 32, deg: int = 2, chunk: int = 8192,

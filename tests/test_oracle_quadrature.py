@@ -90,6 +90,34 @@ def test_stencils_are_nearest_with_index_tiebreak():
     assert st.tolist() == [[0, 1, 2, 3]]
 
 
+def test_stencils_match_plain_loop_ranking_with_many_ties():
+    """A jittered cloud plus an integer lattice whose centres sit on lattice
+    points (every ring of equidistant nodes is an exact tie): the stencils equal
+    a pure-Python ranking by (((dx*dx) + dy*dy) + dz*dz, index)."""
+    rng = _rng(4)
+    g = np.arange(-6, 7, dtype=np.float64)
+    gx, gy = np.meshgrid(g, g, indexing="ij")
+    lattice = np.stack([gx.ravel(), gy.ravel(), np.zeros(gx.size)], axis=1)
+    cloud = rng.normal(size=(200, 3)) * 4.0
+    # 30 integer points at squared distance exactly 25 from (100, 100, 100): more
+    # ties than the k-d tree's proposals, so the full-scan ranking is exercised
+    shell = [p for p in {(sx * a, sy * b, sz * c) for a, b, c in ((3, 4, 0), (4, 3, 0), (0, 3, 4), (0, 4, 3), (3, 0, 4),
+                                                              (4, 0, 3), (5, 0, 0), (0, 5, 0), (0, 0, 5))
+                         for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)}]
+    shell = 100.0 + np.array(sorted(shell), dtype=np.float64)
+    assert len(shell) == 30
+    x = np.concatenate([cloud, lattice, shell])
+    centres = np.concatenate([lattice[rng.choice(len(lattice), 10, replace=False)], rng.normal(size=(10, 3)),
+                              np.full((1, 3), 100.0)])
+    for k in (6, 21, 32):
+        st = Q.stencils(x, centres, k)
+        for c, row in zip(centres, st):
+            def key(j):
+                dx, dy, dz = x[j, 0] - c[0], x[j, 1] - c[1], x[j, 2] - c[2]
+                return ((dx * dx + dy * dy) + dz * dz, j)
+            assert row.tolist() == sorted(range(len(x)), key=key)[:k]
+
+
 # ---------------------------------------------------------------- triangulations
 
 
