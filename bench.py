@@ -77,6 +77,8 @@ def parse():
                     help="RK4 steps of the 48-problem uneven-batch leg (0 = skip it)")
     ap.add_argument("--adjoint-rk4-steps", type=int, default=400,
                     help="RK4 steps of the torus adjoint leg (0 = skip it)")
+    ap.add_argument("--quad-n", type=int, default=65536,
+                    help="nodes of the surface-quadrature leg on the ellipsoid (0 = skip it)")
     return ap.parse_args()
 
 
@@ -292,6 +294,48 @@ def adjoint_leg(P, torch, args):
             "grad_norm_u0": float(gu.norm()), "grad_params": [float(v) for v in gp]}
 
 
+def quad_leg(P, torch, args):
+    """Surface quadrature weights (stencils, projection points, planar RBF-QF
+    solves, accumulation) on the GPU for the ellipsoid of the ensemble workload,
+    at full size and at a quarter size (where the CPU baseline runs)."""
+    from workloads import meshes
+    from workloads import surfaces as S
+    ctx = P.Context(0)
+    out = {}
+    for n in (args.quad_n // 4, args.quad_n):
+        surf = S.ellipsoid(n)
+        tris = meshes.triangulate(surf)
+        x = torch.from_numpy(surf.xyz).cuda()
+        nr = torch.from_numpy(surf.normals).cuda()
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            q = P.quad_weights(ctx, x, nr, tris, True, 32)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        out["n%d" % n] = {"triangles": int(tris.shape[0]), "gpu_ms": best * 1e3,
+                          "triangles_per_s": tris.shape[0] / best}
+        if n == args.quad_n // 4 and not args.no_cpu_baseline:
+            out["n%d" % n]["cpu_baseline"] = cpu_baseline_quad(surf, q.cpu().numpy())
+    return {"workload": "ellipsoid (1, .8, .6), convex-hull triangulation, k = 32, degree-2 polynomials", **out}
+
+
+def cpu_baseline_quad(surf, q_gpu):
+    """The FP64 oracle's surface weights for the same surface, one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import quadrature as Q
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        q_ref = Q.surface_weights(surf, k=32)
+        cpu = time.perf_counter() - t0
+    return {"ms": cpu * 1e3, "cores": 1, "kind": "oracle",
+            "max_rel_diff_gpu_vs_oracle": float(np.max(np.abs(q_gpu - q_ref)) / np.max(np.abs(q_ref)))}
+
+
 def cpu_baseline(w, q, gpu_y_rows, rows):
     """The FP64 oracle's operator on a bounded sample: all sources, a subset of target rows."""
     from threadpoolctl import threadpool_limits
@@ -409,6 +453,9 @@ def main():
     if args.adjoint_rk4_steps > 0:
         print("bench: adjoint", file=sys.stderr, flush=True)
         line["adjoint"] = adjoint_leg(P, torch, args)
+    if args.quad_n > 0:
+        print("bench: quadrature weights", file=sys.stderr, flush=True)
+        line["quadrature"] = quad_leg(P, torch, args)
     if args.probes:
         line["probes"] = probes(P, torch, ctx)
     print(json.dumps(line), flush=True)

@@ -312,6 +312,42 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
                 int64_t ckpt_every, int64_t steps, double dt, const double* ubarT_dev, double* ubar0_dev,
                 double* pbar_host, void* ws_dev, size_t ws_bytes);
 
+/* ---------------------------------------------------------------- quadrature weights */
+
+/* Workspace bytes for nfr_quad_weights (0 if the sizes are unsupported). */
+size_t nfr_quad_workspace_size(int64_t n, int64_t ntri, int k);
+
+/* Surface quadrature weights q (paper section 3.3, eqs. integral and
+ * functional_stencil) on the GPU, all arithmetic FP64:
+ *   - for every triangle E_j (vertices a, b, c = tri_host[3j..3j+2], oriented
+ *     so that (b - a) x (c - a) points outward), its stencil is the k nodes
+ *     nearest to the centroid (a + b + c) / 3, ranked by the squared distance
+ *     (dx dx + dy dy) + dz dz evaluated without fused multiply-add, ties by
+ *     node index;
+ *   - projection point p_j: the origin if star_shaped != 0 (every ray from
+ *     the origin meets the surface once); otherwise the common point of the
+ *     three cutting planes through E_j's edges, the plane of edge e containing
+ *     that edge with normal n_j - n_j' (j' the neighbour across it);
+ *     if that 3 x 3 system has condition number above 1e8 the triangle uses
+ *     orthogonal projection onto its plane instead (a NaN row in proj_dev);
+ *   - the stencil is pulled back to E_j's plane along rays from p_j, planar
+ *     RBF-QF with phi = r^3 and polynomials of degree <= 2 gives one weight
+ *     per stencil node (a (k+6) x (k+6) saddle-point solve, LU with partial
+ *     pivoting), each weight is multiplied by the Jacobian of the projection
+ *     at that node (using the exact unit normals nrm_dev), and q_i adds node
+ *     i's weights over all triangles in increasing (triangle, slot) order.
+ * xyz_dev, nrm_dev: n x 3 FP64 row-major (device).  tri_host: ntri x 3 int32
+ * (host; read during the call).  The triangulation must be closed and
+ * consistently oriented when star_shaped == 0 (NFR_ERR_INVALID_ARG otherwise).
+ * 6 <= k <= 57, k <= n.  Outputs (device, caller-owned): q_dev (n FP64);
+ * stencil_dev (ntri x k int32, may be NULL) receives the stencils; proj_dev
+ * (ntri x 3 FP64, may be NULL) the projection points.  ws_dev: >=
+ * nfr_quad_workspace_size bytes, 256-byte aligned.  Enqueued on the context
+ * stream; the host triangle array may be reused when the call returns. */
+int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* nrm_dev, int64_t ntri,
+                     const int32_t* tri_host, int star_shaped, int k, double* q_dev, int32_t* stencil_dev,
+                     double* proj_dev, void* ws_dev, size_t ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -287,6 +287,37 @@ class Batch:
             pass
 
 
+def quad_weights(ctx: Context, xyz: torch.Tensor, normals: torch.Tensor, tris, star_shaped: bool, k: int = 32,
+                 details: bool = False):
+    """Surface quadrature weights q (N,) float64 on the GPU (nfr_quad_weights).
+
+    xyz, normals: (N, 3) float64 (moved to the context's device); tris: (M, 3)
+    integer array-like (host), oriented outward.  With details=True also
+    returns the stencils (M, k) int32 and projection points (M, 3) float64.
+    """
+    import numpy as np
+    tri = np.ascontiguousarray(np.asarray(tris), dtype=np.int32)
+    if tri.ndim != 2 or tri.shape[1] != 3:
+        raise ValueError("tris must be (M, 3)")
+    xyz = xyz.to(ctx.device, torch.float64).contiguous()
+    normals = normals.to(ctx.device, torch.float64).contiguous()
+    n, m = int(xyz.shape[0]), int(tri.shape[0])
+    ws_bytes = L.lib().nfr_quad_workspace_size(n, m, k)
+    if ws_bytes == 0:
+        raise ValueError("unsupported sizes n=%d, triangles=%d, k=%d" % (n, m, k))
+    ws = _dev_buffer(ws_bytes, ctx.device)
+    q = torch.empty(n, dtype=torch.float64, device=ctx.device)
+    st = torch.empty((m, k), dtype=torch.int32, device=ctx.device) if details else None
+    pj = torch.empty((m, 3), dtype=torch.float64, device=ctx.device) if details else None
+    with torch.cuda.stream(ctx.stream):
+        L.check(L.lib().nfr_quad_weights(ctx.handle, n, xyz.data_ptr(), normals.data_ptr(), m,
+                                         tri.ctypes.data_as(c_void_p), int(bool(star_shaped)), int(k),
+                                         q.data_ptr(), _ptr(st), _ptr(pj), ws.data_ptr(), ws_bytes))
+    if details:
+        return q, st, pj
+    return q
+
+
 class NeuralFieldRK4(torch.autograd.Function):
     """u(T) = RK4^steps(u0; A_e, s_e, A_i, s_i, theta) on a packed problem, single state.
 

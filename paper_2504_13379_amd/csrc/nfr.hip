@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -17,6 +18,7 @@
 #include "kernels_probe.h"
 #include "kernels_adjoint.h"
 #include "kernels_batch.h"
+#include "kernels_quad.h"
 
 #include <algorithm>
 
@@ -1292,6 +1294,146 @@ int nfr_integrate_forced(nfr_problem* prob, const nfr_kernel* kernel, const nfr_
       if ((st = launch_combine(pv, form, B, stage, dt, u_dev, w, fr, s, nullptr, gam))) return st;
     }
   }
+  return NFR_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ quadrature weights
+
+namespace {
+
+struct QuadWorkspace {
+  int* tri = nullptr;
+  int* nbr = nullptr;
+  double* cen = nullptr;
+  double* nrm_tri = nullptr;
+  double* proj = nullptr;
+  int* st = nullptr;
+  double* wE = nullptr;
+  int* cnt = nullptr;
+  int* cursor = nullptr;
+  int64_t* off = nullptr;
+  int64_t* bsum = nullptr;
+  int* list = nullptr;
+  size_t bytes = 0;
+};
+
+QuadWorkspace carve_quad(void* base, int64_t n, int64_t ntri, int k) {
+  QuadWorkspace w;
+  char* b = static_cast<char*>(base);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = b ? b + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  const size_t tk = size_t(ntri) * k;
+  w.tri = static_cast<int*>(take(3 * size_t(ntri) * sizeof(int)));
+  w.nbr = static_cast<int*>(take(3 * size_t(ntri) * sizeof(int)));
+  w.cen = static_cast<double*>(take(3 * size_t(ntri) * sizeof(double)));
+  w.nrm_tri = static_cast<double*>(take(3 * size_t(ntri) * sizeof(double)));
+  w.proj = static_cast<double*>(take(3 * size_t(ntri) * sizeof(double)));
+  w.st = static_cast<int*>(take(tk * sizeof(int)));
+  w.wE = static_cast<double*>(take(tk * sizeof(double)));
+  w.cnt = static_cast<int*>(take(size_t(n) * sizeof(int)));
+  w.cursor = static_cast<int*>(take(size_t(n) * sizeof(int)));
+  w.off = static_cast<int64_t*>(take(size_t(n) * sizeof(int64_t)));
+  w.bsum = static_cast<int64_t*>(take(size_t(ceil_div(n, kWG)) * sizeof(int64_t)));
+  w.list = static_cast<int*>(take(tk * sizeof(int)));
+  w.bytes = off;
+  return w;
+}
+
+bool quad_sizes_ok(int64_t n, int64_t ntri, int k) {
+  return n >= 3 && n <= kMaxN && ntri >= 1 && ntri <= 4 * kMaxN && k >= 6 && k <= kQuadMaxK && k <= n &&
+         ntri * (int64_t)k < (int64_t(1) << 31);
+}
+
+// Neighbour across every edge e (vertex e -> vertex e+1) of every triangle: the
+// triangle holding the reverse directed edge.  Fails unless every directed
+// edge occurs once and its reverse once (a closed, consistently oriented surface).
+int quad_neighbours(const int32_t* tri, int64_t ntri, std::vector<int>& nbr) {
+  std::unordered_map<uint64_t, int64_t> owner;
+  owner.reserve(size_t(3 * ntri) * 2);
+  auto key = [](uint32_t a, uint32_t b) { return (uint64_t(a) << 32) | b; };
+  for (int64_t t = 0; t < ntri; ++t)
+    for (int e = 0; e < 3; ++e) {
+      const uint32_t a = (uint32_t)tri[3 * t + e], b = (uint32_t)tri[3 * t + (e + 1) % 3];
+      if (!owner.emplace(key(a, b), 3 * t + e).second)
+        return fail(NFR_ERR_INVALID_ARG, "directed edge (%u, %u) occurs twice: the triangulation is not consistently oriented", a, b);
+    }
+  nbr.assign(size_t(3 * ntri), -1);
+  for (int64_t t = 0; t < ntri; ++t)
+    for (int e = 0; e < 3; ++e) {
+      const uint32_t a = (uint32_t)tri[3 * t + e], b = (uint32_t)tri[3 * t + (e + 1) % 3];
+      auto it = owner.find(key(b, a));
+      if (it == owner.end())
+        return fail(NFR_ERR_INVALID_ARG, "edge (%u, %u) has no reverse: the triangulation is not closed", a, b);
+      nbr[size_t(3 * t + e)] = (int)(it->second / 3);
+    }
+  return NFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t nfr_quad_workspace_size(int64_t n, int64_t ntri, int k) {
+  if (!quad_sizes_ok(n, ntri, k)) return 0;
+  return carve_quad(nullptr, n, ntri, k).bytes;
+}
+
+int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* nrm_dev, int64_t ntri,
+                     const int32_t* tri_host, int star_shaped, int k, double* q_dev, int32_t* stencil_dev,
+                     double* proj_dev, void* ws_dev, size_t ws_bytes) {
+  if (!xyz_dev || !nrm_dev || !tri_host || !q_dev) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
+  if (!quad_sizes_ok(n, ntri, k))
+    return fail(NFR_ERR_INVALID_ARG, "sizes n = %lld, ntri = %lld, k = %d outside the supported range (6 <= k <= %d, k <= n)",
+                (long long)n, (long long)ntri, k, kQuadMaxK);
+  for (int64_t i = 0; i < 3 * ntri; ++i)
+    if (tri_host[i] < 0 || tri_host[i] >= n)
+      return fail(NFR_ERR_INVALID_ARG, "triangle %lld has vertex %d outside [0, %lld)", (long long)(i / 3), tri_host[i],
+                  (long long)n);
+  for (int64_t t = 0; t < ntri; ++t) {
+    const int32_t a = tri_host[3 * t], b = tri_host[3 * t + 1], c = tri_host[3 * t + 2];
+    if (a == b || b == c || a == c) return fail(NFR_ERR_INVALID_ARG, "triangle %lld repeats a vertex", (long long)t);
+  }
+  std::vector<int> nbr;
+  int st;
+  if (!star_shaped && (st = quad_neighbours(tri_host, ntri, nbr))) return st;
+  if (!ctx) return fail(NFR_ERR_INVALID_ARG, "context is NULL");
+  const QuadWorkspace w = carve_quad(ws_dev, n, ntri, k);
+  if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
+  if (reinterpret_cast<uintptr_t>(ws_dev) % 256) return fail(NFR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  NFR_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  int* stn = stencil_dev ? stencil_dev : w.st;
+  double* proj = proj_dev ? proj_dev : w.proj;
+  const size_t tk = size_t(ntri) * k;
+  NFR_HIP(hipMemcpyAsync(w.tri, tri_host, 3 * size_t(ntri) * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!star_shaped)
+    NFR_HIP(hipMemcpyAsync(w.nbr, nbr.data(), 3 * size_t(ntri) * sizeof(int), hipMemcpyHostToDevice, s));
+  NFR_HIP(hipMemsetAsync(w.cnt, 0, size_t(n) * sizeof(int), s));
+  NFR_HIP(hipMemsetAsync(w.cursor, 0, size_t(n) * sizeof(int), s));
+  const unsigned tb = (unsigned)ceil_div(ntri, kWG);
+  hipLaunchKernelGGL(k_quad_centroids, dim3(tb), dim3(kWG), 0, s, xyz_dev, w.tri, ntri, w.cen, w.nrm_tri);
+  hipLaunchKernelGGL(k_quad_proj, dim3(tb), dim3(kWG), 0, s, xyz_dev, w.tri, w.nbr, w.cen, w.nrm_tri, ntri,
+                     star_shaped ? 1 : 0, 1e8, proj);
+  hipLaunchKernelGGL(k_quad_knn, dim3((unsigned)ceil_div(ntri, kKnnWaves * kKnnC)), dim3(kKnnWaves * 64), 0, s,
+                     xyz_dev, n, w.cen, ntri, k, stn);
+  const size_t lds = (size_t(k + 6) * (k + 7) + 2 * size_t(k)) * sizeof(double);
+  hipLaunchKernelGGL(k_quad_elements, dim3((unsigned)ntri), dim3(64), lds, s, xyz_dev, nrm_dev, w.tri, w.cen,
+                     w.nrm_tri, proj, stn, n, ntri, k, w.wE);
+  const unsigned eb = (unsigned)ceil_div((int64_t)tk, kWG);
+  const int64_t nb = ceil_div(n, kWG);
+  hipLaunchKernelGGL(k_quad_count, dim3(eb), dim3(kWG), 0, s, stn, (int64_t)tk, n, w.cnt);
+  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kWG), 0, s, w.cnt, n, w.bsum);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kWG), 0, s, w.bsum, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kWG), 0, s, w.cnt, n, w.bsum, w.off);
+  hipLaunchKernelGGL(k_quad_fill, dim3(eb), dim3(kWG), 0, s, stn, (int64_t)tk, n, w.off, w.cursor, w.list);
+  hipLaunchKernelGGL(k_quad_sum, dim3((unsigned)nb), dim3(kWG), 0, s, w.off, w.cnt, n, w.list, w.wE, q_dev);
+  NFR_HIP_LAUNCH();
   return NFR_OK;
 }
 

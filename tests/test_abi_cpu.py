@@ -82,3 +82,31 @@ def test_context_without_gpu_reports_no_device(L):
     from paper_2504_13379_amd import _lib
     out = ctypes.c_void_p()
     assert L.nfr_context_create(0, None, ctypes.byref(out)) == _lib.NFR_ERR_NO_DEVICE
+
+
+def test_quadrature_host_validation(L):
+    """Sizes, triangle indices and closedness are checked on the host before
+    the context is touched (dummy device pointers are never dereferenced)."""
+    import numpy as np
+    from paper_2504_13379_amd import _lib
+    assert L.nfr_quad_workspace_size(100, 196, 5) == 0
+    assert L.nfr_quad_workspace_size(100, 196, 58) == 0
+    assert L.nfr_quad_workspace_size(20, 36, 32) == 0
+    assert L.nfr_quad_workspace_size(100, 196, 32) > 0
+    tet = np.array([[0, 2, 1], [0, 1, 3], [1, 2, 3], [0, 3, 2]], dtype=np.int32)
+    dummy = ctypes.c_void_p(256)
+
+    def call(tri, star, k=6, n=8):
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        return L.nfr_quad_weights(None, n, dummy, dummy, tri.shape[0], tri.ctypes.data_as(ctypes.c_void_p), star, k,
+                                  dummy, None, None, dummy, 1 << 20)
+    bad = tet.copy()
+    bad[2, 1] = 8
+    assert call(bad, 0) == _lib.NFR_ERR_INVALID_ARG and b"outside" in L.nfr_last_error()
+    assert call(tet[:3], 0) == _lib.NFR_ERR_INVALID_ARG and b"not closed" in L.nfr_last_error()
+    flipped = tet.copy()
+    flipped[0] = flipped[0, [0, 2, 1]]
+    assert call(flipped, 0) == _lib.NFR_ERR_INVALID_ARG and b"oriented" in L.nfr_last_error()
+    assert call(tet, 0, k=9) == _lib.NFR_ERR_INVALID_ARG and b"sizes" in L.nfr_last_error()
+    assert call(tet, 0) == _lib.NFR_ERR_INVALID_ARG and b"context" in L.nfr_last_error()
+    assert call(tet[:3], 1) == _lib.NFR_ERR_INVALID_ARG and b"context" in L.nfr_last_error()
