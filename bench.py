@@ -38,7 +38,28 @@ TRANS_COST = 4.0
 #   evaluation: 3 sub + 1 mul + 2 fma (r^2) + 1 mul (rho t) = 7 full-rate, plus
 #   2 exp2 (Gaussian) or sqrt + 2 exp2 (exponential) at 4 slots each;
 #   accumulation: 2 fma into y_i and 2 fma into y_j.
-SLOTS_PER_UNORDERED_PAIR = {0: 7 + 2 * TRANS_COST + 4, 1: 7 + 3 * TRANS_COST + 4}
+# With length scales in the ratio rho = 1/m (m = 2, 3, 4) the kernel takes the
+# excitatory exponential as the m-th power of the inhibitory one: one exp2
+# fewer, 1 (m = 2) or 2 (m = 3, 4) multiplies more.
+
+
+def sym_pow(kind, s_e, s_i):
+    """m when s_e/s_i (squared for the Gaussian) is 1/m with m in {2, 3, 4}, else 0."""
+    rho = s_e / s_i
+    if kind == 0:
+        rho *= rho
+    m = 1.0 / rho
+    mi = int(round(m))
+    return mi if 2 <= mi <= 4 and abs(m - mi) <= 1e-12 * mi else 0
+
+
+def slots_per_unordered_pair(kind, m):
+    trans = (2 if kind == 0 else 3) - (1 if m else 0)
+    return 7 + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 4
+
+
+def sym_kernel_name(kind, m, periodic=False):
+    return "k_otf_sym<%d>" % (kind + (2 if periodic else 0) + ((m - 1) << 2 if m else 0))
 
 
 def measured_traffic(kernel: str):
@@ -130,18 +151,22 @@ def run_form(P, torch, prob, w, q_t, form, args, u0_t):
     }
 
 
-def roofline(form_name, res, n, npad):
+def roofline(form_name, res, n, npad, kernel):
     avg_s = res["kernel_avg_ms"] * 1e-3
     if form_name == "w32":
         bytes_per_launch = float(n) * npad * 4.0          # every W element once per application
         ach = bytes_per_launch / avg_s
         return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": ach / HBM_PEAK, "traffic": measured_traffic("k_w_gemv_f32<1>"), "kernel": "k_w_gemv_f32<1>"}
-    # on-the-fly (exponential kernel): slots per unordered pair x npad^2 / 2 pairs per launch
-    ops = SLOTS_PER_UNORDERED_PAIR[1] * float(npad) * npad / 2.0
+    # on-the-fly: slots per unordered pair x npad^2 / 2 pairs per launch
+    kind, s_e, s_i = kernel[0], kernel[2], kernel[4]
+    m = sym_pow(kind, s_e, s_i)
+    name = sym_kernel_name(kind, m)
+    ops = slots_per_unordered_pair(kind, m) * float(npad) * npad / 2.0
     ach = ops / avg_s
     return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tlane-op/s",
-            "frac": ach / VALU_LANES_PER_S, "traffic": measured_traffic("k_otf_sym<1>"), "kernel": "k_otf_sym<1>"}
+            "frac": ach / VALU_LANES_PER_S, "traffic": measured_traffic(name), "kernel": name,
+            "slots_per_unordered_pair": slots_per_unordered_pair(kind, m)}
 
 
 def ensemble_leg(P, torch, args):
@@ -409,11 +434,12 @@ def main():
         print("bench: form %s %.3f ms/step" % (nm, results[nm]["ms_per_step"]), file=sys.stderr, flush=True)
     best = max(results, key=lambda k: results[k]["value"])
     r = results[best]
-    rl = roofline(best, r, w.n, prob.npad)
+    kern = (w.kernel_kind,) + tuple(w.kernel)
+    rl = roofline(best, r, w.n, prob.npad, kern)
 
     forms = {}
     for nm, rr in results.items():
-        rlf = roofline(nm, rr, w.n, prob.npad)
+        rlf = roofline(nm, rr, w.n, prob.npad, kern)
         forms[nm] = {"value": rr["value"], "ms_per_step": rr["ms_per_step"], "kernel_avg_ms": rr["kernel_avg_ms"],
                      "roofline_frac": rlf["frac"]}
     if len(results) == 2:

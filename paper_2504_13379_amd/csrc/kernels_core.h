@@ -171,22 +171,25 @@ __global__ __launch_bounds__(kWG) void k_otf_pair_sum(const float4* __restrict__
 // sums to slot I of the nodes of J, so every node receives exactly one
 // contribution per tile index and the combine adds slots 0..nt-1 in order.
 //
-// Each lane keeps kSymTPT targets in registers.  A group of 64 sources is
-// loaded one per lane and rotated around the wave 64 times (DPP wave rotate
-// by one lane); each source carries its own column accumulators, so after a
-// full turn they hold the sum over the wave's 64 * kSymTPT targets and the
-// source is back in its lane.  Row sums: FP32 per group of 64 sources, folded
-// into FP64; column sums: FP32 over the wave, FP64 across waves.
-#ifndef NFR_SYM_WAVES
-#define NFR_SYM_WAVES 2
+// Each lane keeps kSymTPT targets in registers, so one wave holds the whole
+// tile of 64 * kSymTPT targets; the kSymSplit waves of a workgroup share those
+// targets and split the tile's source groups between them (group g goes to
+// wave g mod kSymSplit).  A group of 64 sources is loaded one per lane and
+// rotated around the wave 64 times (DPP wave rotate by one lane); each source
+// carries its own column accumulators, so after a full turn they hold the sum
+// over all the tile's targets and the source is back in its lane.  Row sums:
+// FP32 per group of 64 sources, folded into FP64, then added over the waves
+// in wave order through LDS; column sums: FP32 over the wave, complete.
+#ifndef NFR_SYM_SPLIT
+#define NFR_SYM_SPLIT 4
 #endif
 #ifndef NFR_SYM_TPT
-#define NFR_SYM_TPT 3
+#define NFR_SYM_TPT 4
 #endif
-constexpr int kSymWaves = NFR_SYM_WAVES;
+constexpr int kSymSplit = NFR_SYM_SPLIT;
 constexpr int kSymTPT = NFR_SYM_TPT;
-constexpr int kSymThreads = 64 * kSymWaves;
-constexpr int kSymTile = kSymThreads * kSymTPT;   // 384 nodes by default
+constexpr int kSymThreads = 64 * kSymSplit;
+constexpr int kSymTile = 64 * kSymTPT;   // 256 nodes by default
 
 __device__ inline float wave_ror1(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, false));
@@ -202,17 +205,34 @@ __device__ inline void sym_decode(int64_t p, int64_t* I, int64_t* J) {
   *I = p - j * (j + 1) / 2;
 }
 
+// Length scales in an integer ratio, rho = 1/m with m in {2, 3, 4}: the
+// excitatory exponential is the m-th power of the inhibitory one,
+// exp2(-t) = exp2(-rho t)^m, so one exponential per pair suffices.  KIND bits
+// 2-3 hold m - 1 (0: two exponentials).
+template <int KIND>
+constexpr int sym_pow() {
+  return (KIND >> 2) == 0 ? 0 : (KIND >> 2) + 1;
+}
+
+template <int M>
+__device__ __forceinline__ float ipow(float x) {
+  if (M == 2) return x * x;
+  if (M == 3) return x * x * x;
+  const float x2 = x * x;
+  return x2 * x2;
+}
+
 template <int KIND, bool COLS>
 __device__ inline void sym_tile(const float4* __restrict__ src, const float* __restrict__ g, int64_t npad,
                                 const PairParams& pp, double* __restrict__ part, int64_t I, int64_t J,
-                                double (*colsum)[kSymTile]) {
+                                double (*rowsum)[kSymTile]) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const float rho = pp.rho;
   float xi[kSymTPT], yi[kSymTPT], zi[kSymTPT], gi[kSymTPT];
 #pragma unroll
   for (int k = 0; k < kSymTPT; ++k) {
-    const int64_t t = I * kSymTile + (int64_t)wave * 64 * kSymTPT + k * 64 + lane;
+    const int64_t t = I * kSymTile + k * 64 + lane;
     const int64_t tc = t < npad ? t : npad - 1;
     const float4 p = src[tc];
     xi[k] = p.x * pp.sig;
@@ -227,7 +247,7 @@ __device__ inline void sym_tile(const float4* __restrict__ src, const float* __r
   int64_t nsrc = npad - J * kSymTile;
   if (nsrc > kSymTile) nsrc = kSymTile;
   const int ngroups = (int)(nsrc / 64);
-  for (int grp = 0; grp < ngroups; ++grp) {
+  for (int grp = wave; grp < ngroups; grp += kSymSplit) {
     const int64_t j = J * kSymTile + grp * 64 + lane;
     const float4 s4 = src[j];
     float sx = s4.x * pp.sig, sy = s4.y * pp.sig, sz = s4.z * pp.sig, sg = g[j];
@@ -241,8 +261,8 @@ __device__ inline void sym_tile(const float4* __restrict__ src, const float* __r
       for (int k = 0; k < kSymTPT; ++k) {
         const float r2 = pair_r2<KIND>(xi[k] - sx, yi[k] - sy, zi[k] - sz, pp.per);
         const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
-        const float e1 = __builtin_amdgcn_exp2f(-t);
         const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
+        const float e1 = sym_pow<KIND>() == 0 ? __builtin_amdgcn_exp2f(-t) : ipow<sym_pow<KIND>()>(e2);
         ae[k] = fmaf(e1, sg, ae[k]);
         ai[k] = fmaf(e2, sg, ai[k]);
         if (COLS) {
@@ -261,20 +281,25 @@ __device__ inline void sym_tile(const float4* __restrict__ src, const float* __r
     }
 #pragma unroll
     for (int k = 0; k < kSymTPT; ++k) racc[k] += pp.Ae * (double)ae[k] - pp.Ai * (double)ai[k];
-    if (COLS) colsum[wave][grp * 64 + lane] = pp.Ae * (double)ce - pp.Ai * (double)ci;
+    if (COLS) part[I * npad + j] = pp.Ae * (double)ce - pp.Ai * (double)ci;
   }
+  if (kSymSplit == 1) {
 #pragma unroll
-  for (int k = 0; k < kSymTPT; ++k) {
-    const int64_t t = I * kSymTile + (int64_t)wave * 64 * kSymTPT + k * 64 + lane;
-    if (t < npad) part[J * npad + t] = racc[k];
-  }
-  if (COLS) {
+    for (int k = 0; k < kSymTPT; ++k) {
+      const int64_t t = I * kSymTile + k * 64 + lane;
+      if (t < npad) part[J * npad + t] = racc[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSymTPT; ++k) rowsum[wave][k * 64 + lane] = racc[k];
     __syncthreads();
-    for (int jj = threadIdx.x; jj < nsrc; jj += kSymThreads) {
+    for (int tt = threadIdx.x; tt < kSymTile; tt += kSymThreads) {
+      const int64_t t = I * kSymTile + tt;
+      if (t >= npad) continue;
       double sum = 0.0;
 #pragma unroll
-      for (int w = 0; w < kSymWaves; ++w) sum += colsum[w][jj];
-      part[I * npad + J * kSymTile + jj] = sum;
+      for (int w = 0; w < kSymSplit; ++w) sum += rowsum[w][tt];
+      part[J * npad + t] = sum;
     }
   }
 }
@@ -283,30 +308,56 @@ __device__ inline void sym_tile(const float4* __restrict__ src, const float* __r
 template <int KIND>
 __global__ __launch_bounds__(kSymThreads) void k_otf_sym(const float4* __restrict__ src, const float* __restrict__ g,
                                                          int64_t npad, PairParams pp, double* __restrict__ part) {
-  __shared__ double colsum[kSymWaves][kSymTile];
+  __shared__ double rowsum[kSymSplit][kSymTile];
   int64_t I, J;
   sym_decode(blockIdx.x, &I, &J);
   if (I == J)
-    sym_tile<KIND, false>(src, g, npad, pp, part, I, J, colsum);
+    sym_tile<KIND, false>(src, g, npad, pp, part, I, J, rowsum);
   else
-    sym_tile<KIND, true>(src, g, npad, pp, part, I, J, colsum);
+    sym_tile<KIND, true>(src, g, npad, pp, part, I, J, rowsum);
 }
 
 // ------------------------------------------------------------------ reductions
 
-// y[b*n + i] = sum over splits (in order) of part[(s*B + b)*npad + i], FP64.
+// Partial sums part[(s*B + b)*npad + i] of one element (b, i), added by a group
+// of L consecutive lanes (L a power of two, at most 64): lane r of the group
+// adds slots r, r + L, r + 2L, ... in order, then the group adds its L values
+// by an xor butterfly.  Both operands of every butterfly addition are the same
+// in the two lanes that perform it, so all L lanes end with the same,
+// reproducible total.  Many slots (the symmetric kernel has one per tile) are
+// then read by many lanes in parallel instead of one.
+template <int L>
+__device__ inline double slot_sum(const double* __restrict__ part, int nsplit, int B, int64_t npad, int b,
+                                  int64_t i, int sub) {
+  double y = 0.0;
+  for (int sp = sub; sp < nsplit; sp += L) y += part[((int64_t)sp * B + b) * npad + i];
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) y += __shfl_xor(y, off, L);
+  return y;
+}
+
+// Element index and lane-in-group of the calling thread for L lanes per element.
+template <int L>
+__device__ inline int64_t group_index(int* sub) {
+  const int64_t gt = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  *sub = (int)(gt & (L - 1));
+  return gt / L;
+}
+
+// y[b*n + i] = sum of the partials of (b, i), FP64.  Grid: n*B*L threads.
+template <int L>
 __global__ __launch_bounds__(kWG) void k_reduce_partials(const double* __restrict__ part, int nsplit, int64_t n,
                                                          int64_t npad, int B, double* __restrict__ y) {
-  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  int sub;
+  const int64_t idx = group_index<L>(&sub);
   if (idx >= n * (int64_t)B) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
-  double s = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * B + b) * npad + i];
-  y[idx] = s;
+  const double s = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
+  if (sub == 0) y[idx] = s;
 }
 
-// RK4 stage combination, all FP64 (one thread per (i, b), i < n):
+// RK4 stage combination, all FP64 (L threads per (i, b), i < n; see slot_sum):
 //   y   = sum of partials (= K(v_s)),  k = -v_s + y
 //   s=1: ksum = k,        v <- u + dt/2 k
 //   s=2: ksum += 2k,      v <- u + dt/2 k
@@ -315,18 +366,20 @@ __global__ __launch_bounds__(kWG) void k_reduce_partials(const double* __restric
 // then g[b*npad + i] = s_i f_b(v) for the next stage (s_i = q_i or 1).
 // k1_out (may be null) receives k_1 = F(u_n) at stage 1 (the Adams-Bashforth start-up records it);
 // gamma (may be null) is a forcing term added to k (B x n, at this stage's time).
+template <int L>
 __global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ part, int nsplit, int64_t n,
                                                      int64_t npad, int B, int stage, double dt,
                                                      double* __restrict__ u, double* __restrict__ v,
                                                      double* __restrict__ ksum, const double* __restrict__ qd,
                                                      int with_q, Firing fr, float* __restrict__ g,
                                                      double* __restrict__ k1_out, const double* __restrict__ gamma) {
-  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  int sub;
+  const int64_t idx = group_index<L>(&sub);
   if (idx >= n * (int64_t)B) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
-  double y = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  const double y = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
+  if (sub != 0) return;
   const double k = -v[idx] + y + (gamma ? gamma[idx] : 0.0);
   double ui = u[idx];
   double vn;
@@ -362,18 +415,20 @@ struct Ab5Weights {
 //   u_{n+1} = u_n + dt sum_k a_k hist[slot(n - k)],
 // then g[b*npad + i] = s_i f_b(u_{n+1}).  hist holds 5 arrays of n*B; slots[k]
 // is the array holding F_{n-k}.
+template <int L>
 __global__ __launch_bounds__(kWG) void k_ab5_combine(const double* __restrict__ part, int nsplit, int64_t n,
                                                      int64_t npad, int B, double dt, Ab5Weights wt, int4 slots03,
                                                      int slot4, double* __restrict__ u, double* __restrict__ hist,
                                                      const double* __restrict__ qd, int with_q, Firing fr,
                                                      float* __restrict__ g) {
-  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  int sub;
+  const int64_t idx = group_index<L>(&sub);
   const int64_t nb = n * (int64_t)B;
   if (idx >= nb) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
-  double y = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  const double y = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
+  if (sub != 0) return;
   const double ui = u[idx];
   const double F = -ui + y;
   hist[slots03.x * nb + idx] = F;
@@ -412,6 +467,7 @@ __global__ __launch_bounds__(kWG) void k_syndep_prep(const double* __restrict__ 
 
 // RK4 stage combination of the coupled (u, a) system, all FP64; next sources
 // g = q a f(u) at the new stage input.
+template <int L>
 __global__ __launch_bounds__(kWG) void k_syndep_combine(const double* __restrict__ part, int nsplit, int64_t n,
                                                         int64_t npad, int B, int stage, double dt, double inv_tau,
                                                         double beta_d, double* __restrict__ u, double* __restrict__ a,
@@ -419,13 +475,14 @@ __global__ __launch_bounds__(kWG) void k_syndep_combine(const double* __restrict
                                                         double* __restrict__ ku_sum, double* __restrict__ ka_sum,
                                                         const double* __restrict__ qd, Firing fr,
                                                         float* __restrict__ g) {
-  const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  int sub;
+  const int64_t idx = group_index<L>(&sub);
   if (idx >= n * (int64_t)B) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
   const double th = state_theta(fr, b);
-  double y = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  const double y = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
+  if (sub != 0) return;
   const double cu = vu[idx], ca = va[idx];
   const double ku = -cu + y;
   const double ka = (1.0 - ca - beta_d * ca * sigmoid(cu, fr.beta, th)) * inv_tau;

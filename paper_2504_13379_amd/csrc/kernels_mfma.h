@@ -488,7 +488,7 @@ inline void launch_mfma_ab5(const ProblemView& pv, int form, int B, double dt, c
 inline void launch_mfma_reduce(const ProblemView& pv, int, int B, const double* part, int nsplit, double* y,
                                hipStream_t s) {
   const int64_t total = pv.n * (int64_t)B;
-  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit, pv.n,
+  hipLaunchKernelGGL(k_reduce_partials<1>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit, pv.n,
                      pv.npad, B, y);
 }
 

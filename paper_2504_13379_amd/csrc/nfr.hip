@@ -114,6 +114,19 @@ PairParams pair_params(const nfr_kernel& k, const ProblemView& pv) {
 // Template code of the pair kernels: kernel kind, + 2 for a periodic problem.
 int kind_code(const nfr_kernel& k, const ProblemView& pv) { return k.kind + (pv.period > 0.0 ? 2 : 0); }
 
+// m - 1 when the length scales are in the ratio rho = 1/m, m in {2, 3, 4}
+// (rho = s_e/s_i, squared for the Gaussian), else 0; the symmetric kernel then
+// derives the excitatory exponential from the inhibitory one.
+int sym_pow_code(const nfr_kernel& k) {
+  double rho = k.s_e / k.s_i;
+  if (k.kind == NFR_KERNEL_GAUSS_MH) rho *= rho;
+  if (!(rho > 0.0)) return 0;
+  const double m = 1.0 / rho;
+  const long mi = std::lround(m);
+  if (mi >= 2 && mi <= 4 && std::fabs(m - (double)mi) <= 1e-12 * (double)mi) return (int)mi - 1;
+  return 0;
+}
+
 KernelF64 kernel64(const nfr_kernel& k, const ProblemView& pv) {
   return KernelF64{k.kind, k.A_e, k.s_e, k.A_i, k.s_i, pv.period};
 }
@@ -270,12 +283,16 @@ int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B
   if (use_sym(form, B)) {
     const PairParams pp = pair_params(k, pv);
     const dim3 grid((unsigned)sym_pairs(sym_tiles(pv.npad)));
-    switch (kind_code(k, pv)) {
-      case 0: hipLaunchKernelGGL(k_otf_sym<0>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
-      case 1: hipLaunchKernelGGL(k_otf_sym<1>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
-      case 2: hipLaunchKernelGGL(k_otf_sym<2>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
-      default: hipLaunchKernelGGL(k_otf_sym<3>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
+#define NFR_SYM_CASE(K) \
+  case K: hipLaunchKernelGGL(k_otf_sym<K>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
+    switch (kind_code(k, pv) | (sym_pow_code(k) << 2)) {
+      NFR_SYM_CASE(0) NFR_SYM_CASE(1) NFR_SYM_CASE(2) NFR_SYM_CASE(3)
+      NFR_SYM_CASE(4) NFR_SYM_CASE(5) NFR_SYM_CASE(6) NFR_SYM_CASE(7)
+      NFR_SYM_CASE(8) NFR_SYM_CASE(9) NFR_SYM_CASE(10) NFR_SYM_CASE(11)
+      NFR_SYM_CASE(12) NFR_SYM_CASE(13) NFR_SYM_CASE(14) NFR_SYM_CASE(15)
+      default: return fail(NFR_ERR_INTERNAL, "no symmetric kernel for this kernel code");
     }
+#undef NFR_SYM_CASE
   } else if (form == NFR_FORM_ONTHEFLY_FP32) {
     const OtfPlan pl = plan_otf(pv.npad, B);
     const PairParams pp = pair_params(k, pv);
@@ -303,6 +320,20 @@ int launch_pairs(nfr_context* ctx, const ProblemView& pv, const nfr_kernel& k, i
   return timing_mark(ctx);
 }
 
+// Lanes per element for adding nsplit partial-sum slots (see slot_sum).
+int slot_lanes(int nsplit) { return nsplit <= 4 ? 1 : (nsplit <= 16 ? 4 : (nsplit <= 64 ? 8 : 16)); }
+
+// Launches KERNEL<L> with L = slot_lanes(nsplit) and n*B*L threads.
+#define NFR_LAUNCH_SLOTS(KERNEL, nsplit, total, s, ...)                                                      \
+  do {                                                                                                      \
+    const int L_ = slot_lanes(nsplit);                                                                      \
+    const dim3 g_((unsigned)ceil_div((total) * L_, kWG));                                                   \
+    if (L_ == 1) hipLaunchKernelGGL(KERNEL<1>, g_, dim3(kWG), 0, s, __VA_ARGS__);                           \
+    else if (L_ == 4) hipLaunchKernelGGL(KERNEL<4>, g_, dim3(kWG), 0, s, __VA_ARGS__);                      \
+    else if (L_ == 8) hipLaunchKernelGGL(KERNEL<8>, g_, dim3(kWG), 0, s, __VA_ARGS__);                      \
+    else hipLaunchKernelGGL(KERNEL<16>, g_, dim3(kWG), 0, s, __VA_ARGS__);                                  \
+  } while (0)
+
 int launch_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, const Workspace& w,
                    const Firing& fr, hipStream_t s, double* k1_out = nullptr, const double* gamma = nullptr) {
   const int nsplit = nsplit_for(pv, B, form);
@@ -311,8 +342,8 @@ int launch_combine(const ProblemView& pv, int form, int B, int stage, double dt,
     launch_mfma_combine(pv, form, B, stage, dt, u, w.v, w.ksum, w.part, nsplit, fr, w.g, k1_out, gamma, s);
   } else {
     const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
-    hipLaunchKernelGGL(k_rk4_combine, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
-                       pv.npad, B, stage, dt, u, w.v, w.ksum, pv.q, with_q, fr, w.g, k1_out, gamma);
+    NFR_LAUNCH_SLOTS(k_rk4_combine, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, stage, dt, u, w.v, w.ksum,
+                     pv.q, with_q, fr, w.g, k1_out, gamma);
   }
   NFR_HIP_LAUNCH();
   return NFR_OK;
@@ -331,8 +362,8 @@ int launch_ab5(const ProblemView& pv, int form, int B, int64_t n_step, double dt
     launch_mfma_ab5(pv, form, B, dt, wt, s03, s4, u, hist, w.part, nsplit, fr, w.g, s);
   } else {
     const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
-    hipLaunchKernelGGL(k_ab5_combine, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
-                       pv.npad, B, dt, wt, s03, s4, u, hist, pv.q, with_q, fr, w.g);
+    NFR_LAUNCH_SLOTS(k_ab5_combine, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, dt, wt, s03, s4, u, hist,
+                     pv.q, with_q, fr, w.g);
   }
   NFR_HIP_LAUNCH();
   return NFR_OK;
@@ -601,8 +632,7 @@ int nfr_apply(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* fir
   if (is_mfma_form(form))
     launch_mfma_reduce(pv, form, B, w.part, nsplit, y_dev, s);
   else
-    hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
-                       pv.npad, B, y_dev);
+    NFR_LAUNCH_SLOTS(k_reduce_partials, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, y_dev);
   NFR_HIP_LAUNCH();
   return NFR_OK;
 }
@@ -1249,9 +1279,8 @@ int nfr_integrate_syndep(nfr_problem* prob, const nfr_kernel* kernel, const nfr_
   for (int64_t n = 0; n < steps; ++n) {
     for (int stage = 1; stage <= 4; ++stage) {
       if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, nullptr, w))) return st;
-      hipLaunchKernelGGL(k_syndep_combine, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, w.part, nsplit, pv.n,
-                         pv.npad, B, stage, dt, 1.0 / tau, beta_d, u_dev, a_dev, w.v, va, w.ksum, ka_sum, pv.q, fr,
-                         w.g);
+      NFR_LAUNCH_SLOTS(k_syndep_combine, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, stage, dt, 1.0 / tau,
+                       beta_d, u_dev, a_dev, w.v, va, w.ksum, ka_sum, pv.q, fr, w.g);
       NFR_HIP_LAUNCH();
     }
   }

@@ -207,3 +207,25 @@ def test_invalid_arguments_rejected(ctx):
     with pytest.raises(P.NfrError) as e:
         prob.apply(P.kernel_struct(7, *GAUSS), f, u)
     assert e.value.status == -1
+
+
+# Length scales in an integer ratio: the symmetric kernel takes exp2(-t) as a
+# power of exp2(-rho t) (rho = 1/m); same tolerance as the two-exponential form.
+RATIO_KERNELS = [(NF.GAUSS_MH, (1.0, 0.2, 0.5, 0.2 * math.sqrt(2.0))),     # rho = 1/2
+                 (NF.GAUSS_MH, (1.0, 0.12, 0.4, 0.12 * math.sqrt(3.0))),   # rho = 1/3
+                 (NF.EXP_MH, (1.0, 0.1, 0.5, 0.2)),                        # rho = 1/2
+                 (NF.EXP_MH, (2.0, 0.1, 1.0, 0.4)),                        # rho = 1/4
+                 (NF.GAUSS_MH, (1.0, 0.1, 0.3, 0.2))]                      # rho = 1/4
+
+
+@pytest.mark.parametrize("kind,p", RATIO_KERNELS)
+@pytest.mark.parametrize("n", [383, 3001])
+def test_apply_integer_ratio_kernels(ctx, kind, p, n):
+    rng = np.random.default_rng(n + int(p[3] * 1000))
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    U = rng.normal(0.2, 0.4, size=(1, n))
+    y = _run_apply(ctx, x, q, U, kind, p, 20.0, 0.2, 0)
+    ref = NF.apply_K(x, q, U, kind, p, 20.0, 0.2)
+    scale = _abs_scale(x, q, U, kind, p, 20.0, 0.2, None)
+    assert np.max(np.abs(y - ref) / scale) <= 1e-5
