@@ -39,8 +39,9 @@ TRANS_COST = 4.0
 #   2 exp2 (Gaussian) or sqrt + 2 exp2 (exponential) at 4 slots each;
 #   accumulation: 2 fma into y_i and 2 fma into y_j.
 # With length scales in the ratio rho = 1/m (m = 2, 3, 4) the kernel takes the
-# excitatory exponential as the m-th power of the inhibitory one: one exp2
-# fewer, 1 (m = 2) or 2 (m = 3, 4) multiplies more.
+# excitatory exponential as the m-th power of the inhibitory one and scales the
+# coordinates by the inhibitory length: one exp2 and the rho t multiply fewer,
+# 1 (m = 2) or 2 (m = 3, 4) multiplies more.
 
 
 def sym_pow(kind, s_e, s_i):
@@ -55,29 +56,36 @@ def sym_pow(kind, s_e, s_i):
 
 def slots_per_unordered_pair(kind, m):
     trans = (2 if kind == 0 else 3) - (1 if m else 0)
-    return 7 + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 4
+    return (6 if m else 7) + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 4
 
 
 def sym_kernel_name(kind, m, periodic=False):
     return "k_otf_sym<%d>" % (kind + (2 if periodic else 0) + ((m - 1) << 2 if m else 0))
 
 
+# Sources that define the profiled kernels (their code and tile constants).
+TRAFFIC_SOURCES = ("common.h", "kernels_core.h", "kernels_mfma.h")
+
+
+def traffic_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2504_13379_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
-    or None when the HIP sources changed since the counters were taken."""
-    import glob
-    import hashlib
+    or None when the kernels' sources changed since the counters were taken."""
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2504_13379_amd", "csrc", "*"))):
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != rec.get("csrc_sha256") or kernel not in rec:
+    if traffic_sources_sha256() != rec.get("sources_sha256") or kernel not in rec:
         return None
     return rec[kernel]["bytes"]
 

@@ -208,7 +208,8 @@ __device__ inline void sym_decode(int64_t p, int64_t* I, int64_t* J) {
 // Length scales in an integer ratio, rho = 1/m with m in {2, 3, 4}: the
 // excitatory exponential is the m-th power of the inhibitory one,
 // exp2(-t) = exp2(-rho t)^m, so one exponential per pair suffices.  KIND bits
-// 2-3 hold m - 1 (0: two exponentials).
+// 2-3 hold m - 1 (0: two exponentials); such launches scale the coordinates
+// (and the period) by the inhibitory length, so the kernel's t is rho t.
 template <int KIND>
 constexpr int sym_pow() {
   return (KIND >> 2) == 0 ? 0 : (KIND >> 2) + 1;
@@ -261,7 +262,8 @@ __device__ inline void sym_tile(const float4* __restrict__ src, const float* __r
       for (int k = 0; k < kSymTPT; ++k) {
         const float r2 = pair_r2<KIND>(xi[k] - sx, yi[k] - sy, zi[k] - sz, pp.per);
         const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
-        const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
+        // with sym_pow the coordinates are scaled by the inhibitory length: t is already rho t
+        const float e2 = __builtin_amdgcn_exp2f(-(sym_pow<KIND>() == 0 ? t * rho : t));
         const float e1 = sym_pow<KIND>() == 0 ? __builtin_amdgcn_exp2f(-t) : ipow<sym_pow<KIND>()>(e2);
         ae[k] = fmaf(e1, sg, ae[k]);
         ai[k] = fmaf(e2, sg, ai[k]);

@@ -281,7 +281,12 @@ int timing_mark(nfr_context* ctx) {
 int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B, const void* W, const Workspace& w,
                      hipStream_t s) {
   if (use_sym(form, B)) {
-    const PairParams pp = pair_params(k, pv);
+    PairParams pp = pair_params(k, pv);
+    if (sym_pow_code(k)) {   // coordinates in units of the inhibitory length (see sym_pow)
+      const double sig_i = k.kind == NFR_KERNEL_GAUSS_MH ? std::sqrt(kLog2e) / k.s_i : kLog2e / k.s_i;
+      pp.sig = (float)sig_i;
+      pp.per = (float)(pv.period * sig_i);
+    }
     const dim3 grid((unsigned)sym_pairs(sym_tiles(pv.npad)));
 #define NFR_SYM_CASE(K) \
   case K: hipLaunchKernelGGL(k_otf_sym<K>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
