@@ -16,79 +16,135 @@
 #pragma once
 
 #include "common.h"
+#include "kernels_core.h"
 
 namespace nfr {
 
-constexpr int kAdjTPT = 4;
-
-template <int KIND>
-__global__ __launch_bounds__(kWG) void k_otf_adjoint(const float4* __restrict__ src, const float* __restrict__ lam,
-                                                     int64_t npad, int64_t chunk, int nsplit, PairParams pp,
-                                                     double* __restrict__ part) {
-  __shared__ float4 s_src[kWG];
-  const int tid = threadIdx.x;
-  const int64_t tbase = (int64_t)blockIdx.x * (kWG * kAdjTPT);
-  const int split = blockIdx.y;
-  float xi[kAdjTPT], yi[kAdjTPT], zi[kAdjTPT];
+// Symmetric transpose sum: every term of S1, S2, T1, T2 is symmetric in
+// (i, j), so the tile-pair scheme of the forward symmetric kernel applies
+// (kernels_core.h: tile pairs I <= J, the targets of tile I held kSymTPT per lane,
+// source groups of J split over the waves, sources rotated by DPP carrying
+// their column accumulators), here with four channels weighted by lambda.
+// Slots: part[(c * nt + s) * npad + i] for channel c, slot s (the row sums of
+// (I, J) go to slot J of the nodes of I, the column sums to slot I of the
+// nodes of J).  The coordinates are in the forward kernel's units (t the
+// excitatory argument); with rho = 1/m the kernel uses e1 = e2^m.
+template <int KIND, bool COLS>
+__device__ inline void sym_adj_tile(const float4* __restrict__ src, const float* __restrict__ lam, int64_t npad,
+                                    int nt, const PairParams& pp, double* __restrict__ part, int64_t I, int64_t J,
+                                    double (*rowsum)[4][kSymTile]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const float rho = pp.rho;
+  float xi[kSymTPT], yi[kSymTPT], zi[kSymTPT], li[kSymTPT];
 #pragma unroll
-  for (int k = 0; k < kAdjTPT; ++k) {
-    int64_t t = tbase + tid + (int64_t)kWG * k;
-    if (t >= npad) t = npad - 1;
-    const float4 p = src[t];
+  for (int k = 0; k < kSymTPT; ++k) {
+    const int64_t t = I * kSymTile + k * 64 + lane;
+    const int64_t tc = t < npad ? t : npad - 1;
+    const float4 p = src[tc];
     xi[k] = p.x * pp.sig;
     yi[k] = p.y * pp.sig;
     zi[k] = p.z * pp.sig;
+    li[k] = t < npad ? lam[t] : 0.0f;
   }
-  double acc[kAdjTPT][4];
+  double racc[kSymTPT][4];
 #pragma unroll
-  for (int k = 0; k < kAdjTPT; ++k)
+  for (int k = 0; k < kSymTPT; ++k)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[k][c] = 0.0;
-  const int64_t j_begin = (int64_t)split * chunk;
-  int64_t j_end = j_begin + chunk;
-  if (j_end > npad) j_end = npad;
-  const float rho = pp.rho;
-  for (int64_t j0 = j_begin; j0 < j_end; j0 += kWG) {
-    {
-      const float4 s = src[j0 + tid];
-      s_src[tid] = make_float4(s.x * pp.sig, s.y * pp.sig, s.z * pp.sig, lam[j0 + tid]);
-    }
-    __syncthreads();
-    float a[kAdjTPT][4];
+    for (int c = 0; c < 4; ++c) racc[k][c] = 0.0;
+
+  int64_t nsrc = npad - J * kSymTile;
+  if (nsrc > kSymTile) nsrc = kSymTile;
+  const int ngroups = (int)(nsrc / 64);
+  for (int grp = wave; grp < ngroups; grp += kSymSplit) {
+    const int64_t j = J * kSymTile + grp * 64 + lane;
+    const float4 s4 = src[j];
+    float sx = s4.x * pp.sig, sy = s4.y * pp.sig, sz = s4.z * pp.sig, sl = lam[j];
+    float col[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float acc[kSymTPT][4];
 #pragma unroll
-    for (int k = 0; k < kAdjTPT; ++k)
+    for (int k = 0; k < kSymTPT; ++k)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) a[k][c] = 0.0f;
-#pragma unroll 4
-    for (int jj = 0; jj < kWG; ++jj) {
-      const float4 s = s_src[jj];
+      for (int c = 0; c < 4; ++c) acc[k][c] = 0.0f;
+#pragma unroll 2
+    for (int step = 0; step < 64; ++step) {
 #pragma unroll
-      for (int k = 0; k < kAdjTPT; ++k) {
-        const float r2 = pair_r2<KIND>(xi[k] - s.x, yi[k] - s.y, zi[k] - s.z, pp.per);
+      for (int k = 0; k < kSymTPT; ++k) {
+        const float r2 = pair_r2<KIND>(xi[k] - sx, yi[k] - sy, zi[k] - sz, pp.per);
         const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
-        const float e1 = __builtin_amdgcn_exp2f(-t);
         const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
-        const float l1 = e1 * s.w;
-        const float l2 = e2 * s.w;
-        a[k][0] += l1;
-        a[k][1] += l2;
-        a[k][2] = fmaf(l1, t, a[k][2]);
-        a[k][3] = fmaf(l2, t, a[k][3]);
+        const float e1 = sym_pow<KIND>() == 0 ? __builtin_amdgcn_exp2f(-t) : ipow<sym_pow<KIND>()>(e2);
+        const float e1t = e1 * t;
+        const float e2t = e2 * t;
+        acc[k][0] = fmaf(e1, sl, acc[k][0]);
+        acc[k][1] = fmaf(e2, sl, acc[k][1]);
+        acc[k][2] = fmaf(e1t, sl, acc[k][2]);
+        acc[k][3] = fmaf(e2t, sl, acc[k][3]);
+        if (COLS) {
+          col[0] = fmaf(e1, li[k], col[0]);
+          col[1] = fmaf(e2, li[k], col[1]);
+          col[2] = fmaf(e1t, li[k], col[2]);
+          col[3] = fmaf(e2t, li[k], col[3]);
+        }
+      }
+      sx = wave_ror1(sx);
+      sy = wave_ror1(sy);
+      sz = wave_ror1(sz);
+      sl = wave_ror1(sl);
+      if (COLS) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) col[c] = wave_ror1(col[c]);
       }
     }
+#pragma unroll
+    for (int k = 0; k < kSymTPT; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) racc[k][c] += (double)acc[k][c];
+    if (COLS) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) part[((int64_t)c * nt + I) * npad + j] = (double)col[c];
+    }
+  }
+  if (kSymSplit > 1) {
+#pragma unroll
+    for (int k = 0; k < kSymTPT; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rowsum[wave][c][k * 64 + lane] = racc[k][c];
     __syncthreads();
+    for (int tt = threadIdx.x; tt < kSymTile; tt += kSymThreads) {
+      const int64_t t = I * kSymTile + tt;
+      if (t >= npad) continue;
 #pragma unroll
-    for (int k = 0; k < kAdjTPT; ++k)
+      for (int c = 0; c < 4; ++c) {
+        double sum = 0.0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[k][c] += (double)a[k][c];
+        for (int w = 0; w < kSymSplit; ++w) sum += rowsum[w][c][tt];
+        part[((int64_t)c * nt + J) * npad + t] = sum;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSymTPT; ++k) {
+      const int64_t t = I * kSymTile + k * 64 + lane;
+      if (t >= npad) continue;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) part[((int64_t)c * nt + J) * npad + t] = racc[k][c];
+    }
   }
-#pragma unroll
-  for (int k = 0; k < kAdjTPT; ++k) {
-    const int64_t t = tbase + tid + (int64_t)kWG * k;
-    if (t >= npad) continue;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) part[((int64_t)c * nsplit + split) * npad + t] = acc[k][c];
-  }
+}
+
+// One launch per reverse stage: nt (nt + 1) / 2 workgroups, nt = ceil(npad / kSymTile).
+template <int KIND>
+__global__ __launch_bounds__(kSymThreads) void k_sym_adjoint(const float4* __restrict__ src,
+                                                             const float* __restrict__ lam, int64_t npad, int nt,
+                                                             PairParams pp, double* __restrict__ part) {
+  __shared__ double rowsum[kSymSplit][4][kSymTile];
+  int64_t I, J;
+  sym_decode(blockIdx.x, &I, &J);
+  if (I == J)
+    sym_adj_tile<KIND, false>(src, lam, npad, nt, pp, part, I, J, rowsum);
+  else
+    sym_adj_tile<KIND, true>(src, lam, npad, nt, pp, part, I, J, rowsum);
 }
 
 // Coefficients turning the raw sums into dw/dp terms:
@@ -117,10 +173,11 @@ __global__ __launch_bounds__(kWG) void k_adj_init(const double* __restrict__ uba
   }
 }
 
-// One reverse stage (one thread per node j < n); see the file comment.  Block
+// One reverse stage (L threads per node j < n, see slot_sum); see the file comment.  Block
 // partial sums of the five parameter terms are added to pblk[block * 8 + c]
 // by thread 0 of the block (the launches are ordered on one stream, so the
 // accumulation order is fixed).
+template <int L>
 __global__ __launch_bounds__(kWG) void k_adj_combine(const double* __restrict__ part, int nsplit, int64_t n,
                                                      int64_t npad, int stage, double dt, AdjCoef co,
                                                      const double* __restrict__ qd, Firing fr,
@@ -128,16 +185,15 @@ __global__ __launch_bounds__(kWG) void k_adj_combine(const double* __restrict__ 
                                                      double* __restrict__ unbar, double* __restrict__ lam,
                                                      float* __restrict__ lam32, double* __restrict__ pblk) {
   __shared__ double red[5][kWG];
-  const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  int sub;
+  const int64_t j = group_index<L>(&sub);
   double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
+  double S[4] = {0.0, 0.0, 0.0, 0.0};
   if (j < n) {
-    double S[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      double s = 0.0;
-      for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)c * nsplit + sp) * npad + j];
-      S[c] = s;
-    }
+    for (int c = 0; c < 4; ++c) S[c] = slot_sum<L>(part + (int64_t)c * nsplit * npad, nsplit, 1, npad, 0, j, sub);
+  }
+  if (j < n && sub == 0) {
     const double z = co.Ae * S[0] - co.Ai * S[1];
     const double f = sigmoid(vs[j], fr.beta, fr.theta);
     const double fp = fr.beta * f * (1.0 - f);

@@ -750,6 +750,9 @@ struct AdjWorkspace {
   size_t bytes = 0;
 };
 
+// Workgroups of one reverse-stage combine (slot_lanes lanes per node).
+int64_t adj_blocks(int64_t n, int nsplit) { return ceil_div(n * slot_lanes(nsplit), kWG); }
+
 AdjWorkspace carve_adjoint(void* base, const ProblemView& pv, int64_t ckpt_every) {
   AdjWorkspace a;
   a.fwd = carve(base, pv, 1, NFR_FORM_ONTHEFLY_FP32, true);
@@ -760,8 +763,8 @@ AdjWorkspace carve_adjoint(void* base, const ProblemView& pv, int64_t ckpt_every
     off += align256(bytes);
     return r;
   };
-  const int nsplit = plan_otf(pv.npad, 1).nsplit;
-  const int64_t nblocks = ceil_div(pv.n, kWG);
+  const int nsplit = (int)sym_tiles(pv.npad);
+  const int64_t nblocks = adj_blocks(pv.n, nsplit);
   a.store = reinterpret_cast<double*>(take(size_t(ckpt_every) * 4 * pv.n * sizeof(double)));
   a.useg = reinterpret_cast<double*>(take(size_t(pv.n) * sizeof(double)));
   a.lam = reinterpret_cast<double*>(take(size_t(pv.n) * sizeof(double)));
@@ -818,9 +821,10 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
   const Firing fr = firing_of(*firing);
   const PairParams pp = pair_params(*kernel, pv);
   const AdjCoef co = adj_coef(*kernel);
-  const OtfPlan pl = plan_otf(pv.npad, 1);
+  const int nt = (int)sym_tiles(pv.npad);
+  const int adj_code = kind_code(*kernel, pv) | (sym_pow_code(*kernel) << 2);
   const int64_t n = pv.n;
-  const int64_t nblocks = ceil_div(n, kWG);
+  const int64_t nblocks = adj_blocks(n, nt);
   const size_t vbytes = size_t(n) * sizeof(double);
   const int form = NFR_FORM_ONTHEFLY_FP32;
 
@@ -847,16 +851,20 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
     for (int64_t l = len - 1; l >= 0; --l) {
       for (int stage = 4; stage >= 1; --stage) {
         if ((st = timing_mark(ctx))) return st;
-        const dim3 agrid((unsigned)pl.tiles, (unsigned)pl.nsplit);
-        switch (kind_code(*kernel, pv)) {
-          case 0: hipLaunchKernelGGL(k_otf_adjoint<0>, agrid, dim3(kWG), 0, s, pv.src, a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart); break;
-          case 1: hipLaunchKernelGGL(k_otf_adjoint<1>, agrid, dim3(kWG), 0, s, pv.src, a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart); break;
-          case 2: hipLaunchKernelGGL(k_otf_adjoint<2>, agrid, dim3(kWG), 0, s, pv.src, a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart); break;
-          default: hipLaunchKernelGGL(k_otf_adjoint<3>, agrid, dim3(kWG), 0, s, pv.src, a.lam32, pv.npad, pl.chunk, pl.nsplit, pp, a.apart); break;
+        const dim3 agrid((unsigned)sym_pairs(nt));
+#define NFR_ADJ_CASE(K) \
+  case K: hipLaunchKernelGGL(k_sym_adjoint<K>, agrid, dim3(kSymThreads), 0, s, pv.src, a.lam32, pv.npad, nt, pp, a.apart); break;
+        switch (adj_code) {
+          NFR_ADJ_CASE(0) NFR_ADJ_CASE(1) NFR_ADJ_CASE(2) NFR_ADJ_CASE(3)
+          NFR_ADJ_CASE(4) NFR_ADJ_CASE(5) NFR_ADJ_CASE(6) NFR_ADJ_CASE(7)
+          NFR_ADJ_CASE(8) NFR_ADJ_CASE(9) NFR_ADJ_CASE(10) NFR_ADJ_CASE(11)
+          NFR_ADJ_CASE(12) NFR_ADJ_CASE(13) NFR_ADJ_CASE(14) NFR_ADJ_CASE(15)
+          default: return fail(NFR_ERR_INTERNAL, "no adjoint kernel for this kernel code");
         }
+#undef NFR_ADJ_CASE
         NFR_HIP_LAUNCH();
         if ((st = timing_mark(ctx))) return st;
-        hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)nblocks), dim3(kWG), 0, s, a.apart, pl.nsplit, n, pv.npad,
+        NFR_LAUNCH_SLOTS(k_adj_combine, nt, n, s, a.apart, nt, n, pv.npad,
                            stage, dt, co, pv.q, fr, a.store + (l * 4 + stage - 1) * n, a.ubar, a.unbar, a.lam,
                            a.lam32, a.pblk);
         NFR_HIP_LAUNCH();
