@@ -189,9 +189,10 @@ size_t nfr_w_bytes(int64_t n, int form);
  * weight) for targets i < n and sources j < npad into `w_dev` (caller-owned,
  * >= nfr_w_bytes(n, form), 256-byte aligned).  Rows are targets, row stride
  * npad elements.  For W_BF16X3 / W_FP16X3 the buffer holds a 256-byte header
- * then the hi matrix then the lo matrix, each npad x npad (rows >= n zero)
- * stored as 32 x 16 tiles in matrix-core operand order (an opaque layout:
- * only nfr_apply / nfr_integrate read it);
+ * then the hi and lo matrices, each npad x npad (rows >= n zero), as 32 x 16
+ * tiles in matrix-core operand order, hi and lo tiles interleaved in groups
+ * of four row blocks (an opaque layout: only nfr_apply / nfr_integrate read
+ * it);
  * W is scaled by 2^s, s = 14 - ceil(log2((|A_e| + |A_i|) max|q|)) for FP16
  * (0 for BF16), so that FP16 neither overflows nor underflows; s is stored in
  * the header and undone when W is applied. */
