@@ -52,84 +52,186 @@ __global__ __launch_bounds__(kWG) void k_quad_centroids(const double* __restrict
 
 // ------------------------------------------------------------------ k nearest nodes
 
-constexpr int kKnnWaves = 4;   // waves per workgroup
-constexpr int kKnnC = 4;       // centroids per wave
-constexpr int kKnnTile = 256;  // nodes staged in LDS per round
+// Nodes are binned into a uniform grid of cubic cells; a centroid's search
+// visits the cells in Chebyshev rings r = 0, 1, 2, ... around its own cell and
+// stops once its k-th key is below the squared distance from the centroid to
+// the boundary of the rings visited (every node outside lies beyond it; a
+// relative margin of 1e-12 covers the rounding of the binning and of that
+// bound).  The result is the exact k smallest (squared distance, index), the
+// same as a full scan.
+
+struct QuadGrid {
+  double ox, oy, oz, h;   // origin (lower corner) and cell size
+  int nx, ny, nz;
+};
+
+// One workgroup of kWG threads: bounding box of the nodes, then (thread 0) a
+// grid with about 4 nodes per cell of the box's volume (a surface fills a
+// small share of its box, so occupied cells hold a few tens of nodes), at most
+// max_cells cells.
+__global__ __launch_bounds__(kWG) void k_quad_grid(const double* __restrict__ xyz, int64_t n, int64_t max_cells,
+                                                   QuadGrid* __restrict__ grid) {
+  __shared__ double s_lo[3][kWG], s_hi[3][kWG];
+  double lo[3] = {xyz[0], xyz[1], xyz[2]}, hi[3] = {xyz[0], xyz[1], xyz[2]};
+  for (int64_t i = threadIdx.x; i < n; i += kWG)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], xyz[3 * i + d]);
+      hi[d] = fmax(hi[d], xyz[3 * i + d]);
+    }
+  for (int d = 0; d < 3; ++d) {
+    s_lo[d][threadIdx.x] = lo[d];
+    s_hi[d][threadIdx.x] = hi[d];
+  }
+  __syncthreads();
+  for (int w = kWG / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int d = 0; d < 3; ++d) {
+        s_lo[d][threadIdx.x] = fmin(s_lo[d][threadIdx.x], s_lo[d][threadIdx.x + w]);
+        s_hi[d][threadIdx.x] = fmax(s_hi[d][threadIdx.x], s_hi[d][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double ext[3], emax = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = s_hi[d][0] - s_lo[d][0];
+    emax = fmax(emax, ext[d]);
+  }
+  if (!(emax > 0.0)) emax = 1.0;
+  // volume, with flat directions given a thousandth of the largest extent
+  double h = cbrt(fmax(ext[0], emax * 1e-3) * fmax(ext[1], emax * 1e-3) * fmax(ext[2], emax * 1e-3) * 4.0 / (double)n);
+  int dim[3];
+  for (;;) {
+    int64_t cells = 1;
+    for (int d = 0; d < 3; ++d) {
+      dim[d] = (int)fmin(floor(ext[d] / h) + 1.0, 2048.0);
+      cells *= dim[d];
+    }
+    if (cells <= max_cells) break;
+    h *= 1.25;
+  }
+  grid->ox = s_lo[0][0];
+  grid->oy = s_lo[1][0];
+  grid->oz = s_lo[2][0];
+  grid->h = h;
+  grid->nx = dim[0];
+  grid->ny = dim[1];
+  grid->nz = dim[2];
+}
+
+__device__ inline int quad_cell_coord(double x, double o, double h, int dim) {
+  const double c = floor((x - o) / h);
+  return c < 0.0 ? 0 : (c >= (double)dim ? dim - 1 : (int)c);
+}
+
+__device__ inline int64_t quad_cell_of(const QuadGrid& g, double x, double y, double z) {
+  const int cx = quad_cell_coord(x, g.ox, g.h, g.nx);
+  const int cy = quad_cell_coord(y, g.oy, g.h, g.ny);
+  const int cz = quad_cell_coord(z, g.oz, g.h, g.nz);
+  return ((int64_t)cz * g.ny + cy) * g.nx + cx;
+}
+
+__global__ __launch_bounds__(kWG) void k_quad_bin_count(const double* __restrict__ xyz, int64_t n,
+                                                        const QuadGrid* __restrict__ grid, int* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(&cnt[quad_cell_of(*grid, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2])], 1);
+}
+
+// Node i goes to a free place of its cell's list (order inside a cell is
+// irrelevant: the ranking key is a total order).
+__global__ __launch_bounds__(kWG) void k_quad_bin_fill(const double* __restrict__ xyz, int64_t n,
+                                                       const QuadGrid* __restrict__ grid,
+                                                       const int64_t* __restrict__ start, int* __restrict__ cursor,
+                                                       int* __restrict__ nodes) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c = quad_cell_of(*grid, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+  nodes[start[c] + atomicAdd(&cursor[c], 1)] = (int)i;
+}
 
 __device__ inline bool key_less(double d, int i, double d2, int i2) { return d < d2 || (d == d2 && i < i2); }
 
 // st[t*k + r], r < k: the k nodes with the smallest (squared distance, index)
-// to centroid t, in increasing order.  Lane r of a wave holds entry r of each
-// of its kKnnC sorted lists; a candidate below a list's k-th key is inserted
-// by a ballot (its rank) and a one-lane shift.  Requires k <= 64 and k <= n.
-__global__ __launch_bounds__(kKnnWaves * 64) void k_quad_knn(const double* __restrict__ xyz, int64_t n,
-                                                             const double* __restrict__ cen, int64_t ntri, int k,
-                                                             int* __restrict__ st) {
-  __shared__ double s_x[kKnnTile], s_y[kKnnTile], s_z[kKnnTile];
+// to centroid t, in increasing order; one wave per centroid.  Lane r holds
+// entry r of the sorted list; a candidate below the k-th key is inserted by a
+// ballot (its rank) and a one-lane shift.  cnt / start: nodes per cell and
+// their offsets into `nodes`.  Requires k <= 64 and k <= n.
+__global__ __launch_bounds__(kWG) void k_quad_knn(const double* __restrict__ xyz, const QuadGrid* __restrict__ grid_p,
+                                                  const int* __restrict__ cnt, const int64_t* __restrict__ start,
+                                                  const int* __restrict__ nodes, const double* __restrict__ cen,
+                                                  int64_t ntri, int k, int* __restrict__ st) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t t0 = ((int64_t)blockIdx.x * kKnnWaves + wave) * kKnnC;
-  double cx[kKnnC], cy[kKnnC], cz[kKnnC], ld[kKnnC], thr[kKnnC];
-  int li[kKnnC], thr_i[kKnnC];
-#pragma unroll
-  for (int c = 0; c < kKnnC; ++c) {
-    const int64_t t = t0 + c < ntri ? t0 + c : ntri - 1;
-    cx[c] = cen[3 * t];
-    cy[c] = cen[3 * t + 1];
-    cz[c] = cen[3 * t + 2];
-    ld[c] = __builtin_inf();
-    li[c] = 0x7fffffff;
-    thr[c] = __builtin_inf();
-    thr_i[c] = 0x7fffffff;
-  }
-  for (int64_t j0 = 0; j0 < n; j0 += kKnnTile) {
-    __syncthreads();
-    {
-      const int64_t j = j0 + threadIdx.x;
-      if (j < n) {
-        s_x[threadIdx.x] = xyz[3 * j];
-        s_y[threadIdx.x] = xyz[3 * j + 1];
-        s_z[threadIdx.x] = xyz[3 * j + 2];
-      }
-    }
-    __syncthreads();
-    for (int sub = 0; sub < kKnnTile; sub += 64) {
-      const int64_t j = j0 + sub + lane;
-      const bool valid = j < n;
-      const double px = valid ? s_x[sub + lane] : 0.0;
-      const double py = valid ? s_y[sub + lane] : 0.0;
-      const double pz = valid ? s_z[sub + lane] : 0.0;
-      const int ji = (int)j;
-#pragma unroll
-      for (int c = 0; c < kKnnC; ++c) {
-        const double key = quad_sqdist(px, py, pz, cx[c], cy[c], cz[c]);
-        uint64_t mask = __ballot(valid && key_less(key, ji, thr[c], thr_i[c]));
-        while (mask) {
-          const int src = __builtin_ctzll(mask);
-          mask &= mask - 1;
-          const double cd = __shfl(key, src);
-          const int ci = (int)(j0 + sub + src);
-          if (!key_less(cd, ci, thr[c], thr_i[c])) continue;
-          const bool before = lane < k && key_less(ld[c], li[c], cd, ci);
-          const int pos = __popcll(__ballot(before));
-          const double up_d = __shfl_up(ld[c], 1);
-          const int up_i = __shfl_up(li[c], 1);
-          if (lane == pos) {
-            ld[c] = cd;
-            li[c] = ci;
-          } else if (lane > pos && lane < k) {
-            ld[c] = up_d;
-            li[c] = up_i;
+  const int64_t t = (int64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+  if (t >= ntri) return;
+  const QuadGrid g = *grid_p;
+  const double cx = cen[3 * t], cy = cen[3 * t + 1], cz = cen[3 * t + 2];
+  const int ix = quad_cell_coord(cx, g.ox, g.h, g.nx);
+  const int iy = quad_cell_coord(cy, g.oy, g.h, g.ny);
+  const int iz = quad_cell_coord(cz, g.oz, g.h, g.nz);
+  double ld = __builtin_inf(), thr = __builtin_inf();
+  int li = 0x7fffffff, thr_i = 0x7fffffff;
+  const int rmax = max(max(g.nx, g.ny), g.nz);
+  for (int r = 0; r <= rmax; ++r) {
+    for (int dz = -r; dz <= r; ++dz) {
+      const int z = iz + dz;
+      if (z < 0 || z >= g.nz) continue;
+      for (int dy = -r; dy <= r; ++dy) {
+        const int y = iy + dy;
+        if (y < 0 || y >= g.ny) continue;
+        const bool face = dz == -r || dz == r || dy == -r || dy == r;
+        for (int dx = -r; dx <= r; dx += (face || r == 0) ? 1 : 2 * r) {   // only the ring's shell
+          const int x = ix + dx;
+          if (x < 0 || x >= g.nx) continue;
+          const int64_t c = ((int64_t)z * g.ny + y) * g.nx + x;
+          const int64_t c0 = start[c];
+          const int m = cnt[c];
+          for (int b = 0; b < m; b += 64) {
+            const bool valid = b + lane < m;
+            const int j = valid ? nodes[c0 + b + lane] : 0;
+            const double key = valid ? quad_sqdist(xyz[3 * (int64_t)j], xyz[3 * (int64_t)j + 1],
+                                                   xyz[3 * (int64_t)j + 2], cx, cy, cz)
+                                     : 0.0;
+            uint64_t mask = __ballot(valid && key_less(key, j, thr, thr_i));
+            while (mask) {
+              const int src = __builtin_ctzll(mask);
+              mask &= mask - 1;
+              const double cd = __shfl(key, src);
+              const int ci = __shfl(j, src);
+              if (!key_less(cd, ci, thr, thr_i)) continue;
+              const bool before = lane < k && key_less(ld, li, cd, ci);
+              const int pos = __popcll(__ballot(before));
+              const double up_d = __shfl_up(ld, 1);
+              const int up_i = __shfl_up(li, 1);
+              if (lane == pos) {
+                ld = cd;
+                li = ci;
+              } else if (lane > pos && lane < k) {
+                ld = up_d;
+                li = up_i;
+              }
+              thr = __shfl(ld, k - 1);
+              thr_i = __shfl(li, k - 1);
+            }
           }
-          thr[c] = __shfl(ld[c], k - 1);
-          thr_i[c] = __shfl(li[c], k - 1);
         }
       }
     }
+    // distance from the centroid to the boundary of rings 0..r (sides with no
+    // cells beyond them do not count)
+    double bound = __builtin_inf();
+    const double o[3] = {g.ox, g.oy, g.oz};
+    const double p[3] = {cx, cy, cz};
+    const int ic[3] = {ix, iy, iz};
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    for (int d = 0; d < 3; ++d) {
+      if (ic[d] - r > 0) bound = fmin(bound, p[d] - (o[d] + (double)(ic[d] - r) * g.h));
+      if (ic[d] + r < dims[d] - 1) bound = fmin(bound, (o[d] + (double)(ic[d] + r + 1) * g.h) - p[d]);
+    }
+    if (bound == __builtin_inf()) break;                                   // every cell visited
+    if (thr_i != 0x7fffffff && bound > 0.0 && thr < bound * bound * (1.0 - 1e-12)) break;
   }
-#pragma unroll
-  for (int c = 0; c < kKnnC; ++c)
-    if (t0 + c < ntri && lane < k) st[(t0 + c) * k + lane] = li[c];
+  if (lane < k) st[t * k + lane] = li;
 }
 
 // ------------------------------------------------------------------ projection points

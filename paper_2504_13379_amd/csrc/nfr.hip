@@ -1358,8 +1358,16 @@ struct QuadWorkspace {
   int64_t* off = nullptr;
   int64_t* bsum = nullptr;
   int* list = nullptr;
+  QuadGrid* grid = nullptr;   // node grid of the k-nearest search
+  int* gcnt = nullptr;        // nodes per cell
+  int* gcursor = nullptr;
+  int64_t* gstart = nullptr;  // first node of each cell in gnodes
+  int64_t* gbsum = nullptr;
+  int* gnodes = nullptr;      // node indices grouped by cell
   size_t bytes = 0;
 };
+
+int64_t quad_max_cells(int64_t n) { return 2 * n + 1; }
 
 QuadWorkspace carve_quad(void* base, int64_t n, int64_t ntri, int k) {
   QuadWorkspace w;
@@ -1383,6 +1391,13 @@ QuadWorkspace carve_quad(void* base, int64_t n, int64_t ntri, int k) {
   w.off = static_cast<int64_t*>(take(size_t(n) * sizeof(int64_t)));
   w.bsum = static_cast<int64_t*>(take(size_t(ceil_div(n, kWG)) * sizeof(int64_t)));
   w.list = static_cast<int*>(take(tk * sizeof(int)));
+  const int64_t mc = quad_max_cells(n);
+  w.grid = static_cast<QuadGrid*>(take(sizeof(QuadGrid)));
+  w.gcnt = static_cast<int*>(take(size_t(mc) * sizeof(int)));
+  w.gcursor = static_cast<int*>(take(size_t(mc) * sizeof(int)));
+  w.gstart = static_cast<int64_t*>(take(size_t(mc) * sizeof(int64_t)));
+  w.gbsum = static_cast<int64_t*>(take(size_t(ceil_div(mc, kWG)) * sizeof(int64_t)));
+  w.gnodes = static_cast<int*>(take(size_t(n) * sizeof(int)));
   w.bytes = off;
   return w;
 }
@@ -1458,12 +1473,24 @@ int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const d
     NFR_HIP(hipMemcpyAsync(w.nbr, nbr.data(), 3 * size_t(ntri) * sizeof(int), hipMemcpyHostToDevice, s));
   NFR_HIP(hipMemsetAsync(w.cnt, 0, size_t(n) * sizeof(int), s));
   NFR_HIP(hipMemsetAsync(w.cursor, 0, size_t(n) * sizeof(int), s));
+  const int64_t mc = quad_max_cells(n);
+  NFR_HIP(hipMemsetAsync(w.gcnt, 0, size_t(mc) * sizeof(int), s));
+  NFR_HIP(hipMemsetAsync(w.gcursor, 0, size_t(mc) * sizeof(int), s));
   const unsigned tb = (unsigned)ceil_div(ntri, kWG);
   hipLaunchKernelGGL(k_quad_centroids, dim3(tb), dim3(kWG), 0, s, xyz_dev, w.tri, ntri, w.cen, w.nrm_tri);
   hipLaunchKernelGGL(k_quad_proj, dim3(tb), dim3(kWG), 0, s, xyz_dev, w.tri, w.nbr, w.cen, w.nrm_tri, ntri,
                      star_shaped ? 1 : 0, 1e8, proj);
-  hipLaunchKernelGGL(k_quad_knn, dim3((unsigned)ceil_div(ntri, kKnnWaves * kKnnC)), dim3(kKnnWaves * 64), 0, s,
-                     xyz_dev, n, w.cen, ntri, k, stn);
+  // k nearest nodes: bin the nodes into a grid, then search rings of cells
+  const unsigned nbn = (unsigned)ceil_div(n, kWG);
+  const int64_t nbc = ceil_div(mc, kWG);
+  hipLaunchKernelGGL(k_quad_grid, dim3(1), dim3(kWG), 0, s, xyz_dev, n, mc, w.grid);
+  hipLaunchKernelGGL(k_quad_bin_count, dim3(nbn), dim3(kWG), 0, s, xyz_dev, n, w.grid, w.gcnt);
+  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nbc), dim3(kWG), 0, s, w.gcnt, mc, w.gbsum);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kWG), 0, s, w.gbsum, nbc);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nbc), dim3(kWG), 0, s, w.gcnt, mc, w.gbsum, w.gstart);
+  hipLaunchKernelGGL(k_quad_bin_fill, dim3(nbn), dim3(kWG), 0, s, xyz_dev, n, w.grid, w.gstart, w.gcursor, w.gnodes);
+  hipLaunchKernelGGL(k_quad_knn, dim3((unsigned)ceil_div(ntri, kWG / 64)), dim3(kWG), 0, s, xyz_dev, w.grid, w.gcnt,
+                     w.gstart, w.gnodes, w.cen, ntri, k, stn);
   const size_t lds = (size_t(k + 6) * (k + 7) + 2 * size_t(k)) * sizeof(double);
   hipLaunchKernelGGL(k_quad_elements, dim3((unsigned)ntri), dim3(64), lds, s, xyz_dev, nrm_dev, w.tri, w.cen,
                      w.nrm_tri, proj, stn, n, ntri, k, w.wE);
