@@ -2,8 +2,8 @@
 // and state counts) advanced together, one persistent pair-sum launch and one
 // combine launch per RK4 stage for the whole batch.
 //
-// Work items are (problem, target tile of kWG*4 targets, source chunk, state
-// block); they are sorted by decreasing cost on the host and a fixed grid of
+// Work items are (problem, target tile of kWG * otf_tpt(bs) targets, source
+// chunk, state block); they are sorted by decreasing cost on the host and a fixed grid of
 // workgroups walks them round-robin, so every stage is a single launch whose
 // largest items start first.
 #pragma once
@@ -37,21 +37,26 @@ struct BatchItem {
   int sb;
 };
 
-constexpr int kBatchTPT = 4;
+// State block of a problem with B states (1, 4 or 16; see otf_tpt for the
+// targets per thread that go with it).
+__host__ __device__ constexpr int batch_bs(int B) { return B == 1 ? 1 : (B <= 4 ? 4 : 16); }
 
 template <int KIND>
 __device__ inline void batch_item(const BatchProblemDev& P, const BatchItem& w, float4* s_src, float (*s_g)[kWG]) {
   if (P.bs == 1)
-    otf_tile<KIND, kBatchTPT, 1>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb, s_src, s_g);
+    otf_tile<KIND, otf_tpt(1), 1>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb, s_src, s_g);
+  else if (P.bs == 4)
+    otf_tile<KIND, otf_tpt(4), 4>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 4, s_src,
+                                  s_g);
   else
-    otf_tile<KIND, kBatchTPT, 4>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 4, s_src,
-                                 s_g);
+    otf_tile<KIND, otf_tpt(16), 16>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 16,
+                                    s_src, s_g);
 }
 
 __global__ __launch_bounds__(kWG) void k_batch_pairs(const BatchProblemDev* __restrict__ probs,
                                                      const BatchItem* __restrict__ items, int nitems) {
   __shared__ float4 s_src[kWG];
-  __shared__ float s_g[4][kWG];
+  __shared__ float s_g[16][kWG];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const BatchItem w = items[it];
     const BatchProblemDev& P = probs[w.p];

@@ -72,6 +72,9 @@ __global__ __launch_bounds__(kWG) void k_source_prep(const double* __restrict__ 
 // their g values and read back as broadcasts.  Each thread sums one LDS tile
 // of kWG sources in FP32 (e and i parts separately), then folds the tile sum
 // into FP64 accumulators: A_e * sum_e - A_i * sum_i.
+// Targets per thread for a block of BS states (TPT x BS accumulators per thread).
+__host__ __device__ constexpr int otf_tpt(int bs) { return bs <= 4 ? 4 : (bs == 8 ? 2 : 1); }
+
 template <int KIND, int TPT, int BS>
 __device__ inline void otf_tile(const float4* __restrict__ src, const float* __restrict__ g, int64_t npad, int B,
                                 int64_t chunk, const PairParams& pp, double* __restrict__ part, int64_t tile,

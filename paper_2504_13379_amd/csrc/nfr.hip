@@ -137,7 +137,6 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------- plans
 
-constexpr int kOtfTPT = 4;
 constexpr int64_t kTargetWGs = 1024;   // about four workgroups per compute unit
 
 struct OtfPlan {
@@ -146,11 +145,16 @@ struct OtfPlan {
   int nsplit = 1;
 };
 
+// States per block of the on-the-fly pair sum: one kernel evaluation serves
+// every state of a block, so larger blocks cost fewer evaluations per pair
+// interaction; targets per thread shrink as blocks grow (registers).
+int otf_bs(int B) { return B == 1 ? 1 : (B == 2 ? 2 : (B <= 4 ? 4 : (B <= 8 ? 8 : 16))); }
+
 OtfPlan plan_otf(int64_t npad, int B) {
   OtfPlan p;
-  p.bs = B == 1 ? 1 : (B == 2 ? 2 : 4);
+  p.bs = otf_bs(B);
   p.nsb = (int)ceil_div(B, p.bs);
-  p.tiles = ceil_div(npad, (int64_t)kWG * kOtfTPT);
+  p.tiles = ceil_div(npad, (int64_t)kWG * otf_tpt(p.bs));
   int64_t want = ceil_div(kTargetWGs, p.tiles * p.nsb);
   const int64_t max_split = npad / kWG;
   if (want < 1) want = 1;
@@ -233,11 +237,15 @@ void launch_otf_kind(const ProblemView& pv, const PairParams& pp, int B, const f
                      const OtfPlan& pl, hipStream_t s) {
   dim3 grid((unsigned)pl.tiles, (unsigned)pl.nsplit, (unsigned)pl.nsb);
   if (pl.bs == 1)
-    hipLaunchKernelGGL((k_otf_pair_sum<KIND, kOtfTPT, 1>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
+    hipLaunchKernelGGL((k_otf_pair_sum<KIND, otf_tpt(1), 1>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
   else if (pl.bs == 2)
-    hipLaunchKernelGGL((k_otf_pair_sum<KIND, kOtfTPT, 2>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
+    hipLaunchKernelGGL((k_otf_pair_sum<KIND, otf_tpt(2), 2>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
+  else if (pl.bs == 4)
+    hipLaunchKernelGGL((k_otf_pair_sum<KIND, otf_tpt(4), 4>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
+  else if (pl.bs == 8)
+    hipLaunchKernelGGL((k_otf_pair_sum<KIND, otf_tpt(8), 8>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
   else
-    hipLaunchKernelGGL((k_otf_pair_sum<KIND, kOtfTPT, 4>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
+    hipLaunchKernelGGL((k_otf_pair_sum<KIND, otf_tpt(16), 16>), grid, dim3(kWG), 0, s, pv.src, g, pv.npad, B, pl.chunk, pp, part);
 }
 
 void launch_gemv(const ProblemView& pv, const float* W, int B, const float* G, double* part, const GemvPlan& pl,
@@ -909,8 +917,8 @@ struct BatchLayout {
 
 int64_t batch_items_for(const nfr_problem* p, int B, int64_t chunk) {
   const int64_t npad = p->view.npad;
-  const int bs = B == 1 ? 1 : 4;
-  return ceil_div(npad, (int64_t)kWG * kBatchTPT) * ceil_div(npad, chunk) * ceil_div(B, bs);
+  const int bs = batch_bs(B);
+  return ceil_div(npad, (int64_t)kWG * otf_tpt(bs)) * ceil_div(npad, chunk) * ceil_div(B, bs);
 }
 
 BatchLayout batch_layout(const nfr_batch* b) {
@@ -954,7 +962,7 @@ void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_
     d.n = pv.n;
     d.npad = pv.npad;
     d.B = Bp;
-    d.bs = Bp == 1 ? 1 : 4;
+    d.bs = batch_bs(Bp);
     d.kind = kind_code(b->kernels[p], pv);
     d.chunk = b->chunk;
     d.nsplit = (int)ceil_div(pv.npad, b->chunk);
@@ -969,12 +977,13 @@ void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_
     d.gel_off = goff;
     eoff += pv.n * Bp;
     goff += pv.npad * Bp;
-    const int64_t tiles = ceil_div(pv.npad, (int64_t)kWG * kBatchTPT);
+    const int tpt = otf_tpt(d.bs);
+    const int64_t tiles = ceil_div(pv.npad, (int64_t)kWG * tpt);
     const int sbs = (int)ceil_div(Bp, d.bs);
     for (int64_t t = 0; t < tiles; ++t)
       for (int sp = 0; sp < d.nsplit; ++sp)
         for (int sb = 0; sb < sbs; ++sb) {
-          const double tg = (double)std::min<int64_t>(kWG * kBatchTPT, pv.npad - t * kWG * kBatchTPT);
+          const double tg = (double)std::min<int64_t>(kWG * tpt, pv.npad - t * kWG * tpt);
           const double sc = (double)std::min<int64_t>(b->chunk, pv.npad - sp * b->chunk);
           const double st = (double)std::min(d.bs, Bp - sb * d.bs);
           const double per_pair = ((d.kind & 1) ? 1.3 : 1.0) + ((d.kind & 2) ? 0.2 : 0.0) + 0.25 * (st - 1.0);
