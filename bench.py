@@ -274,10 +274,22 @@ def batch_leg(P, torch, args):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     pair_ints = sum(4.0 * args.batch_rk4_steps * float(w.n) ** 2 * w.b for w in ws_list)
+    # algorithmic slots of the (one-sided) pair kernel per stage: per target-source pair and
+    # state block one Gaussian evaluation (3 sub + 3 for r^2 + rho t + 2 exp2 = 15 slots),
+    # plus 2 FMAs per state; blocks of 1, 4 or 16 states
+    slots = 0.0
+    for w in ws_list:
+        npad = -(-w.n // 256) * 256
+        bs = 1 if w.b == 1 else (4 if w.b <= 4 else 16)
+        slots += float(npad) ** 2 * (-(-w.b // bs) * (7 + 2 * TRANS_COST) + 2 * w.b)
+    slots *= 4.0 * args.batch_rk4_steps
     chunk, wgs = batch.config
     return {"workload": "48 problems, N log-uniform [1000, 40000], sphere/torus/ellipsoid/bumpy, Gauss Mexican hat, "
                         "B in {1,4,16}, RK4 dt=0.05 x %d steps, graph-captured" % args.batch_rk4_steps,
             "value": pair_ints / (t1 - t0), "unit": "pair-interactions/s", "ms_per_integration": (t1 - t0) * 1e3,
+            "roofline": {"bound": "alu", "achieved": slots / (t1 - t0) / 1e12, "peak": VALU_LANES_PER_S / 1e12,
+                         "unit": "Tlane-op/s", "frac": slots / (t1 - t0) / VALU_LANES_PER_S,
+                         "note": "whole integration time (pair kernel, combine, launch gaps)"},
             "tuned": {"chunk": chunk, "wgs_per_cu": wgs, "best_stage_ms": best, "tune_ms": t_tune * 1e3},
             "launches_per_rk4_step": 1}
 
@@ -319,11 +331,21 @@ def adjoint_leg(P, torch, args):
     P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot)))
     L.nfr_context_set_timing(ctx.handle, 0)
     evals = 3 * 4.0 * w.steps * float(w.n) ** 2        # forward, segment recompute, adjoint sweep
+    # algorithmic slots: forward and recompute on the symmetric kernel, the adjoint sweep on its
+    # four-channel symmetric transpose kernel (rho t multiply kept, e1 = e2^m, e*t products, 8 FMAs)
+    npad = -(-w.n // 256) * 256
+    m = sym_pow(w.kernel_kind, w.kernel[1], w.kernel[3])
+    trans = (2 if w.kernel_kind == 0 else 3) - (1 if m else 0)
+    adj_slots = 7 + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 2 + 8
+    slots = 4.0 * w.steps * float(npad) ** 2 / 2 * (2 * slots_per_unordered_pair(w.kernel_kind, m) + adj_slots)
     return {"workload": "torus N=16384, exp Mexican hat, RK4 dt=0.02 x %d steps, checkpoints every %d, "
                         "loss |u(T)|^2" % (w.steps, every),
             "value": evals / (t1 - t0), "unit": "pair-evaluations/s (forward + recompute + adjoint)",
             "ms_forward_plus_gradient": (t1 - t0) * 1e3, "pair_kernel_launches": int(launches.value),
             "pair_kernel_avg_ms": tot.value / max(1, launches.value),
+            "roofline": {"bound": "alu", "achieved": slots / (tot.value * 1e-3) / 1e12, "peak": VALU_LANES_PER_S / 1e12,
+                         "unit": "Tlane-op/s", "frac": slots / (tot.value * 1e-3) / VALU_LANES_PER_S,
+                         "note": "pair kernels only (forward, recompute, adjoint sweep)"},
             "grad_norm_u0": float(gu.norm()), "grad_params": [float(v) for v in gp]}
 
 
