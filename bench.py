@@ -296,7 +296,8 @@ def batch_leg(P, torch, args):
 
 def adjoint_leg(P, torch, args):
     """Torus adjoint workload: N = 16384, RK4 dt = 0.02, checkpoints every 40 steps;
-    forward with checkpoints + discrete adjoint (gradients w.r.t. u0 and 5 parameters)."""
+    forward with checkpoints + discrete adjoint (gradients w.r.t. u0 and 5 parameters),
+    timed with graph replay on a side stream."""
     import ctypes
 
     import numpy as np
@@ -304,14 +305,16 @@ def adjoint_leg(P, torch, args):
     from workloads import configs as C
     w = C.torus_adjoint(16384, args.adjoint_rk4_steps)
     q = C.area_share_weights(w.surface)
-    ctx = P.Context(0)
-    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
-    u0 = torch.from_numpy(w.u0[0].copy()).cuda()
-    target = torch.zeros_like(u0)
+    stream = torch.cuda.Stream()
     params = torch.tensor(list(w.kernel) + [float(w.theta[0])], dtype=torch.float64)
     every = w.extra["ckpt_every"]
 
-    def run():
+    def setup(ctx):
+        prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
+        u0 = torch.from_numpy(w.u0[0].copy()).cuda()
+        return prob, u0, torch.zeros_like(u0)
+
+    def run(prob, u0, target):
         x0 = u0.clone().requires_grad_(True)
         pp = params.clone().requires_grad_(True)
         uT = P.NeuralFieldRK4.apply(x0, pp, prob, w.kernel_kind, w.beta, w.dt, w.steps, every)
@@ -319,14 +322,25 @@ def adjoint_leg(P, torch, args):
         loss.backward()
         return x0.grad, pp.grad
 
-    run()
-    torch.cuda.synchronize()
+    # timed: a context with its own stream (forward steps and adjoint segments replay graphs)
+    with torch.cuda.stream(stream):
+        gctx = P.Context(0, stream)
+        gargs = setup(gctx)
+        run(*gargs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gu, gp = run(*gargs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    # pair-kernel durations: HIP events around every launch of one eager run on the null stream
     L = P.lib()
-    L.nfr_context_set_timing(ctx.handle, 1)
-    t0 = time.perf_counter()
-    gu, gp = run()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    null = torch.cuda.default_stream()
+    with torch.cuda.stream(null):
+        ctx = P.Context(0, null)
+        eargs = setup(ctx)
+        L.nfr_context_set_timing(ctx.handle, 1)
+        run(*eargs)
+        torch.cuda.synchronize()
     launches, tot = ctypes.c_int64(), ctypes.c_double()
     P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot)))
     L.nfr_context_set_timing(ctx.handle, 0)

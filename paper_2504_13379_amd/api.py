@@ -322,7 +322,8 @@ class NeuralFieldRK4(torch.autograd.Function):
     """u(T) = RK4^steps(u0; A_e, s_e, A_i, s_i, theta) on a packed problem, single state.
 
     forward: nfr_integrate (on-the-fly FP32 pair sums, FP64 state) keeping
-    checkpoints every `ckpt_every` steps; backward: nfr_adjoint.  `params` is
+    checkpoints every `ckpt_every` steps; backward: nfr_adjoint.  On a context
+    with its own stream both replay captured HIP graphs.  `params` is
     a CPU float64 tensor (A_e, s_e, A_i, s_i, theta); its gradient is returned
     on the CPU.
     """
@@ -333,7 +334,9 @@ class NeuralFieldRK4(torch.autograd.Function):
         k = kernel_struct(kind, *p[:4])
         f = Firing(beta, p[4])
         u = u0.detach().reshape(1, problem.n).to(torch.float64).clone().contiguous()
-        ck = problem.integrate(k, f, u, dt, steps, form=L.FORM_ONTHEFLY_FP32, ckpt_every=ckpt_every)
+        graphs = problem.ctx.stream.cuda_stream != 0      # the null stream cannot be captured
+        ck = problem.integrate(k, f, u, dt, steps, form=L.FORM_ONTHEFLY_FP32, ckpt_every=ckpt_every,
+                               use_graph=graphs)
         ctx.problem, ctx.k, ctx.f = problem, k, f
         ctx.dt, ctx.steps, ctx.every = dt, steps, ckpt_every
         ctx.save_for_backward(ck)

@@ -841,24 +841,24 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)ceil_div(nblocks * 8, kWG)), dim3(kWG), 0, s, a.pblk, nblocks * 8);
   NFR_HIP_LAUNCH();
 
-  const int64_t nseg = ceil_div(steps, ckpt_every);
-  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-    const int64_t s0 = seg * ckpt_every;
-    const int64_t len = (steps - s0) < ckpt_every ? (steps - s0) : ckpt_every;
-    // recompute the segment forward from its checkpoint, keeping every stage input
-    NFR_HIP(hipMemcpyAsync(a.useg, ckpt_dev + seg * n, vbytes, hipMemcpyDeviceToDevice, s));
-    if ((st = launch_prep(pv, form, 1, a.useg, fr, a.fwd, a.fwd.v, s))) return st;
+  // recompute of one segment of `len` steps from a.useg, keeping every stage input
+  auto recompute = [&](int64_t len) -> int {
+    int r;
     for (int64_t l = 0; l < len; ++l) {
       for (int stage = 1; stage <= 4; ++stage) {
         NFR_HIP(hipMemcpyAsync(a.store + (l * 4 + stage - 1) * n, a.fwd.v, vbytes, hipMemcpyDeviceToDevice, s));
-        if ((st = launch_pairs(ctx, pv, *kernel, form, 1, nullptr, a.fwd))) return st;
-        if ((st = launch_combine(pv, form, 1, stage, dt, a.useg, a.fwd, fr, s))) return st;
+        if ((r = launch_pairs(ctx, pv, *kernel, form, 1, nullptr, a.fwd))) return r;
+        if ((r = launch_combine(pv, form, 1, stage, dt, a.useg, a.fwd, fr, s))) return r;
       }
     }
-    // reverse sweep over the segment
+    return NFR_OK;
+  };
+  // reverse sweep over one segment of `len` steps
+  auto reverse = [&](int64_t len) -> int {
+    int r;
     for (int64_t l = len - 1; l >= 0; --l) {
       for (int stage = 4; stage >= 1; --stage) {
-        if ((st = timing_mark(ctx))) return st;
+        if ((r = timing_mark(ctx))) return r;
         const dim3 agrid((unsigned)sym_pairs(nt));
 #define NFR_ADJ_CASE(K) \
   case K: hipLaunchKernelGGL(k_sym_adjoint<K>, agrid, dim3(kSymThreads), 0, s, pv.src, a.lam32, pv.npad, nt, pp, a.apart); break;
@@ -871,12 +871,82 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
         }
 #undef NFR_ADJ_CASE
         NFR_HIP_LAUNCH();
-        if ((st = timing_mark(ctx))) return st;
+        if ((r = timing_mark(ctx))) return r;
         NFR_LAUNCH_SLOTS(k_adj_combine, nt, n, s, a.apart, nt, n, pv.npad,
                            stage, dt, co, pv.q, fr, a.store + (l * 4 + stage - 1) * n, a.ubar, a.unbar, a.lam,
                            a.lam32, a.pblk);
         NFR_HIP_LAUNCH();
       }
+    }
+    return NFR_OK;
+  };
+
+  // On a non-default stream the recompute and the reverse sweep of a segment
+  // are captured once per segment length (every segment uses the same
+  // buffers) and replayed; the null stream cannot be captured, so there every
+  // kernel is launched.
+  struct SegGraphs {
+    int64_t len = -1;
+    hipGraphExec_t rec = nullptr, rev = nullptr;
+  };
+  struct GraphCache {
+    hipStream_t stream;
+    SegGraphs g[2];
+    ~GraphCache() {
+      bool any = false;
+      for (auto& e : g) any = any || e.rec || e.rev;
+      if (!any) return;
+      (void)hipStreamSynchronize(stream);   // executable graphs are released once their launches have run
+      for (auto& e : g) {
+        if (e.rec) (void)hipGraphExecDestroy(e.rec);
+        if (e.rev) (void)hipGraphExecDestroy(e.rev);
+      }
+    }
+  } cache{s, {}};
+  auto capture = [&](auto&& body, int64_t len, hipGraphExec_t* out) -> int {
+    hipGraph_t graph = nullptr;
+    NFR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    const int r = body(len);
+    ctx->capturing = false;
+    const hipError_t e_end = hipStreamEndCapture(s, &graph);
+    if (r) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r;
+    }
+    if (e_end != hipSuccess) return fail(NFR_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e_end));
+    const hipError_t e_inst = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e_inst != hipSuccess) return fail(NFR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e_inst));
+    return NFR_OK;
+  };
+  auto graphs_for = [&](int64_t len, SegGraphs** out) -> int {
+    for (auto& e : cache.g)
+      if (e.len == len) {
+        *out = &e;
+        return NFR_OK;
+      }
+    SegGraphs& e = cache.g[0].len < 0 ? cache.g[0] : cache.g[1];
+    e.len = len;
+    int r;
+    if ((r = capture(recompute, len, &e.rec)) || (r = capture(reverse, len, &e.rev))) return r;
+    *out = &e;
+    return NFR_OK;
+  };
+
+  const int64_t nseg = ceil_div(steps, ckpt_every);
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t s0 = seg * ckpt_every;
+    const int64_t len = (steps - s0) < ckpt_every ? (steps - s0) : ckpt_every;
+    NFR_HIP(hipMemcpyAsync(a.useg, ckpt_dev + seg * n, vbytes, hipMemcpyDeviceToDevice, s));
+    if ((st = launch_prep(pv, form, 1, a.useg, fr, a.fwd, a.fwd.v, s))) return st;
+    if (s != nullptr) {
+      SegGraphs* gs = nullptr;
+      if ((st = graphs_for(len, &gs))) return st;
+      NFR_HIP(hipGraphLaunch(gs->rec, s));
+      NFR_HIP(hipGraphLaunch(gs->rev, s));
+    } else {
+      if ((st = recompute(len)) || (st = reverse(len))) return st;
     }
   }
   NFR_HIP(hipMemcpyAsync(ubar0_dev, a.ubar, vbytes, hipMemcpyDeviceToDevice, s));

@@ -97,6 +97,29 @@ def test_adjoint_deterministic_and_autograd(ctx):
     assert np.array_equal(params.grad.numpy(), a[2])
 
 
+def test_adjoint_graph_replay_is_bitwise_eager():
+    """On a context with its own stream the forward steps and the adjoint's segments
+    replay captured graphs; the results equal the eagerly launched ones bit for bit
+    (steps not a multiple of the checkpoint interval: two segment lengths)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w, q, target = _case(NF.EXP_MH, n=900, steps=23, seed=8)
+    x, th = w.surface.xyz, float(w.theta[0])
+    eager = _gpu_grads(P.Context(0), x, q, w.kernel_kind, w.kernel, w.u0, w.beta, th, w.dt, w.steps, 5, target)
+    sctx = P.Context(0, torch.cuda.Stream())
+    with torch.cuda.stream(sctx.stream):
+        prob = P.Problem(sctx, torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
+        u0 = torch.from_numpy(w.u0[0].copy()).cuda().requires_grad_(True)
+        params = torch.tensor(list(w.kernel) + [th], dtype=torch.float64, requires_grad=True)
+        uT = P.NeuralFieldRK4.apply(u0, params, prob, w.kernel_kind, w.beta, w.dt, w.steps, 5)
+        loss = ((uT - torch.from_numpy(target[0]).cuda()) ** 2).sum()
+        loss.backward()
+    torch.cuda.synchronize()
+    assert np.array_equal(uT.detach().cpu().numpy(), eager[0][0])
+    assert np.array_equal(u0.grad.cpu().numpy(), eager[1])
+    assert np.array_equal(params.grad.numpy(), eager[2])
+
+
 def test_adjoint_beta_zero_closed_form_full_size(ctx):
     """beta = 0 on the full-size torus adjoint workload (N = 16384): dL/du0 = R^n 2 (u(T) - target)
     and dL/dA_e = sum_i res_i (1 - R^n) / 2 sum_j exp(-r_ij / s_e) q_j."""
