@@ -29,10 +29,20 @@ namespace nfr {
 // (I, J) go to slot J of the nodes of I, the column sums to slot I of the
 // nodes of J).  The coordinates are in the forward kernel's units (t the
 // excitatory argument); with rho = 1/m the kernel uses e1 = e2^m.
+// Waves per workgroup of the transpose kernel (they split a tile's source
+// groups like the forward kernel's; one group per wave measured fastest at
+// N = 16384: 1, 2, 4 waves took 0.089, 0.082, 0.077 ms per pair launch).
+#ifndef NFR_ADJ_SPLIT
+#define NFR_ADJ_SPLIT 4
+#endif
+constexpr int kAdjSplit = NFR_ADJ_SPLIT;
+constexpr int kAdjThreads = 64 * kAdjSplit;
+
 template <int KIND, bool COLS>
 __device__ inline void sym_adj_tile(const float4* __restrict__ src, const float* __restrict__ lam, int64_t npad,
                                     int nt, const PairParams& pp, double* __restrict__ part, int64_t I, int64_t J,
                                     double (*rowsum)[4][kSymTile]) {
+  static_assert(kSymTile == 64 * kSymTPT, "one wave holds the tile's targets");
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const float rho = pp.rho;
@@ -56,7 +66,7 @@ __device__ inline void sym_adj_tile(const float4* __restrict__ src, const float*
   int64_t nsrc = npad - J * kSymTile;
   if (nsrc > kSymTile) nsrc = kSymTile;
   const int ngroups = (int)(nsrc / 64);
-  for (int grp = wave; grp < ngroups; grp += kSymSplit) {
+  for (int grp = wave; grp < ngroups; grp += kAdjSplit) {
     const int64_t j = J * kSymTile + grp * 64 + lane;
     const float4 s4 = src[j];
     float sx = s4.x * pp.sig, sy = s4.y * pp.sig, sz = s4.z * pp.sig, sl = lam[j];
@@ -105,20 +115,20 @@ __device__ inline void sym_adj_tile(const float4* __restrict__ src, const float*
       for (int c = 0; c < 4; ++c) part[((int64_t)c * nt + I) * npad + j] = (double)col[c];
     }
   }
-  if (kSymSplit > 1) {
+  if (kAdjSplit > 1) {
 #pragma unroll
     for (int k = 0; k < kSymTPT; ++k)
 #pragma unroll
       for (int c = 0; c < 4; ++c) rowsum[wave][c][k * 64 + lane] = racc[k][c];
     __syncthreads();
-    for (int tt = threadIdx.x; tt < kSymTile; tt += kSymThreads) {
+    for (int tt = threadIdx.x; tt < kSymTile; tt += kAdjThreads) {
       const int64_t t = I * kSymTile + tt;
       if (t >= npad) continue;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         double sum = 0.0;
 #pragma unroll
-        for (int w = 0; w < kSymSplit; ++w) sum += rowsum[w][c][tt];
+        for (int w = 0; w < kAdjSplit; ++w) sum += rowsum[w][c][tt];
         part[((int64_t)c * nt + J) * npad + t] = sum;
       }
     }
@@ -135,10 +145,10 @@ __device__ inline void sym_adj_tile(const float4* __restrict__ src, const float*
 
 // One launch per reverse stage: nt (nt + 1) / 2 workgroups, nt = ceil(npad / kSymTile).
 template <int KIND>
-__global__ __launch_bounds__(kSymThreads) void k_sym_adjoint(const float4* __restrict__ src,
+__global__ __launch_bounds__(kAdjThreads) void k_sym_adjoint(const float4* __restrict__ src,
                                                              const float* __restrict__ lam, int64_t npad, int nt,
                                                              PairParams pp, double* __restrict__ part) {
-  __shared__ double rowsum[kSymSplit][4][kSymTile];
+  __shared__ double rowsum[kAdjSplit][4][kSymTile];
   int64_t I, J;
   sym_decode(blockIdx.x, &I, &J);
   if (I == J)

@@ -861,7 +861,7 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
         if ((r = timing_mark(ctx))) return r;
         const dim3 agrid((unsigned)sym_pairs(nt));
 #define NFR_ADJ_CASE(K) \
-  case K: hipLaunchKernelGGL(k_sym_adjoint<K>, agrid, dim3(kSymThreads), 0, s, pv.src, a.lam32, pv.npad, nt, pp, a.apart); break;
+  case K: hipLaunchKernelGGL(k_sym_adjoint<K>, agrid, dim3(kAdjThreads), 0, s, pv.src, a.lam32, pv.npad, nt, pp, a.apart); break;
         switch (adj_code) {
           NFR_ADJ_CASE(0) NFR_ADJ_CASE(1) NFR_ADJ_CASE(2) NFR_ADJ_CASE(3)
           NFR_ADJ_CASE(4) NFR_ADJ_CASE(5) NFR_ADJ_CASE(6) NFR_ADJ_CASE(7)
