@@ -290,6 +290,9 @@ int nfr_batch_integrate(nfr_batch* batch, double* const* u_devs, double dt, int6
 
 /* ---------------------------------------------------------------- adjoint */
 
+/* Workspace bytes of nfr_adjoint: the stage inputs of one checkpoint segment
+ * (4 x ckpt_every x n FP64) plus the transpose kernel's per-tile partial sums,
+ * 4 x npad^2 / 256 FP64 (8.6 GB at n = 262144; it grows quadratically). */
 size_t nfr_adjoint_workspace_size(const nfr_problem* prob, int64_t steps, int64_t ckpt_every);
 
 /* Gradients of a scalar loss L(u(T)) through `steps` RK4 steps of a single

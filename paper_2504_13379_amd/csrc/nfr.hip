@@ -191,12 +191,19 @@ int resolve_form(int form, int64_t n, int B) {
   return NFR_FORM_ONTHEFLY_FP32;
 }
 
-// B = 1 on the fly uses the symmetric kernel: one slot per tile.
-bool use_sym(int form, int B) { return form == NFR_FORM_ONTHEFLY_FP32 && B == 1; }
 int64_t sym_tiles(int64_t npad) { return ceil_div(npad, kSymTile); }
 
+// B = 1 on the fly uses the symmetric kernel: one FP64 slot per tile and node,
+// npad^2 / kSymTile * 8 bytes, which grows quadratically; beyond 8 GiB of
+// slots (N above about 520k) the one-sided kernel, whose partial sums stay
+// small, is used instead.
+constexpr double kSymMaxSlotBytes = 8.0 * 1024 * 1024 * 1024;
+bool use_sym(int form, int B, int64_t npad) {
+  return form == NFR_FORM_ONTHEFLY_FP32 && B == 1 && (double)sym_tiles(npad) * (double)npad * 8.0 <= kSymMaxSlotBytes;
+}
+
 int nsplit_for(const ProblemView& pv, int B, int form) {
-  if (use_sym(form, B)) return (int)sym_tiles(pv.npad);
+  if (use_sym(form, B, pv.npad)) return (int)sym_tiles(pv.npad);
   if (form == NFR_FORM_ONTHEFLY_FP32) return plan_otf(pv.npad, B).nsplit;
   if (form == NFR_FORM_W_FP32) return plan_gemv(pv.n, pv.npad, B).nsplit;
   return mfma_nsplit(pv.n, pv.npad, B);
@@ -288,7 +295,7 @@ int timing_mark(nfr_context* ctx) {
 
 int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B, const void* W, const Workspace& w,
                      hipStream_t s) {
-  if (use_sym(form, B)) {
+  if (use_sym(form, B, pv.npad)) {
     PairParams pp = pair_params(k, pv);
     if (sym_pow_code(k)) {   // coordinates in units of the inhibitory length (see sym_pow)
       const double sig_i = k.kind == NFR_KERNEL_GAUSS_MH ? std::sqrt(kLog2e) / k.s_i : kLog2e / k.s_i;

@@ -229,3 +229,18 @@ def test_apply_integer_ratio_kernels(ctx, kind, p, n):
     ref = NF.apply_K(x, q, U, kind, p, 20.0, 0.2)
     scale = _abs_scale(x, q, U, kind, p, 20.0, 0.2, None)
     assert np.max(np.abs(y - ref) / scale) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [300000, 700000])
+def test_apply_large_n_both_sides_of_the_slot_budget(ctx, n):
+    """Single-state on-the-fly sums at N = 3e5 (symmetric kernel, 2.8 GB of tile slots)
+    and N = 7e5 (beyond the 8 GiB slot budget: the one-sided kernel), sampled rows."""
+    rng = np.random.default_rng(n)
+    x = S.fibonacci_sphere(n)
+    q = np.full(n, 4 * math.pi / n) * rng.uniform(0.9, 1.1, size=n)
+    U = rng.normal(0.2, 0.4, size=(1, n))
+    y = _run_apply(ctx, x, q, U, NF.EXP_MH, EXPK, 20.0, 0.2, 0)
+    rows = rng.choice(n, 24, replace=False)
+    ref = NF.apply_K(x, q, U, NF.EXP_MH, EXPK, 20.0, 0.2, rows=rows)
+    scale = _abs_scale(x, q, U, NF.EXP_MH, EXPK, 20.0, 0.2, rows)
+    assert np.max(np.abs(y[:, rows] - ref) / scale) <= 1e-5
