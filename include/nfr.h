@@ -2,15 +2,17 @@
  * nfr.h -- C ABI of the MI355X (gfx950) library for RBF neural fields on surfaces.
  *
  * The library applies and time-steps the discrete nonlocal operator of the
- * discrete collocation scheme (paper section 2.2, eq. NFODETilde, without the
- * forcing term):
+ * discrete collocation scheme (paper section 2.2, eq. NFODETilde; the forcing
+ * term enters only through nfr_integrate_forced):
  *
  *     u_i'(t) = -u_i + K_i(u),    K_i(u) = sum_{j=0}^{N-1} w(|x_i - x_j|) q_j f(u_j),
  *
  * over N nodes x_i on a surface with quadrature weights q_j (the mu_j of eq.
- * NFODETilde, produced by RBF-QF, paper section 3), a radial Mexican-hat
- * kernel w of the chordal distance and the sigmoid firing rate f of eq.
- * firing_rate.  The sum runs over every j, j = i included.
+ * NFODETilde, produced by RBF-QF, paper section 3; nfr_quad_weights computes
+ * them), a radial Mexican-hat kernel w of the chordal distance (or of the
+ * doubly periodic distance of eq. dist for nfr_problem_create_periodic) and
+ * the sigmoid firing rate f of eq. firing_rate.  The sum runs over every j,
+ * j = i included.
  *
  * Conventions shared by every call:
  *   - Every call returns an int status: NFR_OK (0) or a negative NFR_ERR_*.
@@ -84,7 +86,8 @@ typedef struct {
  *                  hi*hi + hi*lo + lo*hi; f(u) split the same way).  Meant
  *                  for blocks of states (states are processed 32 or 64 at a
  *                  time; B = 1 works but wastes the matrix cores).
- *   AUTO:          the library picks a form from the problem size and B. */
+ *   AUTO:          the library picks the form (at present always
+ *                  ONTHEFLY_FP32, which needs no W matrix). */
 enum nfr_form {
   NFR_FORM_AUTO = -1,
   NFR_FORM_ONTHEFLY_FP32 = 0,
@@ -310,8 +313,10 @@ size_t nfr_adjoint_workspace_size(const nfr_problem* prob, int64_t steps, int64_
  * inference (paper sections 1 and 6).
  *   ubarT_dev: dL/du(T), n doubles (device);  ubar0_dev: receives dL/du(0).
  *   pbar_host: receives dL/d(A_e, s_e, A_i, s_i, theta) (5 doubles, host).
- * firing->theta_dev must be NULL (one threshold).  Synchronous: returns
- * after the gradients are written. */
+ * firing->theta_dev must be NULL (one threshold).  On a context with a
+ * non-default stream the recompute and the reverse sweep of a segment are
+ * captured once per segment length and replayed as HIP graphs (the same
+ * results).  Synchronous: returns after the gradients are written. */
 int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, const double* ckpt_dev,
                 int64_t ckpt_every, int64_t steps, double dt, const double* ubarT_dev, double* ubar0_dev,
                 double* pbar_host, void* ws_dev, size_t ws_bytes);
