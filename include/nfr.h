@@ -321,6 +321,33 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
                 int64_t ckpt_every, int64_t steps, double dt, const double* ubarT_dev, double* ubar0_dev,
                 double* pbar_host, void* ws_dev, size_t ws_bytes);
 
+/* ---------------------------------------------------------------- autotuner */
+
+/* The multi-state on-the-fly pair sum (B >= 2) has one free launch parameter:
+ * how many workgroups the work is cut into (source chunks per target tile).
+ * Tuning results live in a process-wide table that every later plan consults
+ * (the entry nearest in log n and log B); workspace sizes follow the plan, so
+ * query them after tuning.  Tile shapes of the other kernels are fixed at
+ * build time; the uneven batch has its own tuner (nfr_batch_tune). */
+
+/* Workspace bytes of nfr_tune (0 if the sizes are unsupported). */
+size_t nfr_tune_workspace_size(int64_t n_max, int B_max);
+
+/* Times the candidate workgroup targets (256 ... 4096) of the multi-state pair
+ * sum on synthetic problems (spherical Fibonacci nodes, n = n_max/16, n_max/4,
+ * n_max, at least 1024; B = 2, 4, 16, 64, 256 up to B_max; Gaussian Mexican
+ * hat), installs the fastest per (n, B) in the process-wide table and, if
+ * cache_path is non-NULL, writes them there as JSON.  1024 <= n_max <= 4e6,
+ * 2 <= B_max.  Synchronous. */
+int nfr_tune(nfr_context* ctx, const char* cache_path, int64_t n_max, int B_max, void* ws_dev, size_t ws_bytes);
+/* Installs the entries of a cache written by nfr_tune (host only). */
+int nfr_tune_load(const char* cache_path);
+/* The workgroup target the planner uses for n nodes and B >= 2 states
+ * (1024 without tuning); -1 for invalid sizes. */
+int64_t nfr_tune_target(int64_t n, int B);
+/* Empties the process-wide table (plans return to the built-in target). */
+int nfr_tune_clear(void);
+
 /* ---------------------------------------------------------------- quadrature weights */
 
 /* Workspace bytes for nfr_quad_weights (0 if the sizes are unsupported). */

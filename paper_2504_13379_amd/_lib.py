@@ -64,6 +64,11 @@ def _declare(lib):
         "nfr_problem_create": (c_int, [P, c_int64, P, P, P, c_size_t, POINTER(P)]),
         "nfr_problem_create_periodic": (c_int, [P, c_int64, P, P, c_double, P, c_size_t, POINTER(P)]),
         "nfr_problem_period": (c_double, [P]),
+        "nfr_tune_workspace_size": (c_size_t, [c_int64, c_int]),
+        "nfr_tune": (c_int, [P, c_char_p, c_int64, c_int, P, c_size_t]),
+        "nfr_tune_load": (c_int, [c_char_p]),
+        "nfr_tune_target": (c_int64, [c_int64, c_int]),
+        "nfr_tune_clear": (c_int, []),
         "nfr_quad_workspace_size": (c_size_t, [c_int64, c_int64, c_int]),
         "nfr_quad_weights": (c_int, [P, c_int64, P, P, c_int64, P, c_int, c_int, P, P, P, P, c_size_t]),
         "nfr_problem_destroy": (c_int, [P]),

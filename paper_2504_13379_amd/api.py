@@ -287,6 +287,20 @@ class Batch:
             pass
 
 
+def tune(ctx: Context, cache_path: str | None = None, n_max: int = 65536, B_max: int = 64) -> None:
+    """Autotunes the multi-state on-the-fly pair sum (nfr_tune); results apply process-wide."""
+    ws_bytes = L.lib().nfr_tune_workspace_size(int(n_max), int(B_max))
+    if ws_bytes == 0:
+        raise ValueError("unsupported tuning sizes n_max=%d, B_max=%d" % (n_max, B_max))
+    ws = _dev_buffer(ws_bytes, ctx.device)
+    path = cache_path.encode() if cache_path else None
+    L.check(L.lib().nfr_tune(ctx.handle, path, int(n_max), int(B_max), ws.data_ptr(), ws_bytes))
+
+
+def tune_load(cache_path: str) -> None:
+    L.check(L.lib().nfr_tune_load(cache_path.encode()))
+
+
 def quad_weights(ctx: Context, xyz: torch.Tensor, normals: torch.Tensor, tris, star_shaped: bool, k: int = 32,
                  details: bool = False):
     """Surface quadrature weights q (N,) float64 on the GPU (nfr_quad_weights).

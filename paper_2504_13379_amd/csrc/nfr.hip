@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -150,12 +151,38 @@ struct OtfPlan {
 // interaction; targets per thread shrink as blocks grow (registers).
 int otf_bs(int B) { return B == 1 ? 1 : (B == 2 ? 2 : (B <= 4 ? 4 : (B <= 8 ? 8 : 16))); }
 
-OtfPlan plan_otf(int64_t npad, int B) {
+// Tuned workgroup targets of the multi-state on-the-fly pair sum (its one
+// free launch parameter: how many source chunks the work is cut into), keyed
+// by padded node count and state count; process-wide, filled by nfr_tune or
+// nfr_tune_load.  A plan uses the entry nearest in (log npad, log B).
+struct TuneEntry {
+  int64_t npad;
+  int B;
+  int64_t target;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+int64_t otf_target_wgs(int64_t npad, int B) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  int64_t best = kTargetWGs;
+  double best_d = 1e300;
+  for (const TuneEntry& e : g_tune) {
+    const double d = std::fabs(std::log2((double)npad / (double)e.npad)) + std::fabs(std::log2((double)B / (double)e.B));
+    if (d < best_d) {
+      best_d = d;
+      best = e.target;
+    }
+  }
+  return best;
+}
+
+OtfPlan plan_otf_target(int64_t npad, int B, int64_t target) {
   OtfPlan p;
   p.bs = otf_bs(B);
   p.nsb = (int)ceil_div(B, p.bs);
   p.tiles = ceil_div(npad, (int64_t)kWG * otf_tpt(p.bs));
-  int64_t want = ceil_div(kTargetWGs, p.tiles * p.nsb);
+  int64_t want = ceil_div(target, p.tiles * p.nsb);
   const int64_t max_split = npad / kWG;
   if (want < 1) want = 1;
   if (want > max_split) want = max_split;
@@ -163,6 +190,8 @@ OtfPlan plan_otf(int64_t npad, int B) {
   p.nsplit = (int)ceil_div(npad, p.chunk);
   return p;
 }
+
+OtfPlan plan_otf(int64_t npad, int B) { return plan_otf_target(npad, B, B == 1 ? kTargetWGs : otf_target_wgs(npad, B)); }
 
 struct GemvPlan {
   int bs = 1, nsb = 1;
@@ -1589,6 +1618,227 @@ int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const d
   hipLaunchKernelGGL(k_quad_fill, dim3(eb), dim3(kWG), 0, s, stn, (int64_t)tk, n, w.off, w.cursor, w.list);
   hipLaunchKernelGGL(k_quad_sum, dim3((unsigned)nb), dim3(kWG), 0, s, w.off, w.cnt, n, w.list, w.wE, q_dev);
   NFR_HIP_LAUNCH();
+  return NFR_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ autotuner
+
+namespace {
+
+constexpr int kTuneB[] = {2, 4, 16, 64, 256};
+constexpr int64_t kTuneTargets[] = {256, 512, 1024, 2048, 4096};
+constexpr int kTuneMaxSplit = 16;
+
+std::vector<int64_t> tune_sizes(int64_t n_max) {
+  std::vector<int64_t> out;
+  for (int64_t d : {16, 4, 1}) {
+    const int64_t n = std::max<int64_t>(1024, n_max / d);
+    if (out.empty() || out.back() != n) out.push_back(n);
+  }
+  return out;
+}
+
+struct TuneLayout {
+  size_t xyz = 0, q = 0, pack = 0, g = 0, part = 0, bytes = 0;
+};
+
+TuneLayout tune_layout(int64_t n_max, int B_max) {
+  TuneLayout L;
+  const int64_t npad = round_up(n_max, kPad);
+  const int Bm = std::min(B_max, 256);
+  size_t off = 0;
+  L.xyz = off;
+  off += align256(size_t(3) * n_max * sizeof(double));
+  L.q = off;
+  off += align256(size_t(n_max) * sizeof(double));
+  L.pack = off;
+  off += align256(nfr_problem_bytes(n_max));
+  L.g = off;
+  off += align256(size_t(npad) * Bm * sizeof(float));
+  L.part = off;
+  off += align256(size_t(kTuneMaxSplit) * Bm * npad * sizeof(double));
+  L.bytes = off;
+  return L;
+}
+
+bool tune_sizes_ok(int64_t n_max, int B_max) { return n_max >= 1024 && n_max <= kMaxN && B_max >= 2 && B_max <= kMaxB; }
+
+void tune_install(const std::vector<TuneEntry>& add) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const TuneEntry& e : add) {
+    bool replaced = false;
+    for (TuneEntry& f : g_tune)
+      if (f.npad == e.npad && f.B == e.B) {
+        f.target = e.target;
+        replaced = true;
+      }
+    if (!replaced) g_tune.push_back(e);
+  }
+}
+
+// Integer value following "key": in text from position pos; -1 if absent.
+long long json_int_after(const std::string& text, size_t pos, size_t end, const char* key) {
+  const std::string k = std::string("\"") + key + "\"";
+  const size_t at = text.find(k, pos);
+  if (at == std::string::npos || at >= end) return -1;
+  size_t c = text.find(':', at + k.size());
+  if (c == std::string::npos || c >= end) return -1;
+  ++c;
+  while (c < end && (text[c] == ' ' || text[c] == '\t' || text[c] == '\n' || text[c] == '\r')) ++c;
+  long long v = 0;
+  bool any = false;
+  while (c < end && text[c] >= '0' && text[c] <= '9') {
+    v = v * 10 + (text[c] - '0');
+    any = true;
+    if (v > (1LL << 40)) return -1;
+    ++c;
+  }
+  return any ? v : -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t nfr_tune_workspace_size(int64_t n_max, int B_max) {
+  if (!tune_sizes_ok(n_max, B_max)) return 0;
+  return tune_layout(n_max, B_max).bytes;
+}
+
+int nfr_tune(nfr_context* ctx, const char* cache_path, int64_t n_max, int B_max, void* ws_dev, size_t ws_bytes) {
+  if (!ctx) return fail(NFR_ERR_INVALID_ARG, "context is NULL");
+  if (!tune_sizes_ok(n_max, B_max))
+    return fail(NFR_ERR_INVALID_ARG, "n_max = %lld, B_max = %d outside [1024, %lld] x [2, %d]", (long long)n_max, B_max,
+                (long long)kMaxN, kMaxB);
+  const TuneLayout L = tune_layout(n_max, B_max);
+  if (!ws_dev || ws_bytes < L.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.bytes);
+  if (reinterpret_cast<uintptr_t>(ws_dev) % 256) return fail(NFR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  NFR_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  char* base = static_cast<char*>(ws_dev);
+  double* xyz_dev = reinterpret_cast<double*>(base + L.xyz);
+  double* q_dev = reinterpret_cast<double*>(base + L.q);
+  float* g = reinterpret_cast<float*>(base + L.g);
+  double* part = reinterpret_cast<double*>(base + L.part);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  NFR_HIP(hipEventCreate(&ev0));
+  hipError_t e = hipEventCreate(&ev1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev0);
+    return fail(NFR_ERR_HIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+  }
+  struct Events {
+    hipEvent_t a, b;
+    ~Events() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } events{ev0, ev1};
+  const nfr_kernel kern{NFR_KERNEL_GAUSS_MH, 1.0, 0.15, 0.5, 0.4};
+  std::vector<TuneEntry> found;
+  std::vector<double> found_ms;
+  for (int64_t n : tune_sizes(n_max)) {
+    // a synthetic surface: spherical Fibonacci nodes, equal weights
+    std::vector<double> xyz(size_t(3) * n), q(size_t(n), 4.0 * M_PI / (double)n);
+    const double golden = (1.0 + std::sqrt(5.0)) / 2.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double z = 1.0 - (2.0 * i + 1.0) / (double)n;
+      const double r = std::sqrt(std::max(0.0, 1.0 - z * z));
+      const double phi = 2.0 * M_PI * (double)i / golden;
+      xyz[3 * i] = r * std::cos(phi);
+      xyz[3 * i + 1] = r * std::sin(phi);
+      xyz[3 * i + 2] = z;
+    }
+    NFR_HIP(hipMemcpyAsync(xyz_dev, xyz.data(), xyz.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    NFR_HIP(hipMemcpyAsync(q_dev, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    NFR_HIP(hipStreamSynchronize(s));   // the host arrays go out of scope with this iteration
+    nfr_problem* prob = nullptr;
+    int st = nfr_problem_create(ctx, n, xyz_dev, q_dev, base + L.pack, nfr_problem_bytes(n), &prob);
+    if (st) return st;
+    struct ProbGuard {
+      nfr_problem* p;
+      ~ProbGuard() { nfr_problem_destroy(p); }
+    } guard{prob};
+    const ProblemView& pv = prob->view;
+    const PairParams pp = pair_params(kern, pv);
+    for (int B : kTuneB) {
+      if (B > B_max) break;
+      NFR_HIP(hipMemsetAsync(g, 0, size_t(pv.npad) * B * sizeof(float), s));
+      int64_t best_t = kTargetWGs;
+      double best_ms = 1e300;
+      int64_t last_split = -1;
+      for (int64_t target : kTuneTargets) {
+        const OtfPlan pl = plan_otf_target(pv.npad, B, target);
+        if (pl.nsplit > kTuneMaxSplit || pl.nsplit == last_split) continue;   // same launch as the previous target
+        last_split = pl.nsplit;
+        launch_otf_kind<0>(pv, pp, B, g, part, pl, s);
+        NFR_HIP(hipEventRecord(ev0, s));
+        for (int r = 0; r < 3; ++r) launch_otf_kind<0>(pv, pp, B, g, part, pl, s);
+        NFR_HIP(hipEventRecord(ev1, s));
+        NFR_HIP_LAUNCH();
+        NFR_HIP(hipEventSynchronize(ev1));
+        float ms = 0.0f;
+        NFR_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        if (ms / 3.0 < best_ms) {
+          best_ms = ms / 3.0;
+          best_t = target;
+        }
+      }
+      found.push_back(TuneEntry{pv.npad, B, best_t});
+      found_ms.push_back(best_ms);
+    }
+  }
+  tune_install(found);
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "w");
+    if (!f) return fail(NFR_ERR_INVALID_ARG, "cannot write %s", cache_path);
+    std::fprintf(f, "{\"library\": \"nfr\", \"arch\": \"%s\", \"tuned\": \"multi-state on-the-fly pair sum, workgroup target\",\n \"entries\": [\n", ctx->arch);
+    for (size_t i = 0; i < found.size(); ++i)
+      std::fprintf(f, "  {\"npad\": %lld, \"B\": %d, \"target_wgs\": %lld, \"ms\": %.6f}%s\n", (long long)found[i].npad,
+                   found[i].B, (long long)found[i].target, found_ms[i], i + 1 < found.size() ? "," : "");
+    std::fprintf(f, " ]\n}\n");
+    if (std::fclose(f) != 0) return fail(NFR_ERR_INVALID_ARG, "cannot write %s", cache_path);
+  }
+  return NFR_OK;
+}
+
+int nfr_tune_load(const char* cache_path) {
+  if (!cache_path) return fail(NFR_ERR_INVALID_ARG, "cache_path is NULL");
+  FILE* f = std::fopen(cache_path, "r");
+  if (!f) return fail(NFR_ERR_INVALID_ARG, "cannot read %s", cache_path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  std::vector<TuneEntry> add;
+  size_t pos = 0;
+  while ((pos = text.find('{', pos + 1)) != std::string::npos) {
+    const size_t end = text.find('}', pos);
+    if (end == std::string::npos) break;
+    if (text.find("\"npad\"", pos) >= end) continue;
+    const long long npad = json_int_after(text, pos, end, "npad");
+    const long long B = json_int_after(text, pos, end, "B");
+    const long long t = json_int_after(text, pos, end, "target_wgs");
+    if (npad < kPad || npad % kPad || npad > round_up(kMaxN, kPad) || B < 2 || B > kMaxB || t < 1 || t > (1 << 20))
+      return fail(NFR_ERR_INVALID_ARG, "malformed tuning entry in %s", cache_path);
+    add.push_back(TuneEntry{(int64_t)npad, (int)B, (int64_t)t});
+  }
+  if (add.empty()) return fail(NFR_ERR_INVALID_ARG, "no tuning entries in %s", cache_path);
+  tune_install(add);
+  return NFR_OK;
+}
+
+int64_t nfr_tune_target(int64_t n, int B) {
+  if (n < 1 || n > kMaxN || B < 2 || B > kMaxB) return -1;
+  return otf_target_wgs(round_up(n, kPad), B);
+}
+
+int nfr_tune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
   return NFR_OK;
 }
 

@@ -110,3 +110,30 @@ def test_quadrature_host_validation(L):
     assert call(tet, 0, k=9) == _lib.NFR_ERR_INVALID_ARG and b"sizes" in L.nfr_last_error()
     assert call(tet, 0) == _lib.NFR_ERR_INVALID_ARG and b"context" in L.nfr_last_error()
     assert call(tet[:3], 1) == _lib.NFR_ERR_INVALID_ARG and b"context" in L.nfr_last_error()
+
+
+def test_tuning_cache_load_query_clear(L, tmp_path):
+    """The planner's workgroup target follows a loaded cache (nearest entry in
+    log n and log B) and returns to the built-in 1024 after clearing."""
+    from paper_2504_13379_amd import _lib
+    assert L.nfr_tune_clear() == 0
+    assert L.nfr_tune_target(65536, 16) == 1024
+    assert L.nfr_tune_target(65536, 1) == -1 and L.nfr_tune_target(0, 4) == -1
+    path = tmp_path / "tune.json"
+    path.write_text('{"library": "nfr", "arch": "gfx950", "entries": [\n'
+                    ' {"npad": 4096, "B": 4, "target_wgs": 256, "ms": 0.1},\n'
+                    ' {"npad": 65536, "B": 64, "target_wgs": 4096, "ms": 2.0}\n]}\n')
+    try:
+        assert L.nfr_tune_load(str(path).encode()) == 0
+        assert L.nfr_tune_target(4000, 4) == 256
+        assert L.nfr_tune_target(5000, 2) == 256
+        assert L.nfr_tune_target(65536, 64) == 4096
+        assert L.nfr_tune_target(60000, 128) == 4096
+        bad = tmp_path / "bad.json"
+        bad.write_text('{"entries": [{"npad": 1000, "B": 4, "target_wgs": 256}]}')
+        assert L.nfr_tune_load(str(bad).encode()) == _lib.NFR_ERR_INVALID_ARG
+        assert L.nfr_tune_load(str(tmp_path / "missing.json").encode()) == _lib.NFR_ERR_INVALID_ARG
+    finally:
+        L.nfr_tune_clear()
+    assert L.nfr_tune_target(4000, 4) == 1024
+    assert L.nfr_tune_workspace_size(100, 4) == 0 and L.nfr_tune_workspace_size(4096, 4) > 0
