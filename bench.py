@@ -33,6 +33,7 @@ HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
 # issue at a quarter of that rate, so each costs 4 full-rate slots.
 VALU_LANES_PER_S = 256 * 128 * 2.4e9
 TRANS_COST = 4.0
+MFMA_BF16_PEAK = 2.5e15      # dense BF16 / FP16 matrix-core flop/s
 # Algorithmic lane-operation slots per unordered pair {i, j} of the B = 1
 # on-the-fly kernel (the kernel is radial, so one evaluation serves y_i and y_j):
 #   evaluation: 3 sub + 1 mul + 2 fma (r^2) + 1 mul (rho t) = 7 full-rate, plus
@@ -57,6 +58,16 @@ def sym_pow(kind, s_e, s_i):
 def slots_per_unordered_pair(kind, m):
     trans = (2 if kind == 0 else 3) - (1 if m else 0)
     return (6 if m else 7) + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 4
+
+
+def fused_slots_per_w(kind, m):
+    """Slots per W entry of the fused on-the-fly split forms: the evaluation above
+    (7 full-rate, or 6 with an integer ratio, plus the exp2 / sqrt), 2 for
+    A_e q e1 - A_i q e2, and 4 for the hi/lo split (two conversions to the 16-bit
+    type at half a slot each, as pairs are converted by one instruction, the hi
+    value back to FP32, the subtraction and the 2^c scaling)."""
+    trans = (2 if kind == 0 else 3) - (1 if m else 0)
+    return (6 if m else 7) + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 2 + 4
 
 
 def sym_kernel_name(kind, m, periodic=False):
@@ -194,11 +205,12 @@ def ensemble_leg(P, torch, args):
     out = {"workload": "ellipsoid (1,.8,.6), N=65536, B=64, Gauss Mexican hat, RK4 dt=0.05 x %d steps"
                        % args.ens_rk4_steps}
     finals = {}
-    for nm, form in (("bf16x3", P.FORM_W_BF16X3), ("fp16x3", P.FORM_W_FP16X3), ("otf_fp32", P.FORM_ONTHEFLY_FP32)):
+    for nm, form in (("bf16x3", P.FORM_W_BF16X3), ("fp16x3", P.FORM_W_FP16X3), ("otf_bf16x3", P.FORM_ONTHEFLY_BF16X3),
+                     ("otf_fp16x3", P.FORM_ONTHEFLY_FP16X3), ("otf_fp32", P.FORM_ONTHEFLY_FP32)):
         print("bench: ensemble form %s" % nm, file=sys.stderr, flush=True)
         W = None
         t_build = 0.0
-        if form != P.FORM_ONTHEFLY_FP32:
+        if form in (P.FORM_W_BF16X3, P.FORM_W_FP16X3):
             torch.cuda.synchronize()
             tb = time.perf_counter()
             W = prob.w_build(k, form)
@@ -227,13 +239,26 @@ def ensemble_leg(P, torch, args):
             entry["roofline"] = {"bound": "hbm", "achieved": wbytes / avg / 1e9, "peak": HBM_PEAK / 1e9,
                                  "unit": "GB/s", "frac": wbytes / avg / HBM_PEAK,
                                  "traffic": measured_traffic(kname), "kernel": kname}
+        elif form in (P.FORM_ONTHEFLY_BF16X3, P.FORM_ONTHEFLY_FP16X3):
+            # every W entry evaluated once per launch (64 states share it) on the vector
+            # units; the matrix cores do 3 products x 2 flops x 64 states per entry
+            m = sym_pow(w.kernel_kind, w.kernel[1], w.kernel[3])
+            wvals = float(prob.npad) ** 2
+            kname = "k_mfma_otf<%s,%d,2>" % ("bf16" if nm == "otf_bf16x3" else "fp16",
+                                             w.kernel_kind + 4 * (m - 1 if m else 0))
+            achieved = wvals * fused_slots_per_w(w.kernel_kind, m) / avg
+            entry["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANES_PER_S / 1e12,
+                                 "unit": "Tslot/s", "frac": achieved / VALU_LANES_PER_S, "traffic": None, "kernel": kname,
+                                 "slots_per_w": fused_slots_per_w(w.kernel_kind, m),
+                                 "mfma_tflops": wvals * 384.0 / avg / 1e12,
+                                 "mfma_frac": wvals * 384.0 / avg / MFMA_BF16_PEAK}
         out[nm] = entry
         finals[nm] = u.cpu().numpy()
         del W
         torch.cuda.empty_cache()
     import numpy as np
     ref = finals["otf_fp32"]
-    for nm in ("bf16x3", "fp16x3"):
+    for nm in ("bf16x3", "fp16x3", "otf_bf16x3", "otf_fp16x3"):
         out[nm]["max_rel_linf_vs_otf_fp32"] = float(np.max(np.max(np.abs(finals[nm] - ref), axis=1) /
                                                             np.max(np.abs(ref), axis=1)))
     return out

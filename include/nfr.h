@@ -86,6 +86,11 @@ typedef struct {
  *                  hi*hi + hi*lo + lo*hi; f(u) split the same way).  Meant
  *                  for blocks of states (states are processed 32 or 64 at a
  *                  time; B = 1 works but wastes the matrix cores).
+ *   ONTHEFLY_BF16X3 / ONTHEFLY_FP16X3: the same split products on the matrix
+ *                  cores, with every W entry evaluated in FP32 on the fly
+ *                  and split in registers: no W matrix (w_dev is ignored)
+ *                  and no N^2 memory; each kernel value serves 32 or 64
+ *                  states at once.
  *   AUTO:          the library picks the form (at present always
  *                  ONTHEFLY_FP32, which needs no W matrix). */
 enum nfr_form {
@@ -93,7 +98,9 @@ enum nfr_form {
   NFR_FORM_ONTHEFLY_FP32 = 0,
   NFR_FORM_W_FP32 = 1,
   NFR_FORM_W_BF16X3 = 2,
-  NFR_FORM_W_FP16X3 = 3
+  NFR_FORM_W_FP16X3 = 3,
+  NFR_FORM_ONTHEFLY_BF16X3 = 4,
+  NFR_FORM_ONTHEFLY_FP16X3 = 5
 };
 
 typedef struct nfr_context nfr_context;

@@ -29,6 +29,8 @@ FORM_ONTHEFLY_FP32 = 0
 FORM_W_FP32 = 1
 FORM_W_BF16X3 = 2
 FORM_W_FP16X3 = 3
+FORM_ONTHEFLY_BF16X3 = 4
+FORM_ONTHEFLY_FP16X3 = 5
 
 
 class NfrKernel(ctypes.Structure):

@@ -25,6 +25,7 @@ struct ProblemView {
   const float4* src = nullptr;
   const double* q = nullptr;
   const double* xyz = nullptr;
+  const double* qmax = nullptr;   // max_j |q_j| (one FP64 value on the device)
 };
 
 // Kernel evaluation in the on-the-fly pair sum.  Coordinates are multiplied by

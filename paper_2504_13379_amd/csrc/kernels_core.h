@@ -40,6 +40,20 @@ __global__ __launch_bounds__(kWG) void k_pack(const double* __restrict__ xyz, co
   xyz64[3 * i + 2] = z;
 }
 
+// qmax[0] = max_j |q_j| over the npad packed weights (one workgroup).
+__global__ __launch_bounds__(kWG) void k_qmax(const double* __restrict__ qd, int64_t npad, double* __restrict__ qmax) {
+  __shared__ double red[kWG];
+  double m = 0.0;
+  for (int64_t j = threadIdx.x; j < npad; j += kWG) m = fmax(m, fabs(qd[j]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kWG / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) qmax[0] = red[0];
+}
+
 // ------------------------------------------------------------------ sources
 
 // g[b*npad + j] = s_j f_b(u[b*n + j]) in FP32 with s_j = q_j (with_q) or 1;

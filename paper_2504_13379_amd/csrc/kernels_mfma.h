@@ -53,7 +53,11 @@ template <> struct MfmaTraits<_Float16> {
   }
 };
 
-inline bool is_mfma_form(int form) { return form == 2 || form == 3; }
+// Forms 2 / 3: W matrix in BF16 / FP16; 4 / 5: the same products with W
+// evaluated on the fly (no W matrix).
+inline bool is_mfma_form(int form) { return form >= 2 && form <= 5; }
+inline bool mfma_has_w(int form) { return form == 2 || form == 3; }
+inline bool mfma_is_bf16(int form) { return form == 2 || form == 4; }
 inline int64_t mfma_bp(int B) { return round_up(B, 64); }
 inline size_t mfma_g_bytes(int64_t npad, int B) { return size_t(2) * mfma_bp(B) * npad * 2; }
 inline int mfma_nsplit(int64_t, int64_t, int) { return kMfmaSplits; }
@@ -319,6 +323,169 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Wt,
   }
 }
 
+// Fused on-the-fly split form: the same product on the matrix cores, but
+// every W tile is evaluated by the vector units straight into the A-operand
+// layout, so no W matrix exists and nothing but G and the coordinates is read.
+//
+// Lane l = m + 32 h evaluates, for MFMA step kb, the 8 entries of row m and
+// columns 16 kb + 8 h .. +7 in FP32: the pair term of the on-the-fly kernels
+// (PairParams, template code KIND as in the symmetric kernel, bits 2-3 an
+// integer length ratio) times A_e q_j 2^sW and A_i q_j 2^sW, then splits
+// each value into hi + 2^-c lo.  Each W value is evaluated once and used for
+// all 32 NB states of the workgroup (3 NB products per 8 values).
+// The column data of a pipeline step (scaled x, y, z and the two scaled
+// amplitudes) sits in a double-buffered LDS tile read by broadcast: the 32
+// lanes of a half-wave read the same address.  sW is derived in the kernel
+// from max |q| (qmax) exactly as k_mfma_scale derives it.
+struct MfmaOtfParams {
+  float sig, rho, per;
+  double Ae, Ai;
+  const double* qmax;
+};
+
+__device__ inline int mfma_scale_exp(double bound, bool fp16) {
+  // 14 - ceil(log2(bound)); bound = f 2^e with f in [0.5, 1)
+  if (!fp16 || !(bound > 0.0)) return 0;
+  int e;
+  const double f = frexp(bound, &e);
+  return 14 - (f == 0.5 ? e - 1 : e);
+}
+
+template <typename T, int KIND, int NB>
+__global__ __launch_bounds__(kWG, 2) void k_mfma_otf(const float4* __restrict__ src, const double* __restrict__ qd,
+                                                     const T* __restrict__ Ghi, const T* __restrict__ Glo,
+                                                     int64_t npad, int B, int64_t kchunk, MfmaOtfParams op,
+                                                     double* __restrict__ part) {
+  typedef typename MfmaTraits<T>::vec V;
+  constexpr int c = MfmaTraits<T>::c;
+  constexpr int NS = 32 * NB;
+  constexpr int ROWCH = kMfmaStep / 8;
+  constexpr int CHUNKS = NS * 2 * ROWCH / kWG;
+  __shared__ __attribute__((aligned(16))) T sG[2][2][NS][kMfmaLdsStride];
+  __shared__ __attribute__((aligned(16))) float sS[2][5][kMfmaStep];
+
+  const int64_t wg = blockIdx.x;
+  const int split = (int)(wg % kMfmaSplits);
+  const int64_t rb = wg / kMfmaSplits;
+  const int sg = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m = lane & 31;
+  const int h = lane >> 5;
+  const int64_t row0 = rb * kMfmaRowsPerWG + wave * 32;
+  const int64_t k_begin = (int64_t)split * kchunk;
+  int64_t k_end = k_begin + kchunk;
+  if (k_end > npad) k_end = npad;
+  const int nsteps = (int)((k_end - k_begin) / kMfmaStep);
+
+  const int sW = mfma_scale_exp((fabs(op.Ae) + fabs(op.Ai)) * op.qmax[0], c == 11);
+  const float ae = (float)ldexp(op.Ae, sW);
+  const float ai = (float)ldexp(op.Ai, sW);
+  const float4 pr = src[row0 + m];
+  const float xi = pr.x * op.sig, yi = pr.y * op.sig, zi = pr.z * op.sig;
+
+  const T* gsrc[CHUNKS];
+  int g_hl[CHUNKS], g_st[CHUNKS], g_col[CHUNKS];
+#pragma unroll
+  for (int q = 0; q < CHUNKS; ++q) {
+    const int cc = tid + kWG * q;
+    const int row = cc / ROWCH;
+    g_hl[q] = row / NS;
+    g_st[q] = row % NS;
+    g_col[q] = 8 * (cc % ROWCH);
+    gsrc[q] = (g_hl[q] ? Glo : Ghi) + ((int64_t)sg * NS + g_st[q]) * npad + k_begin + g_col[q];
+  }
+
+  f32x16_t accM[NB], accC[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accM[nb][r] = accC[nb][r] = 0.0f;
+
+  // Every wave loads the column data of a step (lane = column); wave 0 stores
+  // it.  Loads past the last step re-read the last step.
+  u32x4_t gn[CHUNKS];
+  float4 sn;
+  double qn;
+  auto load_next = [&](int t) {
+    const int64_t tc = t < nsteps ? t : nsteps - 1;
+#pragma unroll
+    for (int q = 0; q < CHUNKS; ++q) gn[q] = *reinterpret_cast<const u32x4_t*>(gsrc[q] + tc * kMfmaStep);
+    const int64_t j = k_begin + tc * kMfmaStep + lane;
+    sn = src[j];
+    qn = qd[j];
+  };
+  auto store_next = [&](int t) {
+    const int buf = t & 1;
+#pragma unroll
+    for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[buf][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
+    if (wave == 0) {
+      const float qf = (float)qn;
+      sS[buf][0][lane] = sn.x * op.sig;
+      sS[buf][1][lane] = sn.y * op.sig;
+      sS[buf][2][lane] = sn.z * op.sig;
+      sS[buf][3][lane] = ae * qf;
+      sS[buf][4][lane] = ai * qf;
+    }
+  };
+  auto compute = [&](int t) {
+    const int buf = t & 1;
+#pragma unroll
+    for (int kb = 0; kb < kMfmaKb; ++kb) {
+      const int col = 16 * kb + 8 * h;
+      V whi, wlo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float r2 = pair_r2<KIND>(xi - sS[buf][0][col + e], yi - sS[buf][1][col + e], zi - sS[buf][2][col + e],
+                                       op.per);
+        const float tt = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+        const float e2 = __builtin_amdgcn_exp2f(-(sym_pow<KIND>() == 0 ? tt * op.rho : tt));
+        const float e1 = sym_pow<KIND>() == 0 ? __builtin_amdgcn_exp2f(-tt) : ipow<sym_pow<KIND>()>(e2);
+        const float w = fmaf(sS[buf][3][col + e], e1, -(sS[buf][4][col + e] * e2));
+        const T hi = (T)w;
+        whi[e] = hi;
+        wlo[e] = (T)((w - (float)hi) * (float)(1 << c));
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const V bh = *reinterpret_cast<const V*>(&sG[buf][0][nb * 32 + m][col]);
+        const V bl = *reinterpret_cast<const V*>(&sG[buf][1][nb * 32 + m][col]);
+        accM[nb] = MfmaTraits<T>::mma(whi, bh, accM[nb]);
+        accC[nb] = MfmaTraits<T>::mma(whi, bl, accC[nb]);
+        accC[nb] = MfmaTraits<T>::mma(wlo, bh, accC[nb]);
+      }
+    }
+  };
+  // step t: issue the loads of step t + 1, evaluate and multiply step t from
+  // LDS half t & 1, store step t + 1 into the other half, barrier.
+  if (nsteps > 0) {
+    load_next(0);
+    store_next(0);
+    __syncthreads();
+    for (int t = 0; t < nsteps; ++t) {
+      load_next(t + 1);
+      compute(t);
+      store_next(t + 1);
+      __syncthreads();
+    }
+  }
+
+  const double sm = ldexp(1.0, -sW);
+  const double sc = ldexp(1.0, -(sW + c));
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int b = sg * NS + nb * 32 + m;
+    if (b >= B) continue;
+    double* dst = part + ((int64_t)split * B + b) * npad;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t i = row0 + 8 * (r / 4) + 4 * h + (r % 4);
+      dst[i] = (double)accM[nb][r] * sm + (double)accC[nb][r] * sc;
+    }
+  }
+}
+
 // RK4 stage combination for the split forms: as k_rk4_combine, but the next
 // stage's sources are written as Ghi/Glo (no q: it sits inside W).
 template <typename T>
@@ -419,7 +586,7 @@ inline void launch_mfma_w_build_t(const ProblemView& pv, const KernelF64& kp, vo
 }
 
 inline void launch_mfma_w_build(const ProblemView& pv, int form, const KernelF64& kp, void* W, hipStream_t s) {
-  if (form == 2)
+  if (mfma_is_bf16(form))
     launch_mfma_w_build_t<__bf16>(pv, kp, W, s);
   else
     launch_mfma_w_build_t<_Float16>(pv, kp, W, s);
@@ -437,7 +604,7 @@ inline void launch_mfma_prep_t(const ProblemView& pv, int B, const double* u, co
 
 inline void launch_mfma_prep(const ProblemView& pv, int form, int B, const double* u, const Firing& fr, float* g,
                              double* v, hipStream_t s) {
-  if (form == 2)
+  if (mfma_is_bf16(form))
     launch_mfma_prep_t<__bf16>(pv, B, u, fr, g, v, s);
   else
     launch_mfma_prep_t<_Float16>(pv, B, u, fr, g, v, s);
@@ -463,10 +630,36 @@ inline void launch_mfma_apply_t(const ProblemView& pv, int B, const void* W, con
 
 inline void launch_mfma_apply(const ProblemView& pv, int form, int B, const void* W, const float* g, double* part,
                               hipStream_t s) {
-  if (form == 2)
+  if (mfma_is_bf16(form))
     launch_mfma_apply_t<__bf16>(pv, B, W, g, part, s);
   else
     launch_mfma_apply_t<_Float16>(pv, B, W, g, part, s);
+}
+
+template <typename T, int KIND>
+inline void launch_mfma_otf_t(const ProblemView& pv, const MfmaOtfParams& op, int B, const void* g, double* part,
+                              hipStream_t s) {
+  void *ghi, *glo;
+  mfma_g_split(const_cast<void*>(g), pv.npad, B, &ghi, &glo);
+  const int64_t kchunk = round_up(ceil_div(pv.npad, kMfmaSplits), kMfmaStep);
+  const unsigned grid_x = (unsigned)(pv.npad / kMfmaRowsPerWG * kMfmaSplits);
+  if (B <= 32) {
+    hipLaunchKernelGGL((k_mfma_otf<T, KIND, 1>), dim3(grid_x, 1), dim3(kWG), 0, s, pv.src, pv.q,
+                       static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad, B, kchunk, op, part);
+  } else {
+    hipLaunchKernelGGL((k_mfma_otf<T, KIND, 2>), dim3(grid_x, (unsigned)(mfma_bp(B) / 64)), dim3(kWG), 0, s, pv.src,
+                       pv.q, static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad, B, kchunk, op, part);
+  }
+}
+
+// Forms 4 / 5 for template code KIND (see k_mfma_otf).
+template <int KIND>
+inline void launch_mfma_otf(const ProblemView& pv, int form, const MfmaOtfParams& op, int B, const float* g,
+                            double* part, hipStream_t s) {
+  if (mfma_is_bf16(form))
+    launch_mfma_otf_t<__bf16, KIND>(pv, op, B, g, part, s);
+  else
+    launch_mfma_otf_t<_Float16, KIND>(pv, op, B, g, part, s);
 }
 
 template <typename T>
@@ -484,7 +677,7 @@ inline void launch_mfma_combine_t(const ProblemView& pv, int B, int stage, doubl
 inline void launch_mfma_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, double* v,
                                 double* ksum, const double* part, int nsplit, const Firing& fr, float* g,
                                 double* k1_out, const double* gamma, hipStream_t s) {
-  if (form == 2)
+  if (mfma_is_bf16(form))
     launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, gamma, s);
   else
     launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, gamma, s);
@@ -504,7 +697,7 @@ inline void launch_mfma_ab5_t(const ProblemView& pv, int B, double dt, const Ab5
 inline void launch_mfma_ab5(const ProblemView& pv, int form, int B, double dt, const Ab5Weights& wt, int4 s03, int s4,
                             double* u, double* hist, const double* part, int nsplit, const Firing& fr, float* g,
                             hipStream_t s) {
-  if (form == 2)
+  if (mfma_is_bf16(form))
     launch_mfma_ab5_t<__bf16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, g, s);
   else
     launch_mfma_ab5_t<_Float16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, g, s);

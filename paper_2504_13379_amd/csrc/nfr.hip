@@ -92,7 +92,7 @@ int check_firing(const nfr_firing* f) {
 }
 
 int check_form(int form) {
-  if (form < NFR_FORM_AUTO || form > NFR_FORM_W_FP16X3) return fail(NFR_ERR_INVALID_ARG, "unknown form %d", form);
+  if (form < NFR_FORM_AUTO || form > NFR_FORM_ONTHEFLY_FP16X3) return fail(NFR_ERR_INVALID_ARG, "unknown form %d", form);
   if (is_mfma_form(form) && !kMfmaAvailable) return fail(NFR_ERR_INVALID_ARG, "form %d is not available in this build", form);
   return NFR_OK;
 }
@@ -112,6 +112,11 @@ PairParams pair_params(const nfr_kernel& k, const ProblemView& pv) {
   return p;
 }
 
+// pair_params for the kernels that take a sym_pow code: with an integer
+// length ratio the coordinates (and the period) are scaled by the inhibitory
+// length instead (see sym_pow).
+PairParams pair_params_pow(const nfr_kernel& k, const ProblemView& pv);
+
 // Template code of the pair kernels: kernel kind, + 2 for a periodic problem.
 int kind_code(const nfr_kernel& k, const ProblemView& pv) { return k.kind + (pv.period > 0.0 ? 2 : 0); }
 
@@ -126,6 +131,16 @@ int sym_pow_code(const nfr_kernel& k) {
   const long mi = std::lround(m);
   if (mi >= 2 && mi <= 4 && std::fabs(m - (double)mi) <= 1e-12 * (double)mi) return (int)mi - 1;
   return 0;
+}
+
+PairParams pair_params_pow(const nfr_kernel& k, const ProblemView& pv) {
+  PairParams pp = pair_params(k, pv);
+  if (sym_pow_code(k)) {
+    const double sig_i = k.kind == NFR_KERNEL_GAUSS_MH ? std::sqrt(kLog2e) / k.s_i : kLog2e / k.s_i;
+    pp.sig = (float)sig_i;
+    pp.per = (float)(pv.period * sig_i);
+  }
+  return pp;
 }
 
 KernelF64 kernel64(const nfr_kernel& k, const ProblemView& pv) {
@@ -325,12 +340,7 @@ int timing_mark(nfr_context* ctx) {
 int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B, const void* W, const Workspace& w,
                      hipStream_t s) {
   if (use_sym(form, B, pv.npad)) {
-    PairParams pp = pair_params(k, pv);
-    if (sym_pow_code(k)) {   // coordinates in units of the inhibitory length (see sym_pow)
-      const double sig_i = k.kind == NFR_KERNEL_GAUSS_MH ? std::sqrt(kLog2e) / k.s_i : kLog2e / k.s_i;
-      pp.sig = (float)sig_i;
-      pp.per = (float)(pv.period * sig_i);
-    }
+    const PairParams pp = pair_params_pow(k, pv);
     const dim3 grid((unsigned)sym_pairs(sym_tiles(pv.npad)));
 #define NFR_SYM_CASE(K) \
   case K: hipLaunchKernelGGL(k_otf_sym<K>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
@@ -353,6 +363,19 @@ int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B
     }
   } else if (form == NFR_FORM_W_FP32) {
     launch_gemv(pv, static_cast<const float*>(W), B, w.g, w.part, plan_gemv(pv.n, pv.npad, B), s);
+  } else if (!mfma_has_w(form)) {
+    const PairParams pp = pair_params_pow(k, pv);
+    const MfmaOtfParams op{pp.sig, pp.rho, pp.per, pp.Ae, pp.Ai, pv.qmax};
+#define NFR_MFMA_OTF_CASE(K) \
+  case K: launch_mfma_otf<K>(pv, form, op, B, w.g, w.part, s); break;
+    switch (kind_code(k, pv) | (sym_pow_code(k) << 2)) {
+      NFR_MFMA_OTF_CASE(0) NFR_MFMA_OTF_CASE(1) NFR_MFMA_OTF_CASE(2) NFR_MFMA_OTF_CASE(3)
+      NFR_MFMA_OTF_CASE(4) NFR_MFMA_OTF_CASE(5) NFR_MFMA_OTF_CASE(6) NFR_MFMA_OTF_CASE(7)
+      NFR_MFMA_OTF_CASE(8) NFR_MFMA_OTF_CASE(9) NFR_MFMA_OTF_CASE(10) NFR_MFMA_OTF_CASE(11)
+      NFR_MFMA_OTF_CASE(12) NFR_MFMA_OTF_CASE(13) NFR_MFMA_OTF_CASE(14) NFR_MFMA_OTF_CASE(15)
+      default: return fail(NFR_ERR_INTERNAL, "no fused kernel for this kernel code");
+    }
+#undef NFR_MFMA_OTF_CASE
   } else {
     launch_mfma_apply(pv, form, B, W, w.g, w.part, s);
   }
@@ -424,7 +447,7 @@ int check_problem(const nfr_problem* p) {
 }
 
 int check_w(const nfr_problem* p, int form, const void* w_dev) {
-  if (form == NFR_FORM_ONTHEFLY_FP32) return NFR_OK;
+  if (form == NFR_FORM_ONTHEFLY_FP32 || (is_mfma_form(form) && !mfma_has_w(form))) return NFR_OK;
   if (!w_dev) return fail(NFR_ERR_INVALID_ARG, "form %d needs a W matrix (w_dev is NULL)", form);
   (void)p;
   return NFR_OK;
@@ -569,7 +592,8 @@ const char* nfr_context_arch(const nfr_context* ctx) { return ctx ? ctx->arch : 
 size_t nfr_problem_bytes(int64_t n) {
   if (n < 1 || n > kMaxN) return 0;
   const int64_t npad = round_up(n, kPad);
-  return align256(npad * sizeof(float4)) + align256(npad * sizeof(double)) + align256(3 * npad * sizeof(double));
+  return align256(npad * sizeof(float4)) + align256(npad * sizeof(double)) + align256(3 * npad * sizeof(double)) +
+         align256(sizeof(double));
 }
 
 int nfr_problem_create_periodic(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev,
@@ -597,8 +621,10 @@ int nfr_problem_create_periodic(nfr_context* ctx, int64_t n, const double* xyz_d
   p->view.src = reinterpret_cast<const float4*>(base);
   p->view.q = reinterpret_cast<const double*>(base + align256(npad * sizeof(float4)));
   p->view.xyz = reinterpret_cast<const double*>(base + align256(npad * sizeof(float4)) + align256(npad * sizeof(double)));
+  p->view.qmax = reinterpret_cast<const double*>(reinterpret_cast<const char*>(p->view.xyz) + align256(3 * npad * sizeof(double)));
   hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, ctx->stream, xyz_dev, q_dev, n, npad, period,
                      const_cast<float4*>(p->view.src), const_cast<double*>(p->view.q), const_cast<double*>(p->view.xyz));
+  hipLaunchKernelGGL(k_qmax, dim3(1), dim3(kWG), 0, ctx->stream, p->view.q, npad, const_cast<double*>(p->view.qmax));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     delete p;
@@ -627,7 +653,7 @@ size_t nfr_w_bytes(int64_t n, int form) {
   if (n < 1 || n > kMaxN) return 0;
   const int64_t npad = round_up(n, kPad);
   if (form == NFR_FORM_W_FP32) return align256(size_t(n) * npad * sizeof(float));
-  if (is_mfma_form(form)) return mfma_w_bytes(n, npad);
+  if (mfma_has_w(form)) return mfma_w_bytes(n, npad);
   return 0;
 }
 
@@ -635,7 +661,7 @@ int nfr_w_build(nfr_problem* prob, const nfr_kernel* kernel, int form, void* w_d
   int st;
   if ((st = check_problem(prob)) || (st = check_kernel(kernel))) return st;
   if ((st = check_form(form))) return st;
-  if (form != NFR_FORM_W_FP32 && !is_mfma_form(form)) return fail(NFR_ERR_INVALID_ARG, "form %d has no W matrix", form);
+  if (form != NFR_FORM_W_FP32 && !mfma_has_w(form)) return fail(NFR_ERR_INVALID_ARG, "form %d has no W matrix", form);
   if (!w_dev) return fail(NFR_ERR_INVALID_ARG, "w_dev is NULL");
   if (reinterpret_cast<uintptr_t>(w_dev) % 256) return fail(NFR_ERR_INVALID_ARG, "W buffer must be 256-byte aligned");
   const ProblemView& pv = prob->view;

@@ -48,6 +48,11 @@ def test_size_queries(L):
     npad = 32768
     assert L.nfr_w_bytes(32768, 1) == 32768 * npad * 4
     assert L.nfr_w_bytes(1000, 0) == 0
+    npad = 1024
+    for form in (2, 3):   # 256-byte header + hi and lo halves
+        assert L.nfr_w_bytes(1000, form) == 256 + 2 * npad * npad * 2
+    for form in (4, 5, 6, -1):   # fused on-the-fly forms need no W; 6 is no form
+        assert L.nfr_w_bytes(1000, form) == 0
 
 
 def test_null_arguments_rejected_before_device_work(L):

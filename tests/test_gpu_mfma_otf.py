@@ -1,0 +1,191 @@
+"""GPU parity of the fused on-the-fly split forms (ONTHEFLY_BF16X3 = 4,
+ONTHEFLY_FP16X3 = 5): W evaluated in FP32 by the vector units, split into
+hi + 2^-c lo in registers and multiplied on the matrix cores.
+
+Tolerances add the two error sources already bounded for the other forms
+(norm-wise against S_i = sum_j |w_ij q_j f(u_j)|):
+* the FP32 evaluation of each W entry, as in the on-the-fly FP32 form
+  (coordinate, difference, exp2 roundings; also the scaled period):
+  |dy_i| <= 1e-5 S_i;
+* the hi/lo split of W and f(u) with FP32 accumulation, as in the W_* split
+  forms: 3e-5 S_i (BF16), 2e-6 S_i (FP16).
+Hence 4e-5 (BF16) and 1.2e-5 (FP16) for one application; trajectories
+u(T): 1e-4 (BF16, the split-BF16 target) and 2e-5 (FP16: the FP32 path's
+1e-5 plus the split form's 1e-5) relative L-infinity per state.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import neural_field as NF
+from oracle import quadrature as Q
+from workloads import configs as C
+from workloads import surfaces as S
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2504_13379_amd")
+
+GAUSS = (1.0, 0.15, 0.5, 0.4)
+EXPK = (2.0, 0.1, 1.0, 0.3)
+TOL_APPLY = {4: 4e-5, 5: 1.2e-5}
+TOL_STATE = {4: 1e-4, 5: 2e-5}
+L = 2.0 * math.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return P.Context(0)
+
+
+def _apply(ctx, x, q, U, kind, p, beta, theta, form, period=0.0):
+    prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda(), period=period)
+    k = P.kernel_struct(kind, *p)
+    th = torch.from_numpy(np.asarray(theta, dtype=np.float64)).cuda() if np.ndim(theta) else float(theta)
+    y = prob.apply(k, P.Firing(beta, th), torch.from_numpy(np.ascontiguousarray(U)).cuda(), form=form)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def _scale(x, q, U, kind, p, beta, theta, rows=None, period=None):
+    G = q[None, :] * NF.firing(U, beta, theta)
+    return np.abs(G) @ np.abs(NF.kernel_matrix(x, kind, p, rows=rows, period=period)).T
+
+
+@pytest.mark.parametrize("form", [4, 5])
+@pytest.mark.parametrize("n,B", [(1, 1), (200, 3), (256, 32), (300, 33), (1000, 64), (2500, 70), (1100, 130)])
+@pytest.mark.parametrize("kind", [NF.GAUSS_MH, NF.EXP_MH])
+def test_fused_apply_matches_oracle(ctx, form, n, B, kind):
+    rng = np.random.default_rng(7 * n + B + 100 * form + kind)
+    x = S.fibonacci_sphere(n) * 1.05
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.15, 0.3, size=B)
+    p = GAUSS if kind == NF.GAUSS_MH else EXPK
+    y = _apply(ctx, x, q, U, kind, p, 20.0, theta, form)
+    ref = NF.apply_K(x, q, U, kind, p, 20.0, theta)
+    err = np.max(np.abs(y - ref) / _scale(x, q, U, kind, p, 20.0, theta))
+    assert err <= TOL_APPLY[form], err
+
+
+# Integer length ratios rho = 1/m: the excitatory exponential is taken as a
+# power of the inhibitory one, coordinates scaled by the inhibitory length.
+RATIO_KERNELS = [(NF.GAUSS_MH, (1.0, 0.2, 0.5, 0.2 * math.sqrt(2.0))),     # rho = 1/2
+                 (NF.GAUSS_MH, (1.0, 0.12, 0.4, 0.12 * math.sqrt(3.0))),   # rho = 1/3
+                 (NF.EXP_MH, (2.0, 0.1, 1.0, 0.4)),                        # rho = 1/4
+                 (NF.GAUSS_MH, (1.0, 0.1, 0.3, 0.2))]                      # rho = 1/4
+
+
+@pytest.mark.parametrize("form", [4, 5])
+@pytest.mark.parametrize("kind,p", RATIO_KERNELS)
+def test_fused_integer_ratio_kernels(ctx, form, kind, p):
+    n, B = 1500, 40
+    rng = np.random.default_rng(n + int(p[3] * 1000) + form)
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    y = _apply(ctx, x, q, U, kind, p, 20.0, 0.2, form)
+    ref = NF.apply_K(x, q, U, kind, p, 20.0, 0.2)
+    assert np.max(np.abs(y - ref) / _scale(x, q, U, kind, p, 20.0, 0.2)) <= TOL_APPLY[form]
+
+
+@pytest.mark.parametrize("form", [4, 5])
+@pytest.mark.parametrize("kind,p", [(NF.GAUSS_MH, (1.0, 0.6, 0.5, 1.2)), (NF.EXP_MH, (2.0, 0.5, 1.0, 1.5)),
+                                    (NF.GAUSS_MH, (1.0, 0.5, 0.5, 1.0))])   # the last: rho = 1/4
+def test_fused_periodic_plane(ctx, form, kind, p):
+    """Doubly periodic square of side 2 pi (eq. dist), 8 states."""
+    rng = np.random.default_rng(40 + form + kind)
+    surf = S.flat_square(2000, L, rng, 0.3)
+    q = Q.plane_weights(surf.xyz)
+    B = 8
+    U = rng.normal(0.3, 0.4, size=(B, surf.n))
+    theta = rng.uniform(0.1, 0.4, size=B)
+    y = _apply(ctx, surf.xyz, q, U, kind, p, 5.0, theta, form, period=L)
+    ref = NF.apply_K(surf.xyz, q, U, kind, p, 5.0, theta, period=L)
+    err = np.max(np.abs(y - ref) / _scale(surf.xyz, q, U, kind, p, 5.0, theta, period=L))
+    assert err <= TOL_APPLY[form], err
+
+
+def test_fused_fp16_scaling_handles_tiny_weights(ctx):
+    """Weights ~1e-7 would underflow FP16 without the power-of-two lift of W."""
+    n, B = 700, 8
+    rng = np.random.default_rng(3)
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 1e-7
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    y = _apply(ctx, x, q, U, NF.GAUSS_MH, GAUSS, 20.0, 0.2, 5)
+    ref = NF.apply_K(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, 0.2)
+    assert np.max(np.abs(y - ref) / _scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, 0.2)) <= TOL_APPLY[5]
+
+
+def test_fused_matches_w_form_of_same_precision(ctx):
+    """Same products as the BF16 W form; they differ only by the FP32 (fused)
+    against FP64 (W build) evaluation of W before the split."""
+    n, B = 2000, 64
+    rng = np.random.default_rng(5)
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.15, 0.3, size=B)
+    prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
+    k = P.kernel_struct(NF.GAUSS_MH, *GAUSS)
+    f = P.Firing(20.0, torch.from_numpy(theta).cuda())
+    u = torch.from_numpy(U).cuda()
+    yw = prob.apply(k, f, u, form=2, W=prob.w_build(k, 2)).cpu().numpy()
+    yf = prob.apply(k, f, u, form=4).cpu().numpy()
+    yf2 = prob.apply(k, f, u, form=4).cpu().numpy()
+    assert np.array_equal(yf, yf2)
+    scale = _scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta)
+    assert np.max(np.abs(yf - yw) / scale) <= 1e-5 + 2 * 3e-5
+
+
+@pytest.mark.parametrize("form", [4, 5])
+def test_fused_full_size_ellipsoid_sampled_rows(ctx, form):
+    """Ellipsoid ensemble at its full size (N = 65536, B = 64): one application, sampled rows."""
+    w = C.ellipsoid_ensemble()
+    x = w.surface.xyz
+    q = C.area_share_weights(w.surface)
+    rows = np.random.default_rng(12).choice(w.n, 24, replace=False)
+    y = _apply(ctx, x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, form)
+    ref = NF.apply_K(x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows=rows)
+    err = np.max(np.abs(y[:, rows] - ref) / _scale(x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows))
+    assert err <= TOL_APPLY[form], err
+
+
+@pytest.fixture(scope="module")
+def ensemble_case():
+    w = C.ellipsoid_ensemble(3000, 64, steps=30)
+    q = Q.surface_weights(w.surface)
+    op = NF.DenseOperator(w.surface.xyz, q, w.kernel_kind, w.kernel)
+    return w, q, NF.rk4(op, w.u0, w.beta, w.theta, w.dt, w.steps)
+
+
+@pytest.mark.parametrize("form", [4, 5])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_fused_integrate_ensemble_per_member(ctx, ensemble_case, form, use_graph):
+    w, q, ref = ensemble_case
+    c = P.Context(0, torch.cuda.Stream()) if use_graph else ctx
+    prob = P.Problem(c, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
+    k = P.kernel_struct(w.kernel_kind, *w.kernel)
+    u = torch.from_numpy(w.u0.copy()).cuda()
+    prob.integrate(k, P.Firing(w.beta, torch.from_numpy(w.theta).cuda()), u, w.dt, w.steps, form=form,
+                   use_graph=use_graph)
+    torch.cuda.synchronize()
+    err = NF.rel_linf(u.cpu().numpy(), ref)
+    assert err.shape == (64,)
+    assert np.all(err <= TOL_STATE[form]), err.max()
+
+
+def test_fused_form_needs_no_w(ctx):
+    assert P.lib().nfr_w_bytes(1000, 4) == 0 and P.lib().nfr_w_bytes(1000, 5) == 0
+    x = S.fibonacci_sphere(300)
+    prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.full((300,), 4 * math.pi / 300, dtype=torch.float64).cuda())
+    with pytest.raises(ValueError):
+        prob.w_build(P.kernel_struct(0, *GAUSS), 4)
+    k = P.kernel_struct(0, *GAUSS)
+    for form in (4, 5):   # rejected before the (NULL) buffer is looked at
+        assert P.lib().nfr_w_build(prob.handle, ctypes.byref(k), form, None, 0) == -1
