@@ -37,12 +37,19 @@ MFMA_BF16_PEAK = 2.5e15      # dense BF16 / FP16 matrix-core flop/s
 # Algorithmic lane-operation slots per unordered pair {i, j} of the B = 1
 # on-the-fly kernel (the kernel is radial, so one evaluation serves y_i and y_j):
 #   evaluation: 3 sub + 1 mul + 2 fma (r^2) + 1 mul (rho t) = 7 full-rate, plus
-#   2 exp2 (Gaussian) or sqrt + 2 exp2 (exponential) at 4 slots each;
-#   accumulation: 2 fma into y_i and 2 fma into y_j.
+#   2 exp2 (Gaussian) or sqrt + 2 exp2 (exponential) at 4 slots each, and 1 fma
+#   for the normalised kernel u = exp2(-t) + kappa exp2(-rho t);
+#   accumulation: 1 fma into y_i and 1 fma into y_j.
 # With length scales in the ratio rho = 1/m (m = 2, 3, 4) the kernel takes the
 # excitatory exponential as the m-th power of the inhibitory one and scales the
-# coordinates by the inhibitory length: one exp2 and the rho t multiply fewer,
-# 1 (m = 2) or 2 (m = 3, 4) multiplies more.
+# coordinates by the inhibitory length: one exp2 and the rho t multiply fewer;
+# u = e (e^(m-1) + kappa) then takes 2 (m = 2, 3) or 3 (m = 4) operations.
+
+
+def eval_slots(kind, m):
+    """Slots to evaluate u for one pair (see above)."""
+    trans = (2 if kind == 0 else 3) - (1 if m else 0)
+    return (6 if m else 7) + trans * TRANS_COST + (1 if not m else (2 if m <= 3 else 3))
 
 
 def sym_pow(kind, s_e, s_i):
@@ -56,18 +63,15 @@ def sym_pow(kind, s_e, s_i):
 
 
 def slots_per_unordered_pair(kind, m):
-    trans = (2 if kind == 0 else 3) - (1 if m else 0)
-    return (6 if m else 7) + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 4
+    return eval_slots(kind, m) + 2
 
 
-def fused_slots_per_w(kind, m):
-    """Slots per W entry of the fused on-the-fly split forms: the evaluation above
-    (7 full-rate, or 6 with an integer ratio, plus the exp2 / sqrt), 2 for
-    A_e q e1 - A_i q e2, and 4 for the hi/lo split (two conversions to the 16-bit
-    type at half a slot each, as pairs are converted by one instruction, the hi
-    value back to FP32, the subtraction and the 2^c scaling)."""
-    trans = (2 if kind == 0 else 3) - (1 if m else 0)
-    return (6 if m else 7) + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 2 + 4
+def fused_slots_per_w(kind, m, fp16=False):
+    """Slots per W entry of the fused on-the-fly split forms: the evaluation of u
+    above (the weights sit in G), and 3 for the hi/lo split (two conversions of a pair of entries at half a slot each, the hi value
+    back to FP32, the subtraction); FP16 adds the lift of u (its 2^11 remainder
+    scaling fuses into the subtraction)."""
+    return eval_slots(kind, m) + 3 + (1 if fp16 else 0)
 
 
 def sym_kernel_name(kind, m, periodic=False):
@@ -111,6 +115,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel instead of replaying graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="also run the roofline microbenchmarks")
+    ap.add_argument("--probes-only", action="store_true",
+                    help="run only the roofline microbenchmarks and print their rates as one JSON line")
     ap.add_argument("--ens-rk4-steps", type=int, default=10,
                     help="RK4 steps of the ellipsoid-ensemble comparison leg (0 = skip it)")
     ap.add_argument("--batch-rk4-steps", type=int, default=20,
@@ -239,6 +245,14 @@ def ensemble_leg(P, torch, args):
             entry["roofline"] = {"bound": "hbm", "achieved": wbytes / avg / 1e9, "peak": HBM_PEAK / 1e9,
                                  "unit": "GB/s", "frac": wbytes / avg / HBM_PEAK,
                                  "traffic": measured_traffic(kname), "kernel": kname}
+        elif form == P.FORM_ONTHEFLY_FP32:
+            # one-sided multi-state pair sum: per target-source pair one evaluation of u per
+            # block of 16 states (no integer-ratio shortcut in this kernel) + 1 FMA per state
+            kname = "k_otf_pair_sum<%d,1,16>" % w.kernel_kind
+            slots = float(prob.npad) ** 2 * (-(-64 // 16) * eval_slots(w.kernel_kind, 0) + 64)
+            entry["roofline"] = {"bound": "alu", "achieved": slots / avg / 1e12, "peak": VALU_LANES_PER_S / 1e12,
+                                 "unit": "Tslot/s", "frac": slots / avg / VALU_LANES_PER_S, "traffic": None,
+                                 "kernel": kname}
         elif form in (P.FORM_ONTHEFLY_BF16X3, P.FORM_ONTHEFLY_FP16X3):
             # every W entry evaluated once per launch (64 states share it) on the vector
             # units; the matrix cores do 3 products x 2 flops x 64 states per entry
@@ -246,10 +260,11 @@ def ensemble_leg(P, torch, args):
             wvals = float(prob.npad) ** 2
             kname = "k_mfma_otf<%s,%d,2>" % ("bf16" if nm == "otf_bf16x3" else "fp16",
                                              w.kernel_kind + 4 * (m - 1 if m else 0))
-            achieved = wvals * fused_slots_per_w(w.kernel_kind, m) / avg
+            fp16 = nm == "otf_fp16x3"
+            achieved = wvals * fused_slots_per_w(w.kernel_kind, m, fp16) / avg
             entry["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANES_PER_S / 1e12,
                                  "unit": "Tslot/s", "frac": achieved / VALU_LANES_PER_S, "traffic": None, "kernel": kname,
-                                 "slots_per_w": fused_slots_per_w(w.kernel_kind, m),
+                                 "slots_per_w": fused_slots_per_w(w.kernel_kind, m, fp16),
                                  "mfma_tflops": wvals * 384.0 / avg / 1e12,
                                  "mfma_frac": wvals * 384.0 / avg / MFMA_BF16_PEAK}
         out[nm] = entry
@@ -300,13 +315,13 @@ def batch_leg(P, torch, args):
     t1 = time.perf_counter()
     pair_ints = sum(4.0 * args.batch_rk4_steps * float(w.n) ** 2 * w.b for w in ws_list)
     # algorithmic slots of the (one-sided) pair kernel per stage: per target-source pair and
-    # state block one Gaussian evaluation (3 sub + 3 for r^2 + rho t + 2 exp2 = 15 slots),
-    # plus 2 FMAs per state; blocks of 1, 4 or 16 states
+    # state block one evaluation of u (eval_slots: 16 for the Gaussian), plus 1 FMA per
+    # state; blocks of 1, 4 or 16 states
     slots = 0.0
     for w in ws_list:
         npad = -(-w.n // 256) * 256
         bs = 1 if w.b == 1 else (4 if w.b <= 4 else 16)
-        slots += float(npad) ** 2 * (-(-w.b // bs) * (7 + 2 * TRANS_COST) + 2 * w.b)
+        slots += float(npad) ** 2 * (-(-w.b // bs) * eval_slots(0, 0) + w.b)
     slots *= 4.0 * args.batch_rk4_steps
     chunk, wgs = batch.config
     return {"workload": "48 problems, N log-uniform [1000, 40000], sphere/torus/ellipsoid/bumpy, Gauss Mexican hat, "
@@ -453,7 +468,8 @@ def probes(P, torch, ctx):
     out = {}
     grid_threads = torch.cuda.get_device_properties(0).multi_processor_count * 8 * 256
     small = torch.empty(grid_threads * 4 + 256, dtype=torch.uint8, device="cuda")
-    for name, which, size in (("fma_lane_ops", 0, 20000), ("exp_lane_ops", 1, 5000), ("sqrt_lane_ops", 2, 5000),
+    for name, which, size in (("fma_lane_ops", 0, 20000), ("fma_vop3_lane_ops", 6, 20000), ("exp_lane_ops", 1, 5000),
+                              ("sqrt_lane_ops", 2, 5000), ("fma_exp_mix_lane_ops", 7, 5000),
                               ("mfma_bf16_flops", 5, 20000)):
         r = ctypes.c_double()
         P._lib.check(L.nfr_probe(ctx.handle, which, size, small.data_ptr(), small.numel(), ctypes.byref(r)))
@@ -483,6 +499,9 @@ def main():
     import paper_2504_13379_amd as P
     from workloads import configs as C
 
+    if args.probes_only:
+        print(json.dumps({"probes": probes(P, torch, P.Context(0))}), flush=True)
+        return
     w = C.torus_exp(32768, steps=args.rk4_steps)
     q = C.area_share_weights(w.surface)
     stream = torch.cuda.Stream()

@@ -139,7 +139,10 @@ int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms);
  *   HBM_READ:       bytes per second reading `size` floats from buf_dev;
  *   HBM_COPY:       bytes per second (read + write) copying `size` floats from
  *                   the first half of buf_dev to the second half;
- *   MFMA_BF16:      FLOP per second of 32x32x16 BF16 MFMA, `size` iterations.
+ *   MFMA_BF16:      FLOP per second of 32x32x16 BF16 MFMA, `size` iterations;
+ *   FMA_VOP3:       as FMA with the three-operand encoding (x <- x*m + b);
+ *   FMA_EXP:        lane-operations per second of a mix of one exp2 and three
+ *                   accumulating FMAs per chain and iteration. 
  * buf_dev must hold 4*size bytes plus one float per thread of a grid of
  * 8 workgroups per compute unit (HBM_READ), 8*size bytes (HBM_COPY), or one
  * float per thread (others). */
@@ -149,7 +152,9 @@ enum nfr_probe_kind {
   NFR_PROBE_SQRT = 2,
   NFR_PROBE_HBM_READ = 3,
   NFR_PROBE_HBM_COPY = 4,
-  NFR_PROBE_MFMA_BF16 = 5
+  NFR_PROBE_MFMA_BF16 = 5,
+  NFR_PROBE_FMA_VOP3 = 6,
+  NFR_PROBE_FMA_EXP = 7
 };
 int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t buf_bytes, double* rate);
 

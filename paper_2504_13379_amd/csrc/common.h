@@ -34,6 +34,10 @@ struct ProblemView {
 //   exponential: t = |sig (x_i - x_j)|,    sig = log2 e / s_e,        rho = s_e / s_i
 // and the inhibitory one exp2(-rho t); w = A_e exp2(-t) - A_i exp2(-rho t).
 // `per` is the scaled period sig * L of a periodic problem (0 otherwise).
+// The forward pair sums accumulate the normalised kernel
+//   u = exp2(-t) + kappa exp2(-rho t),  kappa = -A_i / A_e,  w = amp u (amp = A_e),
+// one value per pair instead of the two exponentials separately (a kernel with
+// A_e = 0 is first rewritten as its single inhibitory term, see norm_kernel).
 //
 // Pair kernels take KIND = kernel kind (bit 0: 0 Gaussian, 1 exponential)
 // plus 2 for a periodic problem.
@@ -43,6 +47,8 @@ struct PairParams {
   double Ae;
   double Ai;
   float per;
+  float kappa;
+  double amp;
 };
 
 // Squared scaled distance of a pair from its coordinate differences.  For a

@@ -77,6 +77,39 @@ __global__ __launch_bounds__(kWG) void k_source_prep(const double* __restrict__ 
 
 // ------------------------------------------------------------------ on-the-fly pair sum
 
+// Length scales in an integer ratio, rho = 1/m with m in {2, 3, 4}: the
+// excitatory exponential is the m-th power of the inhibitory one,
+// exp2(-t) = exp2(-rho t)^m, so one exponential per pair suffices.  KIND bits
+// 2-3 hold m - 1 (0: two exponentials); such launches scale the coordinates
+// (and the period) by the inhibitory length, so the kernel's t is rho t.
+template <int KIND>
+constexpr int sym_pow() {
+  return (KIND >> 2) == 0 ? 0 : (KIND >> 2) + 1;
+}
+
+template <int M>
+__device__ __forceinline__ float ipow(float x) {
+  if (M == 2) return x * x;
+  if (M == 3) return x * x * x;
+  const float x2 = x * x;
+  return x2 * x2;
+}
+
+// Normalised kernel u = exp2(-t_e) + kappa exp2(-t_i) of one pair from its
+// scaled distance t (r^2 or r).  Without an integer ratio, t = t_e and
+// t_i = rho t; with sym_pow (coordinates in units of the inhibitory length)
+// t = t_i, exp2(-t_e) = exp2(-t)^m and u = e (e^(m-1) + kappa), e = exp2(-t).
+template <int KIND>
+__device__ __forceinline__ float pair_u(float t, float rho, float kappa) {
+  constexpr int M = sym_pow<KIND>();
+  if (M == 0) return fmaf(__builtin_amdgcn_exp2f(-(t * rho)), kappa, __builtin_amdgcn_exp2f(-t));
+  const float e = __builtin_amdgcn_exp2f(-t);
+  if (M == 2) return e * (e + kappa);
+  if (M == 3) return e * fmaf(e, e, kappa);
+  const float e2 = e * e;
+  return fmaf(e2, e2, kappa * e);
+}
+
 // Partial pair sums over one source chunk:
 //   part[(split*B + b)*npad + i] = sum_{j in chunk(split)} w(|x_i - x_j|) g[b*npad + j]
 // Grid: x = target tiles of kWG*TPT targets (thread t owns tile + t + kWG*k),
@@ -84,8 +117,8 @@ __global__ __launch_bounds__(kWG) void k_source_prep(const double* __restrict__ 
 //       z = state blocks of BS states.
 // Sources are staged kWG at a time in LDS as scaled float4 coordinates plus
 // their g values and read back as broadcasts.  Each thread sums one LDS tile
-// of kWG sources in FP32 (e and i parts separately), then folds the tile sum
-// into FP64 accumulators: A_e * sum_e - A_i * sum_i.
+// of kWG sources in FP32 (the normalised kernel u, see PairParams), then folds
+// the tile sum into FP64 accumulators: amp * sum.
 // Targets per thread for a block of BS states (TPT x BS accumulators per thread).
 __host__ __device__ constexpr int otf_tpt(int bs) { return bs <= 4 ? 4 : (bs == 8 ? 2 : 1); }
 
@@ -116,6 +149,7 @@ __device__ inline void otf_tile(const float4* __restrict__ src, const float* __r
   int64_t j_end = j_begin + chunk;
   if (j_end > npad) j_end = npad;
   const float rho = pp.rho;
+  const float kappa = pp.kappa;
 
   for (int64_t j0 = j_begin; j0 < j_end; j0 += kWG) {
     {
@@ -126,11 +160,11 @@ __device__ inline void otf_tile(const float4* __restrict__ src, const float* __r
         s_g[b][tid] = (b0 + b < B) ? g[(int64_t)(b0 + b) * npad + j0 + tid] : 0.0f;
     }
     __syncthreads();
-    float ae[TPT][BS], ai[TPT][BS];
+    float a[TPT][BS];
 #pragma unroll
     for (int k = 0; k < TPT; ++k)
 #pragma unroll
-      for (int b = 0; b < BS; ++b) ae[k][b] = ai[k][b] = 0.0f;
+      for (int b = 0; b < BS; ++b) a[k][b] = 0.0f;
 
 #pragma unroll 4
     for (int jj = 0; jj < kWG; ++jj) {
@@ -142,20 +176,16 @@ __device__ inline void otf_tile(const float4* __restrict__ src, const float* __r
       for (int k = 0; k < TPT; ++k) {
         const float r2 = pair_r2<KIND>(xi[k] - s.x, yi[k] - s.y, zi[k] - s.z, pp.per);
         const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
-        const float e1 = __builtin_amdgcn_exp2f(-t);
-        const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
+        const float u = pair_u<KIND>(t, rho, kappa);
 #pragma unroll
-        for (int b = 0; b < BS; ++b) {
-          ae[k][b] = fmaf(e1, gv[b], ae[k][b]);
-          ai[k][b] = fmaf(e2, gv[b], ai[k][b]);
-        }
+        for (int b = 0; b < BS; ++b) a[k][b] = fmaf(u, gv[b], a[k][b]);
       }
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < TPT; ++k)
 #pragma unroll
-      for (int b = 0; b < BS; ++b) acc[k][b] += pp.Ae * (double)ae[k][b] - pp.Ai * (double)ai[k][b];
+      for (int b = 0; b < BS; ++b) acc[k][b] += pp.amp * (double)a[k][b];
   }
 
 #pragma unroll
@@ -222,24 +252,6 @@ __device__ inline void sym_decode(int64_t p, int64_t* I, int64_t* J) {
   *I = p - j * (j + 1) / 2;
 }
 
-// Length scales in an integer ratio, rho = 1/m with m in {2, 3, 4}: the
-// excitatory exponential is the m-th power of the inhibitory one,
-// exp2(-t) = exp2(-rho t)^m, so one exponential per pair suffices.  KIND bits
-// 2-3 hold m - 1 (0: two exponentials); such launches scale the coordinates
-// (and the period) by the inhibitory length, so the kernel's t is rho t.
-template <int KIND>
-constexpr int sym_pow() {
-  return (KIND >> 2) == 0 ? 0 : (KIND >> 2) + 1;
-}
-
-template <int M>
-__device__ __forceinline__ float ipow(float x) {
-  if (M == 2) return x * x;
-  if (M == 3) return x * x * x;
-  const float x2 = x * x;
-  return x2 * x2;
-}
-
 template <int KIND, bool COLS>
 __device__ inline void sym_tile(const float4* __restrict__ src, const float* __restrict__ g, int64_t npad,
                                 const PairParams& pp, double* __restrict__ part, int64_t I, int64_t J,
@@ -247,6 +259,7 @@ __device__ inline void sym_tile(const float4* __restrict__ src, const float* __r
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const float rho = pp.rho;
+  const float kappa = pp.kappa;
   float xi[kSymTPT], yi[kSymTPT], zi[kSymTPT], gi[kSymTPT];
 #pragma unroll
   for (int k = 0; k < kSymTPT; ++k) {
@@ -269,38 +282,29 @@ __device__ inline void sym_tile(const float4* __restrict__ src, const float* __r
     const int64_t j = J * kSymTile + grp * 64 + lane;
     const float4 s4 = src[j];
     float sx = s4.x * pp.sig, sy = s4.y * pp.sig, sz = s4.z * pp.sig, sg = g[j];
-    float ce = 0.0f, ci = 0.0f;
-    float ae[kSymTPT], ai[kSymTPT];
+    float cs = 0.0f;
+    float rs[kSymTPT];
 #pragma unroll
-    for (int k = 0; k < kSymTPT; ++k) ae[k] = ai[k] = 0.0f;
+    for (int k = 0; k < kSymTPT; ++k) rs[k] = 0.0f;
 #pragma unroll 2
     for (int step = 0; step < 64; ++step) {
 #pragma unroll
       for (int k = 0; k < kSymTPT; ++k) {
         const float r2 = pair_r2<KIND>(xi[k] - sx, yi[k] - sy, zi[k] - sz, pp.per);
         const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
-        // with sym_pow the coordinates are scaled by the inhibitory length: t is already rho t
-        const float e2 = __builtin_amdgcn_exp2f(-(sym_pow<KIND>() == 0 ? t * rho : t));
-        const float e1 = sym_pow<KIND>() == 0 ? __builtin_amdgcn_exp2f(-t) : ipow<sym_pow<KIND>()>(e2);
-        ae[k] = fmaf(e1, sg, ae[k]);
-        ai[k] = fmaf(e2, sg, ai[k]);
-        if (COLS) {
-          ce = fmaf(e1, gi[k], ce);
-          ci = fmaf(e2, gi[k], ci);
-        }
+        const float u = pair_u<KIND>(t, rho, kappa);
+        rs[k] = fmaf(u, sg, rs[k]);
+        if (COLS) cs = fmaf(u, gi[k], cs);
       }
       sx = wave_ror1(sx);
       sy = wave_ror1(sy);
       sz = wave_ror1(sz);
       sg = wave_ror1(sg);
-      if (COLS) {
-        ce = wave_ror1(ce);
-        ci = wave_ror1(ci);
-      }
+      if (COLS) cs = wave_ror1(cs);
     }
 #pragma unroll
-    for (int k = 0; k < kSymTPT; ++k) racc[k] += pp.Ae * (double)ae[k] - pp.Ai * (double)ai[k];
-    if (COLS) part[I * npad + j] = pp.Ae * (double)ce - pp.Ai * (double)ci;
+    for (int k = 0; k < kSymTPT; ++k) racc[k] += pp.amp * (double)rs[k];
+    if (COLS) part[I * npad + j] = pp.amp * (double)cs;
   }
   if (kSymSplit == 1) {
 #pragma unroll

@@ -1,11 +1,13 @@
 // Split-precision W form on the matrix cores (BF16 or FP16, hi + lo).
 //
 //   W_ij = w(|x_i - x_j|) q_j  (targets i, sources j; paper eq. NFODETilde),
-//   W' = 2^sW W = Whi + 2^-c Wlo,   G = f(U) = Ghi + 2^-c Glo   (c = 8 BF16, 11 FP16),
+//   W' = 2^sW W = Whi + 2^-c Wlo,   G = f(U) = Ghi + 2^-c Glo   (c = 0 BF16, 11 FP16),
 //   Y = 2^-sW [ Whi Ghi + 2^-c (Whi Glo + Wlo Ghi) ]     (the lo*lo product is dropped).
 //
 // The two FP32 accumulators (main, correction) are kept apart and only combined
-// in the epilogue.  sW lifts W into FP16's normal range (0 for BF16).
+// in the epilogue.  sW lifts W into FP16's normal range (0 for BF16), and the
+// FP16 remainders are lifted by 2^c for the same reason; BF16 has FP32's
+// exponent range, so its remainders need no lift (c = 0).
 //
 // Buffers: W = [header 256 B | tiles]: Whi and Wlo, each npad x npad (rows =
 // targets, zero beyond n), cut into 32 x 16 tiles, each tile 64 lanes x 8
@@ -40,7 +42,8 @@ typedef __attribute__((ext_vector_type(4))) unsigned int u32x4_t;
 template <typename T> struct MfmaTraits;
 template <> struct MfmaTraits<__bf16> {
   typedef bf16x8_t vec;
-  static constexpr int c = 8;
+  static constexpr int c = 0;
+  static constexpr bool fp16 = false;
   static __device__ inline f32x16_t mma(vec a, vec b, f32x16_t acc) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   }
@@ -48,6 +51,7 @@ template <> struct MfmaTraits<__bf16> {
 template <> struct MfmaTraits<_Float16> {
   typedef f16x8_t vec;
   static constexpr int c = 11;
+  static constexpr bool fp16 = true;
   static __device__ inline f32x16_t mma(vec a, vec b, f32x16_t acc) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
   }
@@ -134,12 +138,31 @@ __global__ __launch_bounds__(kWG) void k_mfma_w_build(const double* __restrict__
   *reinterpret_cast<u32x4_t*>(Wt + off + 4 * 512) = vl;
 }
 
-// Ghi/Glo[b*npad + j] from f_b(u[b*n + j]) for b < Bp, j < npad (zero outside b < B, j < n);
-// optionally copies u into v.
+// 14 - ceil(log2(bound)) for FP16 (puts |x| <= bound just below 2^14), else 0;
+// bound = f 2^e with f in [0.5, 1).
+__device__ inline int mfma_scale_exp(double bound, bool fp16) {
+  if (!fp16 || !(bound > 0.0)) return 0;
+  int e;
+  const double f = frexp(bound, &e);
+  return 14 - (f == 0.5 ? e - 1 : e);
+}
+
+// Factor of source j in G: 1 for the W forms (q sits in W); q_j 2^sG for the
+// fused forms (qd non-null), whose kernel values carry no weight, with sG from
+// max |q| (FP16 only).
+template <typename T>
+__device__ inline double source_factor(const double* __restrict__ qd, const double* __restrict__ qmax, int64_t j) {
+  if (!qd) return 1.0;
+  return ldexp(qd[j], mfma_scale_exp(qmax[0], MfmaTraits<T>::fp16));
+}
+
+// Ghi/Glo[b*npad + j] from f_b(u[b*n + j]) (times source_factor) for b < Bp,
+// j < npad (zero outside b < B, j < n); optionally copies u into v.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_mfma_prep(const double* __restrict__ u, int64_t n, int64_t npad, int B,
-                                                   int64_t Bp, Firing fr, T* __restrict__ Ghi, T* __restrict__ Glo,
-                                                   double* __restrict__ v_copy) {
+                                                   int64_t Bp, Firing fr, const double* __restrict__ qd,
+                                                   const double* __restrict__ qmax, T* __restrict__ Ghi,
+                                                   T* __restrict__ Glo, double* __restrict__ v_copy) {
   const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (idx >= npad * Bp) return;
   const int b = (int)(idx / npad);
@@ -147,7 +170,7 @@ __global__ __launch_bounds__(kWG) void k_mfma_prep(const double* __restrict__ u,
   double g = 0.0;
   if (b < B && j < n) {
     const double uj = u[(int64_t)b * n + j];
-    g = sigmoid(uj, fr.beta, state_theta(fr, b));
+    g = sigmoid(uj, fr.beta, state_theta(fr, b)) * source_factor<T>(qd, qmax, j);
     if (v_copy) v_copy[(int64_t)b * n + j] = uj;
   }
   T hi, lo;
@@ -327,42 +350,44 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Wt,
 // every W tile is evaluated by the vector units straight into the A-operand
 // layout, so no W matrix exists and nothing but G and the coordinates is read.
 //
+// The weights move into G (G_bj = q_j 2^sG f_b(u_bj), see source_factor), so
+// the tile entries are the bare radial kernel normalised by its excitatory
+// amplitude (pair_u: u = exp2(-t) + kappa exp2(-rho t)), and amp 2^-sG is
+// applied in the epilogue.  This keeps the evaluation at 3 subtractions, 3
+// multiply-adds for r^2 (plus the square root of the exponential kernel),
+// 1 multiply for rho t, 2 exp2 (or one exp2 and 1-3 multiplies for a length
+// ratio 1/m) and 1 multiply-add per entry.
 // Lane l = m + 32 h evaluates, for MFMA step kb, the 8 entries of row m and
-// columns 16 kb + 8 h .. +7 in FP32: the pair term of the on-the-fly kernels
-// (PairParams, template code KIND as in the symmetric kernel, bits 2-3 an
-// integer length ratio) times A_e q_j 2^sW and A_i q_j 2^sW, then splits
-// each value into hi + 2^-c lo.  Each W value is evaluated once and used for
-// all 32 NB states of the workgroup (3 NB products per 8 values).
-// The column data of a pipeline step (scaled x, y, z and the two scaled
-// amplitudes) sits in a double-buffered LDS tile read by broadcast: the 32
-// lanes of a half-wave read the same address.  sW is derived in the kernel
-// from max |q| (qmax) exactly as k_mfma_scale derives it.
+// columns 16 kb + 8 h .. +7 in FP32 and splits each into hi + 2^-c lo; each
+// entry serves all 32 NB states of the workgroup (3 NB products per 8
+// entries; BF16 keeps the main and correction products in one accumulator,
+// as its remainders are not lifted).  The column coordinates of a pipeline
+// step sit in a double-buffered LDS tile read by broadcast (the 32 lanes of
+// a half-wave read the same address).  Within a step the entries of MFMA
+// step kb + 1 are evaluated before the products of step kb are issued, so
+// the vector units work while the matrix cores run.
 struct MfmaOtfParams {
   float sig, rho, per;
-  double Ae, Ai;
-  const double* qmax;
+  float kappa;         // -A_i / A_e (PairParams)
+  double amp;          // A_e
+  const double* qmax;  // max_j |q_j| (for the FP16 source lift sG)
 };
 
-__device__ inline int mfma_scale_exp(double bound, bool fp16) {
-  // 14 - ceil(log2(bound)); bound = f 2^e with f in [0.5, 1)
-  if (!fp16 || !(bound > 0.0)) return 0;
-  int e;
-  const double f = frexp(bound, &e);
-  return 14 - (f == 0.5 ? e - 1 : e);
-}
-
+#ifndef NFR_MFMA_OTF_MIN_WGS
+#define NFR_MFMA_OTF_MIN_WGS 2
+#endif
 template <typename T, int KIND, int NB>
-__global__ __launch_bounds__(kWG, 2) void k_mfma_otf(const float4* __restrict__ src, const double* __restrict__ qd,
-                                                     const T* __restrict__ Ghi, const T* __restrict__ Glo,
-                                                     int64_t npad, int B, int64_t kchunk, MfmaOtfParams op,
-                                                     double* __restrict__ part) {
+__global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
+                                                     const T* __restrict__ Glo, int64_t npad, int B, int64_t kchunk,
+                                                     MfmaOtfParams op, double* __restrict__ part) {
   typedef typename MfmaTraits<T>::vec V;
   constexpr int c = MfmaTraits<T>::c;
+  constexpr bool kTwoAcc = MfmaTraits<T>::fp16;
   constexpr int NS = 32 * NB;
   constexpr int ROWCH = kMfmaStep / 8;
   constexpr int CHUNKS = NS * 2 * ROWCH / kWG;
   __shared__ __attribute__((aligned(16))) T sG[2][2][NS][kMfmaLdsStride];
-  __shared__ __attribute__((aligned(16))) float sS[2][5][kMfmaStep];
+  __shared__ __attribute__((aligned(16))) float sS[2][3][kMfmaStep];
 
   const int64_t wg = blockIdx.x;
   const int split = (int)(wg % kMfmaSplits);
@@ -379,9 +404,9 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf(const float4* __restrict__ 
   if (k_end > npad) k_end = npad;
   const int nsteps = (int)((k_end - k_begin) / kMfmaStep);
 
-  const int sW = mfma_scale_exp((fabs(op.Ae) + fabs(op.Ai)) * op.qmax[0], c == 11);
-  const float ae = (float)ldexp(op.Ae, sW);
-  const float ai = (float)ldexp(op.Ai, sW);
+  // FP16 entries are lifted by 2^sU so that |u| <= 1 + |kappa| sits below 2^14.
+  const int sU = mfma_scale_exp(1.0 + fabs((double)op.kappa), kTwoAcc);
+  const float lift = (float)ldexp(1.0, sU);
   const float4 pr = src[row0 + m];
   const float xi = pr.x * op.sig, yi = pr.y * op.sig, zi = pr.z * op.sig;
 
@@ -403,58 +428,80 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf(const float4* __restrict__ 
 #pragma unroll
     for (int r = 0; r < 16; ++r) accM[nb][r] = accC[nb][r] = 0.0f;
 
-  // Every wave loads the column data of a step (lane = column); wave 0 stores
-  // it.  Loads past the last step re-read the last step.
+  // Every wave loads the column coordinates of a step (lane = column); wave 0
+  // stores them.  Loads past the last step re-read the last step.
   u32x4_t gn[CHUNKS];
   float4 sn;
-  double qn;
   auto load_next = [&](int t) {
     const int64_t tc = t < nsteps ? t : nsteps - 1;
 #pragma unroll
     for (int q = 0; q < CHUNKS; ++q) gn[q] = *reinterpret_cast<const u32x4_t*>(gsrc[q] + tc * kMfmaStep);
-    const int64_t j = k_begin + tc * kMfmaStep + lane;
-    sn = src[j];
-    qn = qd[j];
+    sn = src[k_begin + tc * kMfmaStep + lane];
   };
   auto store_next = [&](int t) {
     const int buf = t & 1;
 #pragma unroll
     for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[buf][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
     if (wave == 0) {
-      const float qf = (float)qn;
       sS[buf][0][lane] = sn.x * op.sig;
       sS[buf][1][lane] = sn.y * op.sig;
       sS[buf][2][lane] = sn.z * op.sig;
-      sS[buf][3][lane] = ae * qf;
-      sS[buf][4][lane] = ai * qf;
+    }
+  };
+  auto eval = [&](int buf, int kb, V& whi, V& wlo) {
+    const int col = 16 * kb + 8 * h;
+    float w[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float r2 = pair_r2<KIND>(xi - sS[buf][0][col + e], yi - sS[buf][1][col + e], zi - sS[buf][2][col + e],
+                                     op.per);
+      const float tt = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+      w[e] = pair_u<KIND>(tt, op.rho, op.kappa);
+      if (kTwoAcc) w[e] *= lift;
+    }
+    // split pairwise: one conversion instruction rounds two entries
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      typedef __attribute__((ext_vector_type(2))) float f2_t;
+      typedef __attribute__((ext_vector_type(2))) T h2_t;
+      const f2_t wv = {w[e], w[e + 1]};
+      const h2_t hv = __builtin_convertvector(wv, h2_t);
+      const f2_t hf = __builtin_convertvector(hv, f2_t);
+      f2_t rv = wv - hf;
+      if (c) rv *= (float)(1 << c);
+      const h2_t lv = __builtin_convertvector(rv, h2_t);
+      whi[e] = hv[0];
+      whi[e + 1] = hv[1];
+      wlo[e] = lv[0];
+      wlo[e + 1] = lv[1];
+    }
+  };
+  auto mma = [&](int buf, int kb, const V& whi, const V& wlo) {
+    const int col = 16 * kb + 8 * h;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const V bh = *reinterpret_cast<const V*>(&sG[buf][0][nb * 32 + m][col]);
+      const V bl = *reinterpret_cast<const V*>(&sG[buf][1][nb * 32 + m][col]);
+      accM[nb] = MfmaTraits<T>::mma(whi, bh, accM[nb]);
+      if (kTwoAcc) {
+        accC[nb] = MfmaTraits<T>::mma(whi, bl, accC[nb]);
+        accC[nb] = MfmaTraits<T>::mma(wlo, bh, accC[nb]);
+      } else {
+        accM[nb] = MfmaTraits<T>::mma(whi, bl, accM[nb]);
+        accM[nb] = MfmaTraits<T>::mma(wlo, bh, accM[nb]);
+      }
     }
   };
   auto compute = [&](int t) {
     const int buf = t & 1;
+    V h0, l0, h1, l1;
+    eval(buf, 0, h0, l0);
 #pragma unroll
-    for (int kb = 0; kb < kMfmaKb; ++kb) {
-      const int col = 16 * kb + 8 * h;
-      V whi, wlo;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float r2 = pair_r2<KIND>(xi - sS[buf][0][col + e], yi - sS[buf][1][col + e], zi - sS[buf][2][col + e],
-                                       op.per);
-        const float tt = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
-        const float e2 = __builtin_amdgcn_exp2f(-(sym_pow<KIND>() == 0 ? tt * op.rho : tt));
-        const float e1 = sym_pow<KIND>() == 0 ? __builtin_amdgcn_exp2f(-tt) : ipow<sym_pow<KIND>()>(e2);
-        const float w = fmaf(sS[buf][3][col + e], e1, -(sS[buf][4][col + e] * e2));
-        const T hi = (T)w;
-        whi[e] = hi;
-        wlo[e] = (T)((w - (float)hi) * (float)(1 << c));
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const V bh = *reinterpret_cast<const V*>(&sG[buf][0][nb * 32 + m][col]);
-        const V bl = *reinterpret_cast<const V*>(&sG[buf][1][nb * 32 + m][col]);
-        accM[nb] = MfmaTraits<T>::mma(whi, bh, accM[nb]);
-        accC[nb] = MfmaTraits<T>::mma(whi, bl, accC[nb]);
-        accC[nb] = MfmaTraits<T>::mma(wlo, bh, accC[nb]);
-      }
+    for (int kb = 0; kb < kMfmaKb; kb += 2) {
+      if (kb + 1 < kMfmaKb) eval(buf, kb + 1, h1, l1);
+      mma(buf, kb, h0, l0);
+      if (kb + 2 < kMfmaKb) eval(buf, kb + 2, h0, l0);
+      if (kb + 1 < kMfmaKb) mma(buf, kb + 1, h1, l1);
     }
   };
   // step t: issue the loads of step t + 1, evaluate and multiply step t from
@@ -471,8 +518,9 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf(const float4* __restrict__ 
     }
   }
 
-  const double sm = ldexp(1.0, -sW);
-  const double sc = ldexp(1.0, -(sW + c));
+  const int sG_ = mfma_scale_exp(op.qmax[0], kTwoAcc);
+  const double sm = op.amp * ldexp(1.0, -(sG_ + sU));
+  const double sc = op.amp * ldexp(1.0, -(sG_ + sU + c));
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int b = sg * NS + nb * 32 + m;
@@ -481,7 +529,7 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf(const float4* __restrict__ 
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int64_t i = row0 + 8 * (r / 4) + 4 * h + (r % 4);
-      dst[i] = (double)accM[nb][r] * sm + (double)accC[nb][r] * sc;
+      dst[i] = kTwoAcc ? (double)accM[nb][r] * sm + (double)accC[nb][r] * sc : (double)accM[nb][r] * sm;
     }
   }
 }
@@ -492,7 +540,8 @@ template <typename T>
 __global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__ part, int nsplit, int64_t n,
                                                       int64_t npad, int B, int stage, double dt,
                                                       double* __restrict__ u, double* __restrict__ v,
-                                                      double* __restrict__ ksum, Firing fr, T* __restrict__ Ghi,
+                                                      double* __restrict__ ksum, Firing fr, const double* __restrict__ qd,
+                                                      const double* __restrict__ qmax, T* __restrict__ Ghi,
                                                       T* __restrict__ Glo, double* __restrict__ k1_out,
                                                       const double* __restrict__ gamma) {
   const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
@@ -521,7 +570,7 @@ __global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__
   }
   v[idx] = vn;
   T hi, lo;
-  split_hi_lo<T>(sigmoid(vn, fr.beta, state_theta(fr, b)), hi, lo);
+  split_hi_lo<T>(sigmoid(vn, fr.beta, state_theta(fr, b)) * source_factor<T>(qd, qmax, i), hi, lo);
   Ghi[(int64_t)b * npad + i] = hi;
   Glo[(int64_t)b * npad + i] = lo;
 }
@@ -533,6 +582,7 @@ __global__ __launch_bounds__(kWG) void k_mfma_ab5_combine(const double* __restri
                                                           int64_t npad, int B, double dt, Ab5Weights wt,
                                                           int4 slots03, int slot4, double* __restrict__ u,
                                                           double* __restrict__ hist, Firing fr,
+                                                          const double* __restrict__ qd, const double* __restrict__ qmax,
                                                           T* __restrict__ Ghi, T* __restrict__ Glo) {
   const int64_t idx = (int64_t)blockIdx.x * kWG + threadIdx.x;
   const int64_t nb = n * (int64_t)B;
@@ -549,7 +599,7 @@ __global__ __launch_bounds__(kWG) void k_mfma_ab5_combine(const double* __restri
   const double un = ui + dt * incr;
   u[idx] = un;
   T hi, lo;
-  split_hi_lo<T>(sigmoid(un, fr.beta, state_theta(fr, b)), hi, lo);
+  split_hi_lo<T>(sigmoid(un, fr.beta, state_theta(fr, b)) * source_factor<T>(qd, qmax, i), hi, lo);
   Ghi[(int64_t)b * npad + i] = hi;
   Glo[(int64_t)b * npad + i] = lo;
 }
@@ -580,7 +630,7 @@ inline void launch_mfma_w_build_t(const ProblemView& pv, const KernelF64& kp, vo
   MfmaBufs m = mfma_bufs(W, pv.npad);
   const double amp = fabs(kp.Ae) + fabs(kp.Ai);
   hipLaunchKernelGGL(k_mfma_scale<T>, dim3(1), dim3(kWG), 0, s, pv.q, pv.npad, amp,
-                     (int)(MfmaTraits<T>::c == 11), const_cast<float*>(m.header));
+                     (int)MfmaTraits<T>::fp16, const_cast<float*>(m.header));
   hipLaunchKernelGGL(k_mfma_w_build<T>, dim3((unsigned)pv.npad, (unsigned)ceil_div(pv.npad / 8, kWG)), dim3(kWG), 0, s,
                      pv.xyz, pv.q, pv.n, pv.npad, kp, m.header, static_cast<T*>(m.tiles));
 }
@@ -593,21 +643,24 @@ inline void launch_mfma_w_build(const ProblemView& pv, int form, const KernelF64
 }
 
 template <typename T>
-inline void launch_mfma_prep_t(const ProblemView& pv, int B, const double* u, const Firing& fr, void* g, double* v,
-                               hipStream_t s) {
+inline void launch_mfma_prep_t(const ProblemView& pv, int B, const double* u, const Firing& fr, const double* qd,
+                               void* g, double* v, hipStream_t s) {
   void *ghi, *glo;
   mfma_g_split(g, pv.npad, B, &ghi, &glo);
   const int64_t Bp = mfma_bp(B);
   hipLaunchKernelGGL(k_mfma_prep<T>, dim3((unsigned)ceil_div(pv.npad * Bp, kWG)), dim3(kWG), 0, s, u, pv.n, pv.npad,
-                     B, Bp, fr, static_cast<T*>(ghi), static_cast<T*>(glo), v);
+                     B, Bp, fr, qd, pv.qmax, static_cast<T*>(ghi), static_cast<T*>(glo), v);
 }
+
+// Weights in G for the fused forms (their kernel values carry none), not for the W forms.
+inline const double* mfma_source_q(const ProblemView& pv, int form) { return mfma_has_w(form) ? nullptr : pv.q; }
 
 inline void launch_mfma_prep(const ProblemView& pv, int form, int B, const double* u, const Firing& fr, float* g,
                              double* v, hipStream_t s) {
   if (mfma_is_bf16(form))
-    launch_mfma_prep_t<__bf16>(pv, B, u, fr, g, v, s);
+    launch_mfma_prep_t<__bf16>(pv, B, u, fr, mfma_source_q(pv, form), g, v, s);
   else
-    launch_mfma_prep_t<_Float16>(pv, B, u, fr, g, v, s);
+    launch_mfma_prep_t<_Float16>(pv, B, u, fr, mfma_source_q(pv, form), g, v, s);
 }
 
 template <typename T>
@@ -644,11 +697,11 @@ inline void launch_mfma_otf_t(const ProblemView& pv, const MfmaOtfParams& op, in
   const int64_t kchunk = round_up(ceil_div(pv.npad, kMfmaSplits), kMfmaStep);
   const unsigned grid_x = (unsigned)(pv.npad / kMfmaRowsPerWG * kMfmaSplits);
   if (B <= 32) {
-    hipLaunchKernelGGL((k_mfma_otf<T, KIND, 1>), dim3(grid_x, 1), dim3(kWG), 0, s, pv.src, pv.q,
+    hipLaunchKernelGGL((k_mfma_otf<T, KIND, 1>), dim3(grid_x, 1), dim3(kWG), 0, s, pv.src,
                        static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad, B, kchunk, op, part);
   } else {
     hipLaunchKernelGGL((k_mfma_otf<T, KIND, 2>), dim3(grid_x, (unsigned)(mfma_bp(B) / 64)), dim3(kWG), 0, s, pv.src,
-                       pv.q, static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad, B, kchunk, op, part);
+                       static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad, B, kchunk, op, part);
   }
 }
 
@@ -664,43 +717,46 @@ inline void launch_mfma_otf(const ProblemView& pv, int form, const MfmaOtfParams
 
 template <typename T>
 inline void launch_mfma_combine_t(const ProblemView& pv, int B, int stage, double dt, double* u, double* v,
-                                  double* ksum, const double* part, int nsplit, const Firing& fr, void* g,
-                                  double* k1_out, const double* gamma, hipStream_t s) {
+                                  double* ksum, const double* part, int nsplit, const Firing& fr, const double* qd,
+                                  void* g, double* k1_out, const double* gamma, hipStream_t s) {
   void *ghi, *glo;
   mfma_g_split(g, pv.npad, B, &ghi, &glo);
   const int64_t total = pv.n * (int64_t)B;
   hipLaunchKernelGGL(k_mfma_combine<T>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit, pv.n,
-                     pv.npad, B, stage, dt, u, v, ksum, fr, static_cast<T*>(ghi), static_cast<T*>(glo), k1_out,
-                     gamma);
+                     pv.npad, B, stage, dt, u, v, ksum, fr, qd, pv.qmax, static_cast<T*>(ghi), static_cast<T*>(glo),
+                     k1_out, gamma);
 }
 
 inline void launch_mfma_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, double* v,
                                 double* ksum, const double* part, int nsplit, const Firing& fr, float* g,
                                 double* k1_out, const double* gamma, hipStream_t s) {
   if (mfma_is_bf16(form))
-    launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, gamma, s);
+    launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, mfma_source_q(pv, form), g, k1_out,
+                                  gamma, s);
   else
-    launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, g, k1_out, gamma, s);
+    launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, mfma_source_q(pv, form), g,
+                                    k1_out, gamma, s);
 }
 
 template <typename T>
 inline void launch_mfma_ab5_t(const ProblemView& pv, int B, double dt, const Ab5Weights& wt, int4 s03, int s4,
-                              double* u, double* hist, const double* part, int nsplit, const Firing& fr, void* g,
-                              hipStream_t s) {
+                              double* u, double* hist, const double* part, int nsplit, const Firing& fr,
+                              const double* qd, void* g, hipStream_t s) {
   void *ghi, *glo;
   mfma_g_split(g, pv.npad, B, &ghi, &glo);
   const int64_t total = pv.n * (int64_t)B;
   hipLaunchKernelGGL(k_mfma_ab5_combine<T>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit,
-                     pv.n, pv.npad, B, dt, wt, s03, s4, u, hist, fr, static_cast<T*>(ghi), static_cast<T*>(glo));
+                     pv.n, pv.npad, B, dt, wt, s03, s4, u, hist, fr, qd, pv.qmax, static_cast<T*>(ghi),
+                     static_cast<T*>(glo));
 }
 
 inline void launch_mfma_ab5(const ProblemView& pv, int form, int B, double dt, const Ab5Weights& wt, int4 s03, int s4,
                             double* u, double* hist, const double* part, int nsplit, const Firing& fr, float* g,
                             hipStream_t s) {
   if (mfma_is_bf16(form))
-    launch_mfma_ab5_t<__bf16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, g, s);
+    launch_mfma_ab5_t<__bf16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, mfma_source_q(pv, form), g, s);
   else
-    launch_mfma_ab5_t<_Float16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, g, s);
+    launch_mfma_ab5_t<_Float16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, mfma_source_q(pv, form), g, s);
 }
 
 inline void launch_mfma_reduce(const ProblemView& pv, int, int B, const double* part, int nsplit, double* y,

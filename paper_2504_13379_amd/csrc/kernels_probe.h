@@ -1,4 +1,5 @@
-// Roofline microbenchmarks: issue rates of FP32 FMA, exp2, sqrt; MFMA rate;
+// Roofline microbenchmarks: issue rates of FP32 FMA (two- and three-operand
+// encodings), exp2, sqrt and an exp2 + FMA mix; MFMA rate;
 // HBM read and copy bandwidth.  Every kernel touches only `out[gid]` (one float
 // per thread) or the caller's [src, src + n) / [dst, dst + n) ranges.
 #pragma once
@@ -27,6 +28,55 @@ __global__ __launch_bounds__(kWG) void k_probe_fma(int64_t iters, float* __restr
   float r = 0.0f;
 #pragma unroll
   for (int c = 0; c < kProbeChains; ++c) r += a[c];
+  out[gid] = r;
+}
+
+// As k_probe_fma, but x <- x * m + b: the destination is not the addend, so
+// the three-operand (VOP3) encoding is needed, which the hardware does not
+// dual-issue.
+__global__ __launch_bounds__(kWG) void k_probe_fma_vop3(int64_t iters, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  float a[kProbeChains], b[kProbeChains];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) {
+    a[c] = 1.0f + 1e-7f * (float)(threadIdx.x + c);
+    b[c] = 1e-9f * (float)((threadIdx.x + 3 * c) & 7);
+  }
+  const float m = 1.0f - 1e-6f * (float)(threadIdx.x & 1);
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) a[c] = fmaf(a[c], m, b[c]);
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) r += a[c];
+  out[gid] = r;
+}
+
+// The pair kernels' kind of mix: per chain and iteration one exp2 and three
+// accumulating FMAs (4 lane-operations); x stays in (0, 1].
+__global__ __launch_bounds__(kWG) void k_probe_fma_exp(int64_t iters, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  float a[kProbeChains], z[kProbeChains];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) {
+    a[c] = 0.5f + 1e-3f * (float)((threadIdx.x + c) & 63);
+    z[c] = 0.0f;
+  }
+  const float m = -1.0f + 1e-6f * (float)(threadIdx.x & 1);
+  const float k = 1e-3f;
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) {
+      const float e = __builtin_amdgcn_exp2f(a[c]);
+      a[c] = fmaf(e, m, a[c]);
+      z[c] = fmaf(e, k, z[c]);
+      z[c] = fmaf(a[c], k, z[c]);
+    }
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) r += a[c] + z[c];
   out[gid] = r;
 }
 

@@ -109,7 +109,21 @@ PairParams pair_params(const nfr_kernel& k, const ProblemView& pv) {
   p.Ae = k.A_e;
   p.Ai = k.A_i;
   p.per = (float)(pv.period * (double)p.sig);
+  p.kappa = k.A_e != 0.0 ? (float)(-k.A_i / k.A_e) : 0.0f;
+  p.amp = k.A_e;
   return p;
+}
+
+// The forward pair sums accumulate w / A_e (PairParams); a kernel without an
+// excitatory part is rewritten as its single inhibitory term, -A_i exp(.. s_i ..)
+// in the excitatory slot.
+nfr_kernel norm_kernel(const nfr_kernel& k) {
+  if (k.A_e != 0.0) return k;
+  nfr_kernel n = k;
+  n.A_e = -k.A_i;
+  n.s_e = k.s_i;
+  n.A_i = 0.0;
+  return n;
 }
 
 // pair_params for the kernels that take a sym_pow code: with an integer
@@ -337,8 +351,9 @@ int timing_mark(nfr_context* ctx) {
   return NFR_OK;
 }
 
-int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B, const void* W, const Workspace& w,
+int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k_in, int form, int B, const void* W, const Workspace& w,
                      hipStream_t s) {
+  const nfr_kernel k = norm_kernel(k_in);
   if (use_sym(form, B, pv.npad)) {
     const PairParams pp = pair_params_pow(k, pv);
     const dim3 grid((unsigned)sym_pairs(sym_tiles(pv.npad)));
@@ -365,7 +380,7 @@ int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k, int form, int B
     launch_gemv(pv, static_cast<const float*>(W), B, w.g, w.part, plan_gemv(pv.n, pv.npad, B), s);
   } else if (!mfma_has_w(form)) {
     const PairParams pp = pair_params_pow(k, pv);
-    const MfmaOtfParams op{pp.sig, pp.rho, pp.per, pp.Ae, pp.Ai, pv.qmax};
+    const MfmaOtfParams op{pp.sig, pp.rho, pp.per, pp.kappa, pp.amp, pv.qmax};
 #define NFR_MFMA_OTF_CASE(K) \
   case K: launch_mfma_otf<K>(pv, form, op, B, w.g, w.part, s); break;
     switch (kind_code(k, pv) | (sym_pow_code(k) << 2)) {
@@ -541,7 +556,7 @@ int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms) {
 
 int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t buf_bytes, double* rate) {
   if (!ctx || !buf_dev || !rate) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
-  if (which < NFR_PROBE_FMA || which > NFR_PROBE_MFMA_BF16) return fail(NFR_ERR_INVALID_ARG, "unknown probe %d", which);
+  if (which < NFR_PROBE_FMA || which > NFR_PROBE_FMA_EXP) return fail(NFR_ERR_INVALID_ARG, "unknown probe %d", which);
   if (size < 1) return fail(NFR_ERR_INVALID_ARG, "size must be >= 1");
   const int64_t grid = (int64_t)ctx->cu_count * 8;
   const size_t out_bytes = size_t(grid) * kWG * sizeof(float);
@@ -564,6 +579,8 @@ int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t b
     case NFR_PROBE_SQRT: hipLaunchKernelGGL(k_probe_sqrt, g, b, 0, s, size, f); break;
     case NFR_PROBE_HBM_READ: hipLaunchKernelGGL(k_probe_read, g, b, 0, s, f, size, f + size); break;
     case NFR_PROBE_HBM_COPY: hipLaunchKernelGGL(k_probe_copy, g, b, 0, s, f, f + size, size); break;
+    case NFR_PROBE_FMA_VOP3: hipLaunchKernelGGL(k_probe_fma_vop3, g, b, 0, s, size, f); break;
+    case NFR_PROBE_FMA_EXP: hipLaunchKernelGGL(k_probe_fma_exp, g, b, 0, s, size, f); break;
     default: hipLaunchKernelGGL(k_probe_mfma, g, b, 0, s, size, f); break;
   }
   hipError_t le = hipGetLastError();
@@ -579,7 +596,9 @@ int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t b
   switch (which) {
     case NFR_PROBE_FMA:
     case NFR_PROBE_EXP:
-    case NFR_PROBE_SQRT: *rate = lanes * kProbeChains * double(size) / sec; break;
+    case NFR_PROBE_SQRT:
+    case NFR_PROBE_FMA_VOP3: *rate = lanes * kProbeChains * double(size) / sec; break;
+    case NFR_PROBE_FMA_EXP: *rate = lanes * kProbeChains * 4.0 * double(size) / sec; break;
     case NFR_PROBE_HBM_READ: *rate = double(size) * 4 / sec; break;
     case NFR_PROBE_HBM_COPY: *rate = double(size) * 8 / sec; break;
     default: *rate = double(grid) * (kWG / 64) * 4 * double(size) * (32.0 * 32 * 16 * 2) / sec; break;
@@ -1095,10 +1114,11 @@ void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_
     d.npad = pv.npad;
     d.B = Bp;
     d.bs = batch_bs(Bp);
-    d.kind = kind_code(b->kernels[p], pv);
+    const nfr_kernel kn = norm_kernel(b->kernels[p]);
+    d.kind = kind_code(kn, pv);
     d.chunk = b->chunk;
     d.nsplit = (int)ceil_div(pv.npad, b->chunk);
-    d.pp = pair_params(b->kernels[p], pv);
+    d.pp = pair_params(kn, pv);
     d.fr = firing_of(b->firings[p]);
     d.g = reinterpret_cast<float*>(ws + L.g_off[p]);
     d.part = reinterpret_cast<double*>(ws + L.part_off[p]);
@@ -1788,7 +1808,7 @@ int nfr_tune(nfr_context* ctx, const char* cache_path, int64_t n_max, int B_max,
       ~ProbGuard() { nfr_problem_destroy(p); }
     } guard{prob};
     const ProblemView& pv = prob->view;
-    const PairParams pp = pair_params(kern, pv);
+    const PairParams pp = pair_params(norm_kernel(kern), pv);
     for (int B : kTuneB) {
       if (B > B_max) break;
       NFR_HIP(hipMemsetAsync(g, 0, size_t(pv.npad) * B * sizeof(float), s));
