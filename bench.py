@@ -251,8 +251,8 @@ def ensemble_leg(P, torch, args):
             kname = "k_otf_pair_sum<%d,1,16>" % w.kernel_kind
             slots = float(prob.npad) ** 2 * (-(-64 // 16) * eval_slots(w.kernel_kind, 0) + 64)
             entry["roofline"] = {"bound": "alu", "achieved": slots / avg / 1e12, "peak": VALU_LANES_PER_S / 1e12,
-                                 "unit": "Tslot/s", "frac": slots / avg / VALU_LANES_PER_S, "traffic": None,
-                                 "kernel": kname}
+                                 "unit": "Tslot/s", "frac": slots / avg / VALU_LANES_PER_S,
+                                 "traffic": measured_traffic(kname), "kernel": kname}
         elif form in (P.FORM_ONTHEFLY_BF16X3, P.FORM_ONTHEFLY_FP16X3):
             # every W entry evaluated once per launch (64 states share it) on the vector
             # units; the matrix cores do 3 products x 2 flops x 64 states per entry
@@ -263,7 +263,8 @@ def ensemble_leg(P, torch, args):
             fp16 = nm == "otf_fp16x3"
             achieved = wvals * fused_slots_per_w(w.kernel_kind, m, fp16) / avg
             entry["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANES_PER_S / 1e12,
-                                 "unit": "Tslot/s", "frac": achieved / VALU_LANES_PER_S, "traffic": None, "kernel": kname,
+                                 "unit": "Tslot/s", "frac": achieved / VALU_LANES_PER_S,
+                                 "traffic": measured_traffic(kname), "kernel": kname,
                                  "slots_per_w": fused_slots_per_w(w.kernel_kind, m, fp16),
                                  "mfma_tflops": wvals * 384.0 / avg / 1e12,
                                  "mfma_frac": wvals * 384.0 / avg / MFMA_BF16_PEAK}
