@@ -120,7 +120,7 @@ __device__ __forceinline__ float pair_u(float t, float rho, float kappa) {
 // of kWG sources in FP32 (the normalised kernel u, see PairParams), then folds
 // the tile sum into FP64 accumulators: amp * sum.
 // Targets per thread for a block of BS states (TPT x BS accumulators per thread).
-__host__ __device__ constexpr int otf_tpt(int bs) { return bs <= 4 ? 4 : (bs == 8 ? 2 : 1); }
+__host__ __device__ constexpr int otf_tpt(int bs) { return bs <= 4 ? 4 : 2; }
 
 template <int KIND, int TPT, int BS>
 __device__ inline void otf_tile(const float4* __restrict__ src, const float* __restrict__ g, int64_t npad, int B,

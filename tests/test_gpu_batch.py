@@ -103,3 +103,25 @@ def test_batch_full_size_uneven_workload_beta_zero(gctx):
         expect = b[None, :] + R * (u0[:, rows] - b[None, :])
         got = u.cpu().numpy()[:, rows]
         assert np.max(np.abs(got - expect)) <= 1e-5 * np.max(np.abs(expect)), (surf.kind, surf.n)
+
+
+def test_batch_amplitude_edge_cases(gctx):
+    """Problems whose kernels have no excitatory part, a negative one, or vanish entirely
+    (the pair sums accumulate w / A_e, such kernels are rewritten first)."""
+    rng = np.random.default_rng(9)
+    specs = []
+    for kind, n, B, kern in (("sphere", 700, 4, (0.0, 0.15, 0.5, 0.4)), ("torus", 900, 1, (-1.0, 0.15, 0.5, 0.4)),
+                             ("ellipsoid", 600, 16, (0.0, 0.15, 0.0, 0.4)), ("sphere", 500, 3, (1.0, 0.15, 0.5, 0.4))):
+        surf = S.make_surface(kind, n, rng)
+        q = C.area_share_weights(surf) * rng.uniform(0.9, 1.1, size=n)
+        theta = rng.uniform(0.15, 0.3, size=B)
+        u0 = np.stack([C.bump(surf.xyz, surf.xyz[rng.integers(n)]) for _ in range(B)])
+        specs.append((surf, q, 0, kern, 20.0, theta, u0))
+    dt, steps = 0.05, 8
+    batch, states, _ = _make(gctx, specs)
+    batch.integrate(states, dt, steps, use_graph=True)
+    torch.cuda.synchronize()
+    for (surf, q, kk, kern, beta, theta, u0), u in zip(specs, states):
+        ref = NF.rk4(NF.DenseOperator(surf.xyz, q, kk, kern), u0, beta, theta, dt, steps)
+        err = NF.rel_linf(u.cpu().numpy(), ref)
+        assert np.all(err <= 1e-5), (surf.kind, kern, err)

@@ -47,7 +47,7 @@ def _run_apply(ctx, x, q, U, kind, p, beta, theta, form):
     th = torch.from_numpy(np.asarray(theta, dtype=np.float64)).cuda() if np.ndim(theta) else float(theta)
     f = P.Firing(beta, th)
     u = torch.from_numpy(np.ascontiguousarray(U)).cuda()
-    W = prob.w_build(k, form) if form != P.FORM_ONTHEFLY_FP32 else None
+    W = prob.w_build(k, form) if form in (P.FORM_W_FP32, P.FORM_W_BF16X3, P.FORM_W_FP16X3) else None
     y = prob.apply(k, f, u, form=form, W=W)
     torch.cuda.synchronize()
     return y.cpu().numpy()
@@ -244,3 +244,33 @@ def test_apply_large_n_both_sides_of_the_slot_budget(ctx, n):
     ref = NF.apply_K(x, q, U, NF.EXP_MH, EXPK, 20.0, 0.2, rows=rows)
     scale = _abs_scale(x, q, U, NF.EXP_MH, EXPK, 20.0, 0.2, rows)
     assert np.max(np.abs(y[:, rows] - ref) / scale) <= 1e-5
+
+
+# The forward pair sums accumulate w / A_e (u = e1 - (A_i / A_e) e2); a kernel
+# without an excitatory part is rewritten as its single inhibitory term.
+# Amplitude edge cases for every form, with one negative weight; tolerances
+# as above (split forms: those derived in test_gpu_mfma_otf / test_gpu_mfma).
+AMP_CASES = [(0.0, 0.5), (-1.0, 0.5), (1e-6, 0.5), (0.7, 0.0), (0.0, 0.0)]
+FORM_TOL = {(0, 1): 1e-5, (0, 5): 1e-5, (1, 5): 2e-6, (2, 40): 3e-5, (3, 40): 2e-6, (4, 40): 4e-5, (5, 40): 1.2e-5}
+
+
+@pytest.mark.parametrize("form,B", list(FORM_TOL))
+@pytest.mark.parametrize("Ae,Ai", AMP_CASES)
+@pytest.mark.parametrize("kind", [NF.GAUSS_MH, NF.EXP_MH])
+def test_apply_amplitude_edge_cases(ctx, form, B, Ae, Ai, kind):
+    n = 1100
+    rng = np.random.default_rng(17 + B + 3 * form + kind)
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    q[rng.integers(n)] *= -0.2
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.1, 0.3, size=B) if B > 1 else 0.2
+    p = (Ae, 0.15, Ai, 0.45) if kind == NF.GAUSS_MH else (Ae, 0.1, Ai, 0.3)   # the exponential one: ratio 1/3
+    y = _run_apply(ctx, x, q, U, kind, p, 20.0, theta, form)
+    ref = NF.apply_K(x, q, U, kind, p, 20.0, theta)
+    if Ae == 0.0 and Ai == 0.0:
+        assert np.all(y == 0.0)
+        return
+    scale = _abs_scale(x, q, U, kind, p, 20.0, theta, None)
+    err = np.max(np.abs(y - ref) / scale)
+    assert err <= FORM_TOL[(form, B)], err
