@@ -114,6 +114,7 @@ def parse():
     ap.add_argument("--forms", default="otf,w32")
     ap.add_argument("--no-graph", action="store_true", help="launch every kernel instead of replaying graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the N = 2000 sphere time-per-step leg")
     ap.add_argument("--probes", action="store_true", help="also run the roofline microbenchmarks")
     ap.add_argument("--probes-only", action="store_true",
                     help="run only the roofline microbenchmarks and print their rates as one JSON line")
@@ -277,6 +278,42 @@ def ensemble_leg(P, torch, args):
     for nm in ("bf16x3", "fp16x3", "otf_bf16x3", "otf_fp16x3"):
         out[nm]["max_rel_linf_vs_otf_fp32"] = float(np.max(np.max(np.abs(finals[nm] - ref), axis=1) /
                                                             np.max(np.abs(ref), axis=1)))
+    return out
+
+
+def small_leg(P, torch, args):
+    """Unit sphere N = 2000, B = 1, Gaussian Mexican hat, 50 RK4 steps: at this size the step is
+    launch-bound, so the figure of merit is time per RK4 step (graph replay vs launching every
+    kernel); the two runs must agree bit for bit (parity with the oracle is the tests' job)."""
+    import numpy as np
+
+    from workloads import configs as C
+    w = C.sphere_small(2000)
+    q = C.area_share_weights(w.surface)
+    ctx = P.Context(0, torch.cuda.Stream())
+    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
+    k = P.kernel_struct(w.kernel_kind, *w.kernel)
+    f = P.Firing(w.beta, float(w.theta[0]))
+    ws = prob.integrate_workspace(1, P.FORM_ONTHEFLY_FP32)
+    out = {"workload": "unit sphere, Fibonacci N=2000, Gauss Mexican hat, B=1, RK4 dt=0.05 x %d steps" % w.steps}
+    finals = {}
+    for graph in (True, False):
+        u = torch.from_numpy(w.u0.copy()).cuda()
+        prob.integrate(k, f, u, w.dt, w.steps, form=P.FORM_ONTHEFLY_FP32, ws=ws, use_graph=graph)   # warm-up
+        times = []
+        for _ in range(5):
+            u.copy_(torch.from_numpy(w.u0))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prob.integrate(k, f, u, w.dt, w.steps, form=P.FORM_ONTHEFLY_FP32, ws=ws, use_graph=graph)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        t = sorted(times)[len(times) // 2]
+        nm = "graph" if graph else "launched"
+        out[nm] = {"us_per_rk4_step": t / w.steps * 1e6,
+                   "value": 4.0 * w.steps * float(w.n) ** 2 / t, "unit": "pair-interactions/s"}
+        finals[nm] = u.cpu().numpy()
+    out["graph_equals_launched"] = bool(np.array_equal(finals["graph"], finals["launched"]))
     return out
 
 
@@ -560,6 +597,9 @@ def main():
         cb, err = cpu_baseline(w, q, y.cpu().numpy()[:, rows], rows)
         line["cpu_baseline"] = cb
         line["rel_err_vs_fp64_sampled_apply"] = err
+    if not args.no_small:
+        print("bench: small sphere", file=sys.stderr, flush=True)
+        line["small"] = small_leg(P, torch, args)
     if args.ens_rk4_steps > 0:
         line["ensemble"] = ensemble_leg(P, torch, args)
     if args.batch_rk4_steps > 0:
