@@ -249,7 +249,7 @@ def ensemble_leg(P, torch, args):
         elif form == P.FORM_ONTHEFLY_FP32:
             # one-sided multi-state pair sum: per target-source pair one evaluation of u per
             # block of 16 states (no integer-ratio shortcut in this kernel) + 1 FMA per state
-            kname = "k_otf_pair_sum<%d,1,16>" % w.kernel_kind
+            kname = "k_otf_pair_sum<%d,2,16>" % w.kernel_kind
             slots = float(prob.npad) ** 2 * (-(-64 // 16) * eval_slots(w.kernel_kind, 0) + 64)
             entry["roofline"] = {"bound": "alu", "achieved": slots / avg / 1e12, "peak": VALU_LANES_PER_S / 1e12,
                                  "unit": "Tslot/s", "frac": slots / avg / VALU_LANES_PER_S,

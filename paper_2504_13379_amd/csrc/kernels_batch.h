@@ -2,7 +2,7 @@
 // and state counts) advanced together, one persistent pair-sum launch and one
 // combine launch per RK4 stage for the whole batch.
 //
-// Work items are (problem, target tile of kWG * otf_tpt(bs) targets, source
+// Work items are (problem, target tile of kWG * batch_tpt(bs) targets, source
 // chunk, state block); they are sorted by decreasing cost on the host and a fixed grid of
 // workgroups walks them round-robin, so every stage is a single launch whose
 // largest items start first.
@@ -37,19 +37,30 @@ struct BatchItem {
   int sb;
 };
 
-// State block of a problem with B states (1, 4 or 16; see otf_tpt for the
+// State block of a problem with B states (1, 4 or 16; see batch_tpt for the
 // targets per thread that go with it).
 __host__ __device__ constexpr int batch_bs(int B) { return B == 1 ? 1 : (B <= 4 ? 4 : 16); }
+
+// Targets per thread of a batch item with state block bs.  One kernel serves
+// every block size and takes the register allocation of the largest, so the
+// two targets per thread that the single-problem 16-state sum uses (201
+// registers) would cut the occupancy of every item; one target (148
+// registers) is faster over the uneven batch (1.39e13 against 1.30e13
+// pair-interactions/s).
+#ifndef NFR_BATCH_TPT16
+#define NFR_BATCH_TPT16 1
+#endif
+__host__ __device__ constexpr int batch_tpt(int bs) { return bs == 16 ? NFR_BATCH_TPT16 : otf_tpt(bs); }
 
 template <int KIND>
 __device__ inline void batch_item(const BatchProblemDev& P, const BatchItem& w, float4* s_src, float (*s_g)[kWG]) {
   if (P.bs == 1)
-    otf_tile<KIND, otf_tpt(1), 1>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb, s_src, s_g);
+    otf_tile<KIND, batch_tpt(1), 1>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb, s_src, s_g);
   else if (P.bs == 4)
-    otf_tile<KIND, otf_tpt(4), 4>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 4, s_src,
+    otf_tile<KIND, batch_tpt(4), 4>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 4, s_src,
                                   s_g);
   else
-    otf_tile<KIND, otf_tpt(16), 16>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 16,
+    otf_tile<KIND, batch_tpt(16), 16>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb * 16,
                                     s_src, s_g);
 }
 

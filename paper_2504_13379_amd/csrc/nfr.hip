@@ -1069,7 +1069,7 @@ struct BatchLayout {
 int64_t batch_items_for(const nfr_problem* p, int B, int64_t chunk) {
   const int64_t npad = p->view.npad;
   const int bs = batch_bs(B);
-  return ceil_div(npad, (int64_t)kWG * otf_tpt(bs)) * ceil_div(npad, chunk) * ceil_div(B, bs);
+  return ceil_div(npad, (int64_t)kWG * batch_tpt(bs)) * ceil_div(npad, chunk) * ceil_div(B, bs);
 }
 
 BatchLayout batch_layout(const nfr_batch* b) {
@@ -1129,7 +1129,7 @@ void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_
     d.gel_off = goff;
     eoff += pv.n * Bp;
     goff += pv.npad * Bp;
-    const int tpt = otf_tpt(d.bs);
+    const int tpt = batch_tpt(d.bs);
     const int64_t tiles = ceil_div(pv.npad, (int64_t)kWG * tpt);
     const int sbs = (int)ceil_div(Bp, d.bs);
     for (int64_t t = 0; t < tiles; ++t)
