@@ -237,6 +237,11 @@ constexpr int kSymSplit = NFR_SYM_SPLIT;
 constexpr int kSymTPT = NFR_SYM_TPT;
 constexpr int kSymThreads = 64 * kSymSplit;
 constexpr int kSymTile = 64 * kSymTPT;   // 256 nodes by default
+// Shape for small problems: one wave per tile pair and one target per lane
+// (tiles of 64), so that a few thousand nodes still give hundreds of tile
+// pairs; the large shape's 4-target tiles leave most of the chip idle there.
+constexpr int kSymSmallTPT = 1;
+constexpr int kSymSmallSplit = 1;
 
 __device__ inline float wave_ror1(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, false));
@@ -252,10 +257,11 @@ __device__ inline void sym_decode(int64_t p, int64_t* I, int64_t* J) {
   *I = p - j * (j + 1) / 2;
 }
 
-template <int KIND, bool COLS>
+template <int KIND, bool COLS, int TPT, int SPLIT>
 __device__ inline void sym_tile(const float4* __restrict__ src, const float* __restrict__ g, int64_t npad,
                                 const PairParams& pp, double* __restrict__ part, int64_t I, int64_t J,
-                                double (*rowsum)[kSymTile]) {
+                                double (*rowsum)[64 * TPT]) {
+  constexpr int kSymTPT = TPT, kSymSplit = SPLIT, kSymTile = 64 * TPT, kSymThreads = 64 * SPLIT;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const float rho = pp.rho;
@@ -327,17 +333,17 @@ __device__ inline void sym_tile(const float4* __restrict__ src, const float* __r
   }
 }
 
-// part[s * npad + i]: slot s of node i (see above); nt = ceil(npad / kSymTile).
-template <int KIND>
-__global__ __launch_bounds__(kSymThreads) void k_otf_sym(const float4* __restrict__ src, const float* __restrict__ g,
-                                                         int64_t npad, PairParams pp, double* __restrict__ part) {
-  __shared__ double rowsum[kSymSplit][kSymTile];
+// part[s * npad + i]: slot s of node i (see above); nt = ceil(npad / (64 TPT)).
+template <int KIND, int TPT, int SPLIT>
+__global__ __launch_bounds__(64 * SPLIT) void k_otf_sym(const float4* __restrict__ src, const float* __restrict__ g,
+                                                        int64_t npad, PairParams pp, double* __restrict__ part) {
+  __shared__ double rowsum[SPLIT][64 * TPT];
   int64_t I, J;
   sym_decode(blockIdx.x, &I, &J);
   if (I == J)
-    sym_tile<KIND, false>(src, g, npad, pp, part, I, J, rowsum);
+    sym_tile<KIND, false, TPT, SPLIT>(src, g, npad, pp, part, I, J, rowsum);
   else
-    sym_tile<KIND, true>(src, g, npad, pp, part, I, J, rowsum);
+    sym_tile<KIND, true, TPT, SPLIT>(src, g, npad, pp, part, I, J, rowsum);
 }
 
 // ------------------------------------------------------------------ reductions

@@ -249,7 +249,28 @@ int resolve_form(int form, int64_t n, int B) {
   return NFR_FORM_ONTHEFLY_FP32;
 }
 
-int64_t sym_tiles(int64_t npad) { return ceil_div(npad, kSymTile); }
+// The forward symmetric kernel uses tiles of 64 nodes up to kSymSmallMaxNpad
+// padded nodes (see kSymSmallTPT), of kSymTile above; the adjoint's transpose
+// kernel always uses kSymTile.  Measured (sphere, B = 1, pair kernel per
+// launch, large / small shape): N = 2000 12.7 / 7.9 us, 4096 12.7 / 11.8,
+// 6144 19.1 / 16.6, 8192 25.8 / 25.3, 16384 65.0 / 71.6.
+#ifndef NFR_SYM_SMALL_MAX
+#define NFR_SYM_SMALL_MAX 6144
+#endif
+constexpr int64_t kSymSmallMaxNpad = NFR_SYM_SMALL_MAX;
+bool sym_small(int64_t npad) { return npad <= kSymSmallMaxNpad; }
+int64_t sym_tiles(int64_t npad) { return ceil_div(npad, sym_small(npad) ? 64 * kSymSmallTPT : kSymTile); }
+int64_t adj_tiles(int64_t npad) { return ceil_div(npad, kSymTile); }
+
+template <int K>
+void launch_sym(const ProblemView& pv, const PairParams& pp, const float* g, double* part, hipStream_t s) {
+  const dim3 grid((unsigned)sym_pairs(sym_tiles(pv.npad)));
+  if (sym_small(pv.npad))
+    hipLaunchKernelGGL((k_otf_sym<K, kSymSmallTPT, kSymSmallSplit>), grid, dim3(64 * kSymSmallSplit), 0, s, pv.src, g,
+                       pv.npad, pp, part);
+  else
+    hipLaunchKernelGGL((k_otf_sym<K, kSymTPT, kSymSplit>), grid, dim3(kSymThreads), 0, s, pv.src, g, pv.npad, pp, part);
+}
 
 // B = 1 on the fly uses the symmetric kernel: one FP64 slot per tile and node,
 // npad^2 / kSymTile * 8 bytes, which grows quadratically; beyond 8 GiB of
@@ -356,9 +377,8 @@ int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k_in, int form, in
   const nfr_kernel k = norm_kernel(k_in);
   if (use_sym(form, B, pv.npad)) {
     const PairParams pp = pair_params_pow(k, pv);
-    const dim3 grid((unsigned)sym_pairs(sym_tiles(pv.npad)));
 #define NFR_SYM_CASE(K) \
-  case K: hipLaunchKernelGGL(k_otf_sym<K>, grid, dim3(kSymThreads), 0, s, pv.src, w.g, pv.npad, pp, w.part); break;
+  case K: launch_sym<K>(pv, pp, w.g, w.part, s); break;
     switch (kind_code(k, pv) | (sym_pow_code(k) << 2)) {
       NFR_SYM_CASE(0) NFR_SYM_CASE(1) NFR_SYM_CASE(2) NFR_SYM_CASE(3)
       NFR_SYM_CASE(4) NFR_SYM_CASE(5) NFR_SYM_CASE(6) NFR_SYM_CASE(7)
@@ -852,7 +872,7 @@ AdjWorkspace carve_adjoint(void* base, const ProblemView& pv, int64_t ckpt_every
     off += align256(bytes);
     return r;
   };
-  const int nsplit = (int)sym_tiles(pv.npad);
+  const int nsplit = (int)adj_tiles(pv.npad);
   const int64_t nblocks = adj_blocks(pv.n, nsplit);
   a.store = reinterpret_cast<double*>(take(size_t(ckpt_every) * 4 * pv.n * sizeof(double)));
   a.useg = reinterpret_cast<double*>(take(size_t(pv.n) * sizeof(double)));
@@ -910,7 +930,7 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
   const Firing fr = firing_of(*firing);
   const PairParams pp = pair_params(*kernel, pv);
   const AdjCoef co = adj_coef(*kernel);
-  const int nt = (int)sym_tiles(pv.npad);
+  const int nt = (int)adj_tiles(pv.npad);
   const int adj_code = kind_code(*kernel, pv) | (sym_pow_code(*kernel) << 2);
   const int64_t n = pv.n;
   const int64_t nblocks = adj_blocks(n, nt);
