@@ -189,3 +189,20 @@ def test_fused_form_needs_no_w(ctx):
     k = P.kernel_struct(0, *GAUSS)
     for form in (4, 5):   # rejected before the (NULL) buffer is looked at
         assert P.lib().nfr_w_build(prob.handle, ctypes.byref(k), form, None, 0) == -1
+
+
+@pytest.mark.parametrize("form", [4, 5])
+def test_fused_large_n_sampled_rows(ctx, form):
+    """N = 262144, B = 64 (the split-W form would need 275 GB of W here): one application,
+    24 sampled rows against the oracle."""
+    n, B = 262144, 64
+    rng = np.random.default_rng(21 + form)
+    x = S.fibonacci_sphere(n) * 1.05
+    q = np.full(n, 4 * math.pi * 1.05 ** 2 / n) * rng.uniform(0.9, 1.1, size=n)
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.15, 0.3, size=B)
+    y = _apply(ctx, x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, form)
+    rows = rng.choice(n, 24, replace=False)
+    ref = NF.apply_K(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, rows=rows)
+    err = np.max(np.abs(y[:, rows] - ref) / _scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, rows))
+    assert err <= TOL_APPLY[form], err
