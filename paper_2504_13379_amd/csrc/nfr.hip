@@ -488,12 +488,6 @@ int check_w(const nfr_problem* p, int form, const void* w_dev) {
   return NFR_OK;
 }
 
-int check_mfma_b(int form, int B) {
-  (void)form;
-  (void)B;
-  return NFR_OK;
-}
-
 }  // namespace
 
 // ================================================================ C ABI
@@ -733,7 +727,7 @@ int nfr_apply(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* fir
   if (!u_dev || !y_dev) return fail(NFR_ERR_INVALID_ARG, "NULL state pointer");
   const ProblemView& pv = prob->view;
   form = resolve_form(form, pv.n, B);
-  if ((st = check_w(prob, form, w_dev)) || (st = check_mfma_b(form, B))) return st;
+  if ((st = check_w(prob, form, w_dev))) return st;
   const Workspace w = carve(ws_dev, pv, B, form, false);
   if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
   NFR_HIP(hipSetDevice(prob->ctx->device));
@@ -771,7 +765,7 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
   if (ckpt_dev && ckpt_every < 1) return fail(NFR_ERR_INVALID_ARG, "ckpt_every must be >= 1");
   const ProblemView& pv = prob->view;
   form = resolve_form(form, pv.n, B);
-  if ((st = check_w(prob, form, w_dev)) || (st = check_mfma_b(form, B))) return st;
+  if ((st = check_w(prob, form, w_dev))) return st;
   const Workspace w = carve(ws_dev, pv, B, form, true);
   if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
   if (use_graph && prob->ctx->stream == nullptr)
