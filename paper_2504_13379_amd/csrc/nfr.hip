@@ -10,7 +10,6 @@
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -1585,25 +1584,37 @@ bool quad_sizes_ok(int64_t n, int64_t ntri, int k) {
 // Neighbour across every edge e (vertex e -> vertex e+1) of every triangle: the
 // triangle holding the reverse directed edge.  Fails unless every directed
 // edge occurs once and its reverse once (a closed, consistently oriented surface).
-int quad_neighbours(const int32_t* tri, int64_t ntri, std::vector<int>& nbr) {
-  std::unordered_map<uint64_t, int64_t> owner;
-  owner.reserve(size_t(3 * ntri) * 2);
-  auto key = [](uint32_t a, uint32_t b) { return (uint64_t(a) << 32) | b; };
-  for (int64_t t = 0; t < ntri; ++t)
-    for (int e = 0; e < 3; ++e) {
-      const uint32_t a = (uint32_t)tri[3 * t + e], b = (uint32_t)tri[3 * t + (e + 1) % 3];
-      if (!owner.emplace(key(a, b), 3 * t + e).second)
-        return fail(NFR_ERR_INVALID_ARG, "directed edge (%u, %u) occurs twice: the triangulation is not consistently oriented", a, b);
-    }
-  nbr.assign(size_t(3 * ntri), -1);
-  for (int64_t t = 0; t < ntri; ++t)
-    for (int e = 0; e < 3; ++e) {
-      const uint32_t a = (uint32_t)tri[3 * t + e], b = (uint32_t)tri[3 * t + (e + 1) % 3];
-      auto it = owner.find(key(b, a));
-      if (it == owner.end())
-        return fail(NFR_ERR_INVALID_ARG, "edge (%u, %u) has no reverse: the triangulation is not closed", a, b);
-      nbr[size_t(3 * t + e)] = (int)(it->second / 3);
-    }
+// Triangle across each edge: the triangle that holds the reversed directed
+// edge.  Directed edges are grouped by their first vertex (a counting sort),
+// so the reverse of (a, b) is looked for among the few edges that start at b;
+// a repeated directed edge or a missing reverse is reported.
+int quad_neighbours(const int32_t* tri, int64_t ntri, int64_t n, std::vector<int>& nbr) {
+  const int64_t ne = 3 * ntri;
+  std::vector<int64_t> start(size_t(n) + 1, 0);
+  for (int64_t e = 0; e < ne; ++e) ++start[size_t(tri[e]) + 1];
+  for (int64_t v = 0; v < n; ++v) start[size_t(v) + 1] += start[size_t(v)];
+  std::vector<int64_t> fill(start.begin(), start.end() - 1);
+  std::vector<int64_t> by_first(static_cast<size_t>(ne));
+  for (int64_t e = 0; e < ne; ++e) by_first[size_t(fill[size_t(tri[e])]++)] = e;
+  auto head = [&](int64_t e) { return tri[e]; };
+  auto tail = [&](int64_t e) { return tri[3 * (e / 3) + (e % 3 + 1) % 3]; };
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t p = start[size_t(v)]; p < start[size_t(v) + 1]; ++p)
+      for (int64_t r = p + 1; r < start[size_t(v) + 1]; ++r)
+        if (tail(by_first[size_t(p)]) == tail(by_first[size_t(r)]))
+          return fail(NFR_ERR_INVALID_ARG, "directed edge (%d, %d) occurs twice: the triangulation is not consistently oriented",
+                      (int)v, tail(by_first[size_t(p)]));
+  nbr.assign(size_t(ne), -1);
+  for (int64_t e = 0; e < ne; ++e) {
+    const int32_t a = head(e), b = tail(e);
+    for (int64_t p = start[size_t(b)]; p < start[size_t(b) + 1]; ++p)
+      if (tail(by_first[size_t(p)]) == a) {
+        nbr[size_t(e)] = (int)(by_first[size_t(p)] / 3);
+        break;
+      }
+    if (nbr[size_t(e)] < 0)
+      return fail(NFR_ERR_INVALID_ARG, "edge (%d, %d) has no reverse: the triangulation is not closed", (int)a, (int)b);
+  }
   return NFR_OK;
 }
 
@@ -1633,7 +1644,7 @@ int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const d
   }
   std::vector<int> nbr;
   int st;
-  if (!star_shaped && (st = quad_neighbours(tri_host, ntri, nbr))) return st;
+  if (!star_shaped && (st = quad_neighbours(tri_host, ntri, n, nbr))) return st;
   if (!ctx) return fail(NFR_ERR_INVALID_ARG, "context is NULL");
   const QuadWorkspace w = carve_quad(ws_dev, n, ntri, k);
   if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
