@@ -111,7 +111,11 @@ def test_periodic_apply_large_sampled_rows(ctx):
     assert np.max(np.abs(y[:, rows] - ref) / sc) <= 1e-5
 
 
-@pytest.mark.parametrize("form", [0, 1, 3])
+# fused on-the-fly split forms (4 BF16, 5 FP16): 1e-4 / 2e-5 as derived in test_gpu_mfma_otf
+FORCED_TOL = {0: 1e-5, 1: 1e-5, 3: 1e-5, 4: 1e-4, 5: 2e-5}
+
+
+@pytest.mark.parametrize("form", [0, 1, 3, 4, 5])
 def test_forced_mms_flat_periodic(ctx, form):
     m = mms.FlatMMS(4000)
     q = Q.plane_weights(m.surface.xyz)
@@ -121,15 +125,16 @@ def test_forced_mms_flat_periodic(ctx, form):
                         m.beta, m.theta, dt, steps, lambda k, c: F[k, {0.0: 0, 0.5: 1, 1.0: 2}[c]])
     prob = P.Problem(ctx, torch.from_numpy(m.surface.xyz).cuda(), torch.from_numpy(q).cuda(), period=L)
     k = P.kernel_struct(m.kind, *m.kernel)
-    W = prob.w_build(k, form) if form else None
+    W = prob.w_build(k, form) if form in (1, 2, 3) else None
     u = torch.from_numpy(m.u(0.0)[None, :].copy()).cuda()
     prob.integrate_forced(k, P.Firing(m.beta, m.theta), u, dt, steps, torch.from_numpy(F).cuda(), form=form, W=W)
     torch.cuda.synchronize()
     got = u.cpu().numpy()
-    assert np.all(NF.rel_linf(got, ref) <= 1e-5)
+    tol = FORCED_TOL[form]
+    assert np.all(NF.rel_linf(got, ref) <= tol)
     exact = m.u(dt * steps)
     oracle_err = np.max(np.abs(ref[0] - exact)) / np.max(np.abs(exact))
-    assert np.max(np.abs(got[0] - exact)) / np.max(np.abs(exact)) <= oracle_err + 1e-5
+    assert np.max(np.abs(got[0] - exact)) / np.max(np.abs(exact)) <= oracle_err + tol
 
 
 def test_periodic_adjoint_matches_oracle(ctx):

@@ -21,7 +21,13 @@ def ctx():
     return P.Context(0)
 
 
-@pytest.mark.parametrize("form", [0, 1, 3])
+# u(T) against the oracle's forced RK4: 1e-5 (FP32, FP16x3), fused on-the-fly
+# split forms 1e-4 (BF16) / 2e-5 (FP16) as derived in test_gpu_mfma_otf; the
+# exact solution to the quadrature's accuracy (1e-5) or that tolerance if larger.
+FORCED_TOL = {0: 1e-5, 1: 1e-5, 3: 1e-5, 4: 1e-4, 5: 2e-5}
+
+
+@pytest.mark.parametrize("form", [0, 1, 3, 4, 5])
 def test_forced_mms_sphere(ctx, form):
     m = mms.SphereMMS(4000)
     q = Q.surface_weights(m.surface)
@@ -31,11 +37,12 @@ def test_forced_mms_sphere(ctx, form):
                         dt, steps, lambda k, c: F[k, {0.0: 0, 0.5: 1, 1.0: 2}[c]])
     prob = P.Problem(ctx, torch.from_numpy(m.surface.xyz).cuda(), torch.from_numpy(q).cuda())
     k = P.kernel_struct(m.kind, *m.kernel)
-    W = prob.w_build(k, form) if form else None
+    W = prob.w_build(k, form) if form in (1, 2, 3) else None
     u = torch.from_numpy(m.u(0.0)[None, :].copy()).cuda()
     prob.integrate_forced(k, P.Firing(m.beta, m.theta), u, dt, steps, torch.from_numpy(F).cuda(), form=form, W=W)
     torch.cuda.synchronize()
     got = u.cpu().numpy()
-    assert np.all(NF.rel_linf(got, ref) <= 1e-5)
+    tol = FORCED_TOL[form]
+    assert np.all(NF.rel_linf(got, ref) <= tol)
     exact = m.u(dt * steps)
-    assert np.max(np.abs(got[0] - exact)) <= 1e-5 * np.max(np.abs(exact))
+    assert np.max(np.abs(got[0] - exact)) <= max(1e-5, tol) * np.max(np.abs(exact))
