@@ -55,6 +55,18 @@ def test_size_queries(L):
         assert L.nfr_w_bytes(1000, form) == 0
 
 
+def test_problem_layout_and_tune_workspace(L):
+    """Packed problem: float4 coordinates | FP64 weights | FP64 coordinates |
+    one FP64 max |q| slot, each 256-byte aligned, N padded to 256."""
+    a = lambda b: (b + 255) // 256 * 256
+    for n in (1, 255, 256, 1000, 65536):
+        npad = (n + 255) // 256 * 256
+        assert L.nfr_problem_bytes(n) == a(npad * 16) + a(npad * 8) + a(3 * npad * 8) + a(8)
+    assert L.nfr_tune_workspace_size(512, 64) == 0        # n_max below 1024
+    assert L.nfr_tune_workspace_size(65536, 1) == 0       # B_max below 2
+    assert L.nfr_tune_workspace_size(65536, 64) > L.nfr_tune_workspace_size(65536, 16) > 0
+
+
 def test_null_arguments_rejected_before_device_work(L):
     from paper_2504_13379_amd import _lib
     k = _lib.NfrKernel(0, 1.0, 0.15, 0.5, 0.4)
