@@ -34,6 +34,7 @@ HBM_PEAK = 8.0e12            # bytes/s, MI355X HBM3E
 VALU_LANES_PER_S = 256 * 128 * 2.4e9
 TRANS_COST = 4.0
 MFMA_BF16_PEAK = 2.5e15      # dense BF16 / FP16 matrix-core flop/s
+MFMA_F32_PEAK = 157.3e12     # dense FP32 matrix-core flop/s
 # Algorithmic lane-operation slots per unordered pair {i, j} of the B = 1
 # on-the-fly kernel (the kernel is radial, so one evaluation serves y_i and y_j):
 #   evaluation: 3 sub + 1 mul + 2 fma (r^2) + 1 mul (rho t) = 7 full-rate, plus
@@ -213,7 +214,8 @@ def ensemble_leg(P, torch, args):
                        % args.ens_rk4_steps}
     finals = {}
     for nm, form in (("bf16x3", P.FORM_W_BF16X3), ("fp16x3", P.FORM_W_FP16X3), ("otf_bf16x3", P.FORM_ONTHEFLY_BF16X3),
-                     ("otf_fp16x3", P.FORM_ONTHEFLY_FP16X3), ("otf_fp32", P.FORM_ONTHEFLY_FP32)):
+                     ("otf_fp16x3", P.FORM_ONTHEFLY_FP16X3), ("otf_fp32_mfma", P.FORM_ONTHEFLY_FP32_MFMA),
+                     ("otf_fp32", P.FORM_ONTHEFLY_FP32)):
         print("bench: ensemble form %s" % nm, file=sys.stderr, flush=True)
         W = None
         t_build = 0.0
@@ -246,6 +248,16 @@ def ensemble_leg(P, torch, args):
             entry["roofline"] = {"bound": "hbm", "achieved": wbytes / avg / 1e9, "peak": HBM_PEAK / 1e9,
                                  "unit": "GB/s", "frac": wbytes / avg / HBM_PEAK,
                                  "traffic": measured_traffic(kname), "kernel": kname}
+        elif form == P.FORM_ONTHEFLY_FP32_MFMA:
+            # products on the FP32 matrix cores: 2 flop per pair-interaction (64 states, each
+            # kernel value once per launch on the vector units)
+            m = sym_pow(w.kernel_kind, w.kernel[1], w.kernel[3])
+            kname = "k_mfma_otf_f32<%d,2>" % (w.kernel_kind + 4 * (m - 1 if m else 0))
+            flops = 2.0 * float(prob.npad) ** 2 * 64
+            entry["roofline"] = {"bound": "mfma", "achieved": flops / avg / 1e12, "peak": MFMA_F32_PEAK / 1e12,
+                                 "unit": "TFLOP/s", "frac": flops / avg / MFMA_F32_PEAK,
+                                 "traffic": measured_traffic(kname), "kernel": kname,
+                                 "alu_frac": float(prob.npad) ** 2 * eval_slots(w.kernel_kind, m) / avg / VALU_LANES_PER_S}
         elif form == P.FORM_ONTHEFLY_FP32:
             # one-sided multi-state pair sum: per target-source pair one evaluation of u per
             # block of 16 states (no integer-ratio shortcut in this kernel) + 1 FMA per state
@@ -275,7 +287,7 @@ def ensemble_leg(P, torch, args):
         torch.cuda.empty_cache()
     import numpy as np
     ref = finals["otf_fp32"]
-    for nm in ("bf16x3", "fp16x3", "otf_bf16x3", "otf_fp16x3"):
+    for nm in ("bf16x3", "fp16x3", "otf_bf16x3", "otf_fp16x3", "otf_fp32_mfma"):
         out[nm]["max_rel_linf_vs_otf_fp32"] = float(np.max(np.max(np.abs(finals[nm] - ref), axis=1) /
                                                             np.max(np.abs(ref), axis=1)))
     return out
@@ -508,7 +520,7 @@ def probes(P, torch, ctx):
     small = torch.empty(grid_threads * 4 + 256, dtype=torch.uint8, device="cuda")
     for name, which, size in (("fma_lane_ops", 0, 20000), ("fma_vop3_lane_ops", 6, 20000), ("exp_lane_ops", 1, 5000),
                               ("sqrt_lane_ops", 2, 5000), ("fma_exp_mix_lane_ops", 7, 5000),
-                              ("mfma_bf16_flops", 5, 20000)):
+                              ("mfma_bf16_flops", 5, 20000), ("mfma_f32_flops", 8, 20000)):
         r = ctypes.c_double()
         P._lib.check(L.nfr_probe(ctx.handle, which, size, small.data_ptr(), small.numel(), ctypes.byref(r)))
         out[name] = r.value

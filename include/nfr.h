@@ -91,6 +91,11 @@ typedef struct {
  *                  and split in registers: no W matrix (w_dev is ignored)
  *                  and no N^2 memory; each kernel value serves 32 or 64
  *                  states at once.
+ *   ONTHEFLY_FP32_MFMA: the ONTHEFLY_FP32 arithmetic (FP32 kernel values,
+ *                  products and 256-source sums, FP64 beyond) with the
+ *                  products on the FP32 matrix cores: for blocks of states
+ *                  (32 or 64 at a time), the vector units only evaluate the
+ *                  kernel.  No W matrix.
  *   AUTO:          the library picks the form (at present always
  *                  ONTHEFLY_FP32, which needs no W matrix). */
 enum nfr_form {
@@ -100,7 +105,8 @@ enum nfr_form {
   NFR_FORM_W_BF16X3 = 2,
   NFR_FORM_W_FP16X3 = 3,
   NFR_FORM_ONTHEFLY_BF16X3 = 4,
-  NFR_FORM_ONTHEFLY_FP16X3 = 5
+  NFR_FORM_ONTHEFLY_FP16X3 = 5,
+  NFR_FORM_ONTHEFLY_FP32_MFMA = 6
 };
 
 typedef struct nfr_context nfr_context;
@@ -142,7 +148,8 @@ int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms);
  *   MFMA_BF16:      FLOP per second of 32x32x16 BF16 MFMA, `size` iterations;
  *   FMA_VOP3:       as FMA with the three-operand encoding (x <- x*m + b);
  *   FMA_EXP:        lane-operations per second of a mix of one exp2 and three
- *                   accumulating FMAs per chain and iteration. 
+ *                   accumulating FMAs per chain and iteration;
+ *   MFMA_F32:       FLOP per second of 32x32x2 FP32 MFMA, `size` iterations. 
  * buf_dev must hold 4*size bytes plus one float per thread of a grid of
  * 8 workgroups per compute unit (HBM_READ), 8*size bytes (HBM_COPY), or one
  * float per thread (others). */
@@ -154,7 +161,8 @@ enum nfr_probe_kind {
   NFR_PROBE_HBM_COPY = 4,
   NFR_PROBE_MFMA_BF16 = 5,
   NFR_PROBE_FMA_VOP3 = 6,
-  NFR_PROBE_FMA_EXP = 7
+  NFR_PROBE_FMA_EXP = 7,
+  NFR_PROBE_MFMA_F32 = 8
 };
 int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t buf_bytes, double* rate);
 

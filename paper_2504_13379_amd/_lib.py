@@ -31,6 +31,7 @@ FORM_W_BF16X3 = 2
 FORM_W_FP16X3 = 3
 FORM_ONTHEFLY_BF16X3 = 4
 FORM_ONTHEFLY_FP16X3 = 5
+FORM_ONTHEFLY_FP32_MFMA = 6
 
 
 class NfrKernel(ctypes.Structure):

@@ -534,6 +534,153 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
   }
 }
 
+// On-the-fly FP32 form with the products on the FP32 matrix cores
+// (32x32x2 FP32 MFMA): the same arithmetic class as the vector-unit sum
+// (FP32 kernel values, FP32 products and sums over 256 sources folded into
+// FP64), for blocks of 32 NB states.  The sources are g = q f(u) in FP32, as
+// for the vector-unit form, so its source preparation and RK4 combination
+// are shared.
+//
+// MFMA step ks of a pipeline step covers sources ks and 32 + ks: lane
+// l = m + 32 h evaluates u(row m, source 32 h + ks) (A operand, one value)
+// and holds g(source 32 h + ks, state m) (B operand); outputs as in the split
+// kernels (rows 8 (r / 4) + 4 h + r % 4, state m).  The vector units only
+// evaluate the kernel (one value per lane per MFMA step), so the matrix
+// cores bound the kernel.  Coordinates and g of a pipeline step are staged
+// through double-buffered LDS tiles; states beyond B read state B - 1 (their
+// outputs are never written).
+constexpr int kF32FoldSteps = 4;     // pipeline steps (of 64 sources) per FP64 fold
+
+template <int KIND, int NB>
+__global__ __launch_bounds__(kWG, 2) void k_mfma_otf_f32(const float4* __restrict__ src, const float* __restrict__ g,
+                                                         int64_t npad, int B, int64_t kchunk, PairParams pp,
+                                                         double* __restrict__ part) {
+  constexpr int NS = 32 * NB;
+  constexpr int STRIDE = kMfmaStep + 4;          // floats per LDS row of sG
+  constexpr int ROWCH = kMfmaStep / 4;           // 16-byte chunks per row
+  constexpr int CHUNKS = NS * ROWCH / kWG;       // chunks per thread per step
+  typedef __attribute__((ext_vector_type(4))) float f4_t;
+  __shared__ __attribute__((aligned(16))) float sG[2][NS][STRIDE];
+  __shared__ __attribute__((aligned(16))) float sS[2][3][kMfmaStep];
+
+  const int64_t wg = blockIdx.x;
+  const int split = (int)(wg % kMfmaSplits);
+  const int64_t rb = wg / kMfmaSplits;
+  const int sg = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m = lane & 31;
+  const int h = lane >> 5;
+  const int64_t row0 = rb * kMfmaRowsPerWG + wave * 32;
+  const int64_t k_begin = (int64_t)split * kchunk;
+  int64_t k_end = k_begin + kchunk;
+  if (k_end > npad) k_end = npad;
+  const int nsteps = (int)((k_end - k_begin) / kMfmaStep);
+
+  const float4 pr = src[row0 + m];
+  const float xi = pr.x * pp.sig, yi = pr.y * pp.sig, zi = pr.z * pp.sig;
+
+  const float* gsrc[CHUNKS];
+  int g_row[CHUNKS], g_col[CHUNKS];
+#pragma unroll
+  for (int q = 0; q < CHUNKS; ++q) {
+    const int cc = tid + kWG * q;
+    g_row[q] = cc / ROWCH;
+    g_col[q] = 4 * (cc % ROWCH);
+    int b = sg * NS + g_row[q];
+    if (b > B - 1) b = B - 1;
+    gsrc[q] = g + (int64_t)b * npad + k_begin + g_col[q];
+  }
+
+  f32x16_t acc[NB];
+  double facc[NB][16];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      acc[nb][r] = 0.0f;
+      facc[nb][r] = 0.0;
+    }
+
+  f4_t gn[CHUNKS];
+  float4 sn;
+  auto load_next = [&](int t) {
+    const int64_t tc = t < nsteps ? t : nsteps - 1;
+#pragma unroll
+    for (int q = 0; q < CHUNKS; ++q) gn[q] = *reinterpret_cast<const f4_t*>(gsrc[q] + tc * kMfmaStep);
+    sn = src[k_begin + tc * kMfmaStep + lane];
+  };
+  auto store_next = [&](int t) {
+    const int buf = t & 1;
+#pragma unroll
+    for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<f4_t*>(&sG[buf][g_row[q]][g_col[q]]) = gn[q];
+    if (wave == 0) {
+      sS[buf][0][lane] = sn.x * pp.sig;
+      sS[buf][1][lane] = sn.y * pp.sig;
+      sS[buf][2][lane] = sn.z * pp.sig;
+    }
+  };
+  auto compute = [&](int t) {
+    const int buf = t & 1;
+#pragma unroll
+    for (int k4 = 0; k4 < kMfmaStep / 8; ++k4) {
+      const int c0 = 32 * h + 4 * k4;
+      const f4_t cx = *reinterpret_cast<const f4_t*>(&sS[buf][0][c0]);
+      const f4_t cy = *reinterpret_cast<const f4_t*>(&sS[buf][1][c0]);
+      const f4_t cz = *reinterpret_cast<const f4_t*>(&sS[buf][2][c0]);
+      f4_t gv[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) gv[nb] = *reinterpret_cast<const f4_t*>(&sG[buf][nb * 32 + m][c0]);
+      float u[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float r2 = pair_r2<KIND>(xi - cx[e], yi - cy[e], zi - cz[e], pp.per);
+        const float tt = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+        u[e] = pair_u<KIND>(tt, pp.rho, pp.kappa);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(u[e], gv[nb][e], acc[nb], 0, 0, 0);
+    }
+  };
+  auto fold = [&]() {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        facc[nb][r] += (double)acc[nb][r];
+        acc[nb][r] = 0.0f;
+      }
+  };
+  if (nsteps > 0) {
+    load_next(0);
+    store_next(0);
+    __syncthreads();
+    for (int t = 0; t < nsteps; ++t) {
+      load_next(t + 1);
+      compute(t);
+      if ((t + 1) % kF32FoldSteps == 0) fold();
+      store_next(t + 1);
+      __syncthreads();
+    }
+    fold();
+  }
+
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int b = sg * NS + nb * 32 + m;
+    if (b >= B) continue;
+    double* dst = part + ((int64_t)split * B + b) * npad;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t i = row0 + 8 * (r / 4) + 4 * h + (r % 4);
+      dst[i] = pp.amp * facc[nb][r];
+    }
+  }
+}
+
 // RK4 stage combination for the split forms: as k_rk4_combine, but the next
 // stage's sources are written as Ghi/Glo (no q: it sits inside W).
 template <typename T>
@@ -713,6 +860,21 @@ inline void launch_mfma_otf(const ProblemView& pv, int form, const MfmaOtfParams
     launch_mfma_otf_t<__bf16, KIND>(pv, op, B, g, part, s);
   else
     launch_mfma_otf_t<_Float16, KIND>(pv, op, B, g, part, s);
+}
+
+// On-the-fly FP32 form on the FP32 matrix cores for template code KIND; g is
+// the FP32 source array of the on-the-fly forms (npad x B, q included).
+template <int KIND>
+inline void launch_mfma_otf_f32(const ProblemView& pv, const PairParams& pp, int B, const float* g, double* part,
+                                hipStream_t s) {
+  const int64_t kchunk = round_up(ceil_div(pv.npad, kMfmaSplits), kMfmaStep);
+  const unsigned grid_x = (unsigned)(pv.npad / kMfmaRowsPerWG * kMfmaSplits);
+  if (B <= 32)
+    hipLaunchKernelGGL((k_mfma_otf_f32<KIND, 1>), dim3(grid_x, 1), dim3(kWG), 0, s, pv.src, g, pv.npad, B, kchunk, pp,
+                       part);
+  else
+    hipLaunchKernelGGL((k_mfma_otf_f32<KIND, 2>), dim3(grid_x, (unsigned)ceil_div(B, 64)), dim3(kWG), 0, s, pv.src, g,
+                       pv.npad, B, kchunk, pp, part);
 }
 
 template <typename T>

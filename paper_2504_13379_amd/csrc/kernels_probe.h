@@ -1,5 +1,5 @@
 // Roofline microbenchmarks: issue rates of FP32 FMA (two- and three-operand
-// encodings), exp2, sqrt and an exp2 + FMA mix; MFMA rate;
+// encodings), exp2, sqrt and an exp2 + FMA mix; BF16 and FP32 MFMA rates;
 // HBM read and copy bandwidth.  Every kernel touches only `out[gid]` (one float
 // per thread) or the caller's [src, src + n) / [dst, dst + n) ranges.
 #pragma once
@@ -153,6 +153,23 @@ __global__ __launch_bounds__(kWG) void k_probe_mfma(int64_t iters, float* __rest
     c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c1, 0, 0, 0);
     c2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c2, 0, 0, 0);
     c3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c3, 0, 0, 0);
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) r += c0[e] + c1[e] + c2[e] + c3[e];
+  out[gid] = r;
+}
+
+// Four independent 32x32x2 FP32 MFMA accumulation chains per wave.
+__global__ __launch_bounds__(kWG) void k_probe_mfma_f32(int64_t iters, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  const float a = 1e-3f * (float)(threadIdx.x & 7), b = 1e-3f * (float)((threadIdx.x * 3) & 7);
+  probe_f32x16 c0 = {}, c1 = {}, c2 = {}, c3 = {};
+  for (int64_t it = 0; it < iters; ++it) {
+    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c1, 0, 0, 0);
+    c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c2, 0, 0, 0);
+    c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c3, 0, 0, 0);
   }
   float r = 0.0f;
 #pragma unroll

@@ -91,7 +91,7 @@ int check_firing(const nfr_firing* f) {
 }
 
 int check_form(int form) {
-  if (form < NFR_FORM_AUTO || form > NFR_FORM_ONTHEFLY_FP16X3) return fail(NFR_ERR_INVALID_ARG, "unknown form %d", form);
+  if (form < NFR_FORM_AUTO || form > NFR_FORM_ONTHEFLY_FP32_MFMA) return fail(NFR_ERR_INVALID_ARG, "unknown form %d", form);
   if (is_mfma_form(form) && !kMfmaAvailable) return fail(NFR_ERR_INVALID_ARG, "form %d is not available in this build", form);
   return NFR_OK;
 }
@@ -280,6 +280,10 @@ bool use_sym(int form, int B, int64_t npad) {
   return form == NFR_FORM_ONTHEFLY_FP32 && B == 1 && (double)sym_tiles(npad) * (double)npad * 8.0 <= kSymMaxSlotBytes;
 }
 
+// Forms whose FP32 source array g holds q f(u) (the on-the-fly FP32 forms);
+// the W forms hold f(u) (q sits in W).
+bool sources_carry_q(int form) { return form == NFR_FORM_ONTHEFLY_FP32 || form == NFR_FORM_ONTHEFLY_FP32_MFMA; }
+
 int nsplit_for(const ProblemView& pv, int B, int form) {
   if (use_sym(form, B, pv.npad)) return (int)sym_tiles(pv.npad);
   if (form == NFR_FORM_ONTHEFLY_FP32) return plan_otf(pv.npad, B).nsplit;
@@ -350,7 +354,7 @@ int launch_prep(const ProblemView& pv, int form, int B, const double* u, const F
   if (is_mfma_form(form)) {
     launch_mfma_prep(pv, form, B, u, fr, w.g, v_copy, s);
   } else {
-    const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
+    const int with_q = sources_carry_q(form) ? 1 : 0;
     const int64_t total = pv.npad * (int64_t)B;
     hipLaunchKernelGGL(k_source_prep, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, u, pv.n, pv.npad, B,
                        pv.q, with_q, fr, w.g, v_copy);
@@ -397,6 +401,18 @@ int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k_in, int form, in
     }
   } else if (form == NFR_FORM_W_FP32) {
     launch_gemv(pv, static_cast<const float*>(W), B, w.g, w.part, plan_gemv(pv.n, pv.npad, B), s);
+  } else if (form == NFR_FORM_ONTHEFLY_FP32_MFMA) {
+    const PairParams pp = pair_params_pow(k, pv);
+#define NFR_F32M_CASE(K) \
+  case K: launch_mfma_otf_f32<K>(pv, pp, B, w.g, w.part, s); break;
+    switch (kind_code(k, pv) | (sym_pow_code(k) << 2)) {
+      NFR_F32M_CASE(0) NFR_F32M_CASE(1) NFR_F32M_CASE(2) NFR_F32M_CASE(3)
+      NFR_F32M_CASE(4) NFR_F32M_CASE(5) NFR_F32M_CASE(6) NFR_F32M_CASE(7)
+      NFR_F32M_CASE(8) NFR_F32M_CASE(9) NFR_F32M_CASE(10) NFR_F32M_CASE(11)
+      NFR_F32M_CASE(12) NFR_F32M_CASE(13) NFR_F32M_CASE(14) NFR_F32M_CASE(15)
+      default: return fail(NFR_ERR_INTERNAL, "no FP32 matrix-core kernel for this kernel code");
+    }
+#undef NFR_F32M_CASE
   } else if (!mfma_has_w(form)) {
     const PairParams pp = pair_params_pow(k, pv);
     const MfmaOtfParams op{pp.sig, pp.rho, pp.per, pp.kappa, pp.amp, pv.qmax};
@@ -447,7 +463,7 @@ int launch_combine(const ProblemView& pv, int form, int B, int stage, double dt,
   if (is_mfma_form(form)) {
     launch_mfma_combine(pv, form, B, stage, dt, u, w.v, w.ksum, w.part, nsplit, fr, w.g, k1_out, gamma, s);
   } else {
-    const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
+    const int with_q = sources_carry_q(form) ? 1 : 0;
     NFR_LAUNCH_SLOTS(k_rk4_combine, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, stage, dt, u, w.v, w.ksum,
                      pv.q, with_q, fr, w.g, k1_out, gamma);
   }
@@ -467,7 +483,7 @@ int launch_ab5(const ProblemView& pv, int form, int B, int64_t n_step, double dt
   if (is_mfma_form(form)) {
     launch_mfma_ab5(pv, form, B, dt, wt, s03, s4, u, hist, w.part, nsplit, fr, w.g, s);
   } else {
-    const int with_q = form == NFR_FORM_ONTHEFLY_FP32 ? 1 : 0;
+    const int with_q = sources_carry_q(form) ? 1 : 0;
     NFR_LAUNCH_SLOTS(k_ab5_combine, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, dt, wt, s03, s4, u, hist,
                      pv.q, with_q, fr, w.g);
   }
@@ -481,7 +497,8 @@ int check_problem(const nfr_problem* p) {
 }
 
 int check_w(const nfr_problem* p, int form, const void* w_dev) {
-  if (form == NFR_FORM_ONTHEFLY_FP32 || (is_mfma_form(form) && !mfma_has_w(form))) return NFR_OK;
+  if (form == NFR_FORM_ONTHEFLY_FP32 || form == NFR_FORM_ONTHEFLY_FP32_MFMA || (is_mfma_form(form) && !mfma_has_w(form)))
+    return NFR_OK;
   if (!w_dev) return fail(NFR_ERR_INVALID_ARG, "form %d needs a W matrix (w_dev is NULL)", form);
   (void)p;
   return NFR_OK;
@@ -569,7 +586,7 @@ int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms) {
 
 int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t buf_bytes, double* rate) {
   if (!ctx || !buf_dev || !rate) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
-  if (which < NFR_PROBE_FMA || which > NFR_PROBE_FMA_EXP) return fail(NFR_ERR_INVALID_ARG, "unknown probe %d", which);
+  if (which < NFR_PROBE_FMA || which > NFR_PROBE_MFMA_F32) return fail(NFR_ERR_INVALID_ARG, "unknown probe %d", which);
   if (size < 1) return fail(NFR_ERR_INVALID_ARG, "size must be >= 1");
   const int64_t grid = (int64_t)ctx->cu_count * 8;
   const size_t out_bytes = size_t(grid) * kWG * sizeof(float);
@@ -594,6 +611,7 @@ int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t b
     case NFR_PROBE_HBM_COPY: hipLaunchKernelGGL(k_probe_copy, g, b, 0, s, f, f + size, size); break;
     case NFR_PROBE_FMA_VOP3: hipLaunchKernelGGL(k_probe_fma_vop3, g, b, 0, s, size, f); break;
     case NFR_PROBE_FMA_EXP: hipLaunchKernelGGL(k_probe_fma_exp, g, b, 0, s, size, f); break;
+    case NFR_PROBE_MFMA_F32: hipLaunchKernelGGL(k_probe_mfma_f32, g, b, 0, s, size, f); break;
     default: hipLaunchKernelGGL(k_probe_mfma, g, b, 0, s, size, f); break;
   }
   hipError_t le = hipGetLastError();
@@ -614,6 +632,7 @@ int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t b
     case NFR_PROBE_FMA_EXP: *rate = lanes * kProbeChains * 4.0 * double(size) / sec; break;
     case NFR_PROBE_HBM_READ: *rate = double(size) * 4 / sec; break;
     case NFR_PROBE_HBM_COPY: *rate = double(size) * 8 / sec; break;
+    case NFR_PROBE_MFMA_F32: *rate = double(grid) * (kWG / 64) * 4 * double(size) * (32.0 * 32 * 2 * 2) / sec; break;
     default: *rate = double(grid) * (kWG / 64) * 4 * double(size) * (32.0 * 32 * 16 * 2) / sec; break;
   }
   return NFR_OK;
