@@ -520,10 +520,14 @@ def probes(P, torch, ctx):
     small = torch.empty(grid_threads * 4 + 256, dtype=torch.uint8, device="cuda")
     for name, which, size in (("fma_lane_ops", 0, 20000), ("fma_vop3_lane_ops", 6, 20000), ("exp_lane_ops", 1, 5000),
                               ("sqrt_lane_ops", 2, 5000), ("fma_exp_mix_lane_ops", 7, 5000),
-                              ("mfma_bf16_flops", 5, 20000), ("mfma_f32_flops", 8, 20000)):
-        r = ctypes.c_double()
-        P._lib.check(L.nfr_probe(ctx.handle, which, size, small.data_ptr(), small.numel(), ctypes.byref(r)))
-        out[name] = r.value
+                              ("mfma_bf16_flops", 5, 20000), ("mfma_f32_flops", 8, 20000),
+                              ("mfma_f32_beside_fma_flops", 9, 20000), ("mfma_bf16_beside_fma_flops", 10, 20000)):
+        best = 0.0
+        for _ in range(2):                          # the first launch may run before the clock has ramped
+            r = ctypes.c_double()
+            P._lib.check(L.nfr_probe(ctx.handle, which, size, small.data_ptr(), small.numel(), ctypes.byref(r)))
+            best = max(best, r.value)
+        out[name] = best
     nfl = 1 << 30                                   # 4 GiB read, 2 x 2 GiB copy
     big = torch.empty(nfl * 4 + grid_threads * 4 + 256, dtype=torch.uint8, device="cuda")
     for name, which, size in (("hbm_read_Bps", 3, nfl), ("hbm_copy_Bps", 4, nfl // 2)):

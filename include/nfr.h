@@ -149,7 +149,12 @@ int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms);
  *   FMA_VOP3:       as FMA with the three-operand encoding (x <- x*m + b);
  *   FMA_EXP:        lane-operations per second of a mix of one exp2 and three
  *                   accumulating FMAs per chain and iteration;
- *   MFMA_F32:       FLOP per second of 32x32x2 FP32 MFMA, `size` iterations. 
+ *   MFMA_F32:       FLOP per second of 32x32x2 FP32 MFMA, `size` iterations;
+ *   MFMA_F32_FMA:   MFMA FLOP per second of two 32x32x2 FP32 MFMA chains run
+ *                   beside eight FMA chains (32 FMAs per iteration, no data
+ *                   shared): equal to MFMA_F32 if the vector units run while
+ *                   the matrix cores do, half of it if the two alternate;
+ *   MFMA_BF16_FMA:  the same with four 32x32x16 BF16 MFMAs per iteration.
  * buf_dev must hold 4*size bytes plus one float per thread of a grid of
  * 8 workgroups per compute unit (HBM_READ), 8*size bytes (HBM_COPY), or one
  * float per thread (others). */
@@ -162,7 +167,9 @@ enum nfr_probe_kind {
   NFR_PROBE_MFMA_BF16 = 5,
   NFR_PROBE_FMA_VOP3 = 6,
   NFR_PROBE_FMA_EXP = 7,
-  NFR_PROBE_MFMA_F32 = 8
+  NFR_PROBE_MFMA_F32 = 8,
+  NFR_PROBE_MFMA_F32_FMA = 9,
+  NFR_PROBE_MFMA_BF16_FMA = 10
 };
 int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t buf_bytes, double* rate);
 

@@ -387,7 +387,10 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
   constexpr int ROWCH = kMfmaStep / 8;
   constexpr int CHUNKS = NS * 2 * ROWCH / kWG;
   __shared__ __attribute__((aligned(16))) T sG[2][2][NS][kMfmaLdsStride];
-  __shared__ __attribute__((aligned(16))) float sS[2][3][kMfmaStep];
+  // column coordinates x, y, z (row 3: the packed zero component); wave w
+  // loads and stores row w, so no load sits behind a branch
+  __shared__ __attribute__((aligned(16))) float sS[2][4][kMfmaStep];
+  static_assert(kWG == 4 * 64, "one wave per coordinate row");
 
   const int64_t wg = blockIdx.x;
   const int split = (int)(wg % kMfmaSplits);
@@ -428,25 +431,21 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
 #pragma unroll
     for (int r = 0; r < 16; ++r) accM[nb][r] = accC[nb][r] = 0.0f;
 
-  // Every wave loads the column coordinates of a step (lane = column); wave 0
-  // stores them.  Loads past the last step re-read the last step.
+  // Wave w loads component w of the column coordinates of a step (lane =
+  // column).  Loads past the last step re-read the last step.
   u32x4_t gn[CHUNKS];
-  float4 sn;
+  float sn;
   auto load_next = [&](int t) {
     const int64_t tc = t < nsteps ? t : nsteps - 1;
 #pragma unroll
     for (int q = 0; q < CHUNKS; ++q) gn[q] = *reinterpret_cast<const u32x4_t*>(gsrc[q] + tc * kMfmaStep);
-    sn = src[k_begin + tc * kMfmaStep + lane];
+    sn = reinterpret_cast<const float*>(src + k_begin + tc * kMfmaStep + lane)[wave];
   };
   auto store_next = [&](int t) {
     const int buf = t & 1;
 #pragma unroll
     for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[buf][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
-    if (wave == 0) {
-      sS[buf][0][lane] = sn.x * op.sig;
-      sS[buf][1][lane] = sn.y * op.sig;
-      sS[buf][2][lane] = sn.z * op.sig;
-    }
+    sS[buf][wave][lane] = sn * op.sig;
   };
   auto eval = [&](int buf, int kb, V& whi, V& wlo) {
     const int col = 16 * kb + 8 * h;
@@ -512,6 +511,9 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     __syncthreads();
     for (int t = 0; t < nsteps; ++t) {
       load_next(t + 1);
+      // keep the prefetch at the top: left to itself the scheduler sinks it
+      // to just before its LDS store, exposing its latency every step
+      __builtin_amdgcn_sched_barrier(0);
       compute(t);
       store_next(t + 1);
       __syncthreads();
@@ -561,7 +563,10 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf_f32(const float4* __restric
   constexpr int CHUNKS = NS * ROWCH / kWG;       // chunks per thread per step
   typedef __attribute__((ext_vector_type(4))) float f4_t;
   __shared__ __attribute__((aligned(16))) float sG[2][NS][STRIDE];
-  __shared__ __attribute__((aligned(16))) float sS[2][3][kMfmaStep];
+  // column coordinates x, y, z (row 3: the packed zero component); wave w
+  // loads and stores row w, so no load sits behind a branch
+  __shared__ __attribute__((aligned(16))) float sS[2][4][kMfmaStep];
+  static_assert(kWG == 4 * 64, "one wave per coordinate row");
 
   const int64_t wg = blockIdx.x;
   const int split = (int)(wg % kMfmaSplits);
@@ -604,22 +609,18 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf_f32(const float4* __restric
     }
 
   f4_t gn[CHUNKS];
-  float4 sn;
+  float sn;
   auto load_next = [&](int t) {
     const int64_t tc = t < nsteps ? t : nsteps - 1;
 #pragma unroll
     for (int q = 0; q < CHUNKS; ++q) gn[q] = *reinterpret_cast<const f4_t*>(gsrc[q] + tc * kMfmaStep);
-    sn = src[k_begin + tc * kMfmaStep + lane];
+    sn = reinterpret_cast<const float*>(src + k_begin + tc * kMfmaStep + lane)[wave];
   };
   auto store_next = [&](int t) {
     const int buf = t & 1;
 #pragma unroll
     for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<f4_t*>(&sG[buf][g_row[q]][g_col[q]]) = gn[q];
-    if (wave == 0) {
-      sS[buf][0][lane] = sn.x * pp.sig;
-      sS[buf][1][lane] = sn.y * pp.sig;
-      sS[buf][2][lane] = sn.z * pp.sig;
-    }
+    sS[buf][wave][lane] = sn * pp.sig;
   };
   auto compute = [&](int t) {
     const int buf = t & 1;
@@ -660,6 +661,9 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf_f32(const float4* __restric
     __syncthreads();
     for (int t = 0; t < nsteps; ++t) {
       load_next(t + 1);
+      // keep the prefetch at the top: left to itself the scheduler sinks it
+      // to just before its LDS store, exposing its latency every step
+      __builtin_amdgcn_sched_barrier(0);
       compute(t);
       if ((t + 1) % kF32FoldSteps == 0) fold();
       store_next(t + 1);

@@ -1,6 +1,6 @@
 // Roofline microbenchmarks: issue rates of FP32 FMA (two- and three-operand
-// encodings), exp2, sqrt and an exp2 + FMA mix; BF16 and FP32 MFMA rates;
-// HBM read and copy bandwidth.  Every kernel touches only `out[gid]` (one float
+// encodings), exp2, sqrt and an exp2 + FMA mix; BF16 and FP32 MFMA rates,
+// alone and next to independent FMAs; HBM read and copy bandwidth.  Every kernel touches only `out[gid]` (one float
 // per thread) or the caller's [src, src + n) / [dst, dst + n) ranges.
 #pragma once
 
@@ -174,6 +174,73 @@ __global__ __launch_bounds__(kWG) void k_probe_mfma_f32(int64_t iters, float* __
   float r = 0.0f;
 #pragma unroll
   for (int e = 0; e < 16; ++e) r += c0[e] + c1[e] + c2[e] + c3[e];
+  out[gid] = r;
+}
+
+// Co-issue probes: per iteration two independent MFMA chains (FP32: two
+// 32x32x2, 64 clocks each; BF16: four 32x32x16, 32 clocks each, so 128 clocks
+// of matrix-core work either way) and eight independent FMA chains of four
+// FMAs (32 wave instructions, 128 clocks at one per four clocks), no data
+// shared between the two.  Their rate next to the pure probes shows whether
+// the vector units run while the matrix cores do.
+__global__ __launch_bounds__(kWG) void k_probe_mfma_f32_fma(int64_t iters, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  const float a = 1e-3f * (float)(threadIdx.x & 7), b = 1e-3f * (float)((threadIdx.x * 3) & 7);
+  probe_f32x16 c0 = {}, c1 = {};
+  float x[kProbeChains], y[kProbeChains];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) {
+    x[c] = 1.0f + 1e-7f * (float)(threadIdx.x + c);
+    y[c] = 1e-9f * (float)((threadIdx.x + 3 * c) & 7);
+  }
+  const float m = 1.0f - 1e-6f * (float)(threadIdx.x & 1);
+  for (int64_t it = 0; it < iters; ++it) {
+    c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c1, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < kProbeChains; ++c) x[c] = fmaf(y[c], m, x[c]);
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) r += c0[e] + c1[e];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) r += x[c];
+  out[gid] = r;
+}
+
+__global__ __launch_bounds__(kWG) void k_probe_mfma_bf16_fma(int64_t iters, float* __restrict__ out) {
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  probe_bf16x8 a, b;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    a[e] = (__bf16)(1e-3f * (float)((threadIdx.x + e) & 7));
+    b[e] = (__bf16)(1e-3f * (float)((threadIdx.x * 3 + e) & 7));
+  }
+  probe_f32x16 c0 = {}, c1 = {};
+  float x[kProbeChains], y[kProbeChains];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) {
+    x[c] = 1.0f + 1e-7f * (float)(threadIdx.x + c);
+    y[c] = 1e-9f * (float)((threadIdx.x + 3 * c) & 7);
+  }
+  const float m = 1.0f - 1e-6f * (float)(threadIdx.x & 1);
+  for (int64_t it = 0; it < iters; ++it) {
+    c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c1, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c1, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < kProbeChains; ++c) x[c] = fmaf(y[c], m, x[c]);
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) r += c0[e] + c1[e];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) r += x[c];
   out[gid] = r;
 }
 
