@@ -395,20 +395,30 @@ __global__ __launch_bounds__(kWG) void k_reduce_partials(const double* __restric
 // then g[b*npad + i] = s_i f_b(v) for the next stage (s_i = q_i or 1).
 // k1_out (may be null) receives k_1 = F(u_n) at stage 1 (the Adams-Bashforth start-up records it);
 // gamma (may be null) is a forcing term added to k (B x n, at this stage's time).
-template <int L>
-__global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ part, int nsplit, int64_t n,
-                                                     int64_t npad, int B, int stage, double dt,
-                                                     double* __restrict__ u, double* __restrict__ v,
-                                                     double* __restrict__ ksum, const double* __restrict__ qd,
-                                                     int with_q, Firing fr, float* __restrict__ g,
-                                                     double* __restrict__ k1_out, const double* __restrict__ gamma) {
-  int sub;
-  const int64_t idx = group_index<L>(&sub);
-  if (idx >= n * (int64_t)B) return;
-  const int b = (int)(idx / n);
-  const int64_t i = idx - (int64_t)b * n;
-  const double y = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
-  if (sub != 0) return;
+struct Rk4Stage {
+  int stage;
+  double dt;
+  double* u;
+  double* v;
+  double* ksum;
+  const double* qd;
+  int with_q;
+  Firing fr;
+  double* k1_out;
+  const double* gamma;
+};
+
+// The update of element idx = (b, i) from its pair sum y (see above).
+__device__ inline void rk4_update(const Rk4Stage& st, int64_t idx, int b, int64_t i, int64_t npad, double y,
+                                  float* __restrict__ g) {
+  const int stage = st.stage;
+  const double dt = st.dt;
+  double* __restrict__ u = st.u;
+  double* __restrict__ v = st.v;
+  double* __restrict__ ksum = st.ksum;
+  double* __restrict__ k1_out = st.k1_out;
+  const double* __restrict__ gamma = st.gamma;
+  const Firing& fr = st.fr;
   const double k = -v[idx] + y + (gamma ? gamma[idx] : 0.0);
   double ui = u[idx];
   double vn;
@@ -428,8 +438,96 @@ __global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ 
     vn = ui;
   }
   v[idx] = vn;
-  const double s = with_q ? qd[i] : 1.0;
+  const double s = st.with_q ? st.qd[i] : 1.0;
   g[(int64_t)b * npad + i] = (float)(s * sigmoid(vn, fr.beta, state_theta(fr, b)));
+}
+
+template <int L>
+__global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ part, int nsplit, int64_t n,
+                                                     int64_t npad, int B, Rk4Stage st, float* __restrict__ g) {
+  int sub;
+  const int64_t idx = group_index<L>(&sub);
+  if (idx >= n * (int64_t)B) return;
+  const int b = (int)(idx / n);
+  const int64_t i = idx - (int64_t)b * n;
+  const double y = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
+  if (sub != 0) return;
+  rk4_update(st, idx, b, i, npad, y, g);
+}
+
+// Pair sum of one state for small problems (a few thousand nodes), where the
+// symmetric kernel has too few tile pairs to fill the chip: every target-
+// source pair is evaluated once (twice the symmetric kernel's evaluations),
+// but a workgroup owns only kSmallRows targets, so N = 2000 gives 512
+// workgroups (4 targets each: at N = 1000 / 2000 / 4096 an RK4 step took
+// 18.5 / 25.7 / 43.4 us, against 21.7 / 28.8 / 44.5 with 8 targets, 18.3 /
+// 25.7 / 46.3 with 2 and 29.7 / 39.6 / 58.2 with 16).  Thread t takes
+// sources t, t + kWG, ...; for each target it sums
+// its sources in FP32; the threads' sums are then added in FP64 in a fixed
+// tree (xor butterfly within a wave, then the waves in order), so the result
+// is reproducible.  Without STAGE: part[i] = y_i, one slot per node.  With
+// STAGE the workgroup applies the RK4 stage update of k_rk4_combine to its
+// own targets straight away (one launch per stage, y added as the one-slot
+// combine adds it); the next stage's sources then go to g_next, a second
+// buffer, because other workgroups may still be reading g.
+#ifndef NFR_SMALL_ROWS
+#define NFR_SMALL_ROWS 4
+#endif
+constexpr int kSmallRows = NFR_SMALL_ROWS;
+
+template <int KIND, bool STAGE>
+__global__ __launch_bounds__(kWG) void k_otf_small(const float4* __restrict__ src, const float* __restrict__ g,
+                                                   int64_t n, int64_t npad, PairParams pp, double* __restrict__ part,
+                                                   Rk4Stage st, float* __restrict__ g_next) {
+  __shared__ double red[kWG / 64][kSmallRows];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * kSmallRows;
+  float tx[kSmallRows], ty[kSmallRows], tz[kSmallRows], acc[kSmallRows];
+#pragma unroll
+  for (int r = 0; r < kSmallRows; ++r) {
+    const float4 p = src[r0 + r];
+    tx[r] = p.x * pp.sig;
+    ty[r] = p.y * pp.sig;
+    tz[r] = p.z * pp.sig;
+    acc[r] = 0.0f;
+  }
+  for (int64_t j = threadIdx.x; j < npad; j += kWG) {
+    const float4 s4 = src[j];
+    const float sx = s4.x * pp.sig, sy = s4.y * pp.sig, sz = s4.z * pp.sig, sg = g[j];
+#pragma unroll
+    for (int r = 0; r < kSmallRows; ++r) {
+      const float r2 = pair_r2<KIND>(tx[r] - sx, ty[r] - sy, tz[r] - sz, pp.per);
+      const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+      acc[r] = fmaf(pair_u<KIND>(t, pp.rho, pp.kappa), sg, acc[r]);
+    }
+  }
+  double d[kSmallRows];
+#pragma unroll
+  for (int r = 0; r < kSmallRows; ++r) d[r] = (double)acc[r];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int r = 0; r < kSmallRows; ++r) d[r] += __shfl_xor(d[r], off, 64);
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < kSmallRows; ++r) red[wave][r] = d[r];
+  __syncthreads();
+  if (threadIdx.x < kSmallRows) {
+    double y = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWG / 64; ++w) y += red[w][threadIdx.x];
+    const int64_t i = r0 + threadIdx.x;
+    if (!STAGE) {
+      part[i] = pp.amp * y;
+    } else if (i < n) {
+      double ys = 0.0;            // as slot_sum adds the single slot
+      ys += pp.amp * y;
+      rk4_update(st, i, 0, i, npad, ys, g_next);
+    } else {
+      g_next[i] = 0.0f;           // padding sources stay zero in both buffers
+    }
+  }
 }
 
 // ------------------------------------------------------------------ Adams-Bashforth 5

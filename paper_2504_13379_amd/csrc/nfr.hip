@@ -261,8 +261,26 @@ bool sym_small(int64_t npad) { return npad <= kSymSmallMaxNpad; }
 int64_t sym_tiles(int64_t npad) { return ceil_div(npad, sym_small(npad) ? 64 * kSymSmallTPT : kSymTile); }
 int64_t adj_tiles(int64_t npad) { return ceil_div(npad, kSymTile); }
 
+// Up to this many padded nodes one state's pair sum is the one-sided
+// k_otf_small (kSmallRows targets per workgroup, one slot per node) instead of
+// the symmetric kernel.  RK4 step on the sphere, one-sided (one launch per
+// stage) / symmetric (pair kernel + combine): N = 1000 18.5 / 35.6 us,
+// 2000 25.7 / 37.1, 4096 43.4 / 57.4; with 8 targets per workgroup 6144
+// 73.3 / 74.9 and 8192 113 / 108.
+#ifndef NFR_SMALL_ONESIDED_MAX
+#define NFR_SMALL_ONESIDED_MAX 4096
+#endif
+constexpr int64_t kSmallOneSidedMaxNpad = NFR_SMALL_ONESIDED_MAX;
+bool small_onesided(int64_t npad) { return npad <= kSmallOneSidedMaxNpad; }
+
 template <int K>
 void launch_sym(const ProblemView& pv, const PairParams& pp, const float* g, double* part, hipStream_t s) {
+  static_assert(kPad % kSmallRows == 0, "whole target blocks");
+  if (small_onesided(pv.npad)) {
+    hipLaunchKernelGGL((k_otf_small<K, false>), dim3((unsigned)(pv.npad / kSmallRows)), dim3(kWG), 0, s, pv.src, g,
+                       pv.n, pv.npad, pp, part, Rk4Stage{}, nullptr);
+    return;
+  }
   const dim3 grid((unsigned)sym_pairs(sym_tiles(pv.npad)));
   if (sym_small(pv.npad))
     hipLaunchKernelGGL((k_otf_sym<K, kSymSmallTPT, kSymSmallSplit>), grid, dim3(64 * kSymSmallSplit), 0, s, pv.src, g,
@@ -285,7 +303,7 @@ bool use_sym(int form, int B, int64_t npad) {
 bool sources_carry_q(int form) { return form == NFR_FORM_ONTHEFLY_FP32 || form == NFR_FORM_ONTHEFLY_FP32_MFMA; }
 
 int nsplit_for(const ProblemView& pv, int B, int form) {
-  if (use_sym(form, B, pv.npad)) return (int)sym_tiles(pv.npad);
+  if (use_sym(form, B, pv.npad)) return small_onesided(pv.npad) ? 1 : (int)sym_tiles(pv.npad);
   if (form == NFR_FORM_ONTHEFLY_FP32) return plan_otf(pv.npad, B).nsplit;
   if (form == NFR_FORM_W_FP32) return plan_gemv(pv.n, pv.npad, B).nsplit;
   return mfma_nsplit(pv.n, pv.npad, B);
@@ -293,11 +311,20 @@ int nsplit_for(const ProblemView& pv, int B, int form) {
 
 struct Workspace {
   float* g = nullptr;
+  float* g2 = nullptr;         // second source buffer of the one-launch small stage (null: two launches)
   double* part = nullptr;
   double* v = nullptr;
   double* ksum = nullptr;
   size_t bytes = 0;
 };
+
+// Small single-state problems on the one-sided path step each RK4 stage in
+// one launch (k_otf_small with STAGE), alternating the sources between g and
+// g2: stages 1 and 3 read g and write g2, stages 2 and 4 the reverse, so
+// every step starts and ends with the sources in g.
+bool use_small_stage(const ProblemView& pv, int form, int B) {
+  return use_sym(form, B, pv.npad) && small_onesided(pv.npad);
+}
 
 Workspace carve(void* base, const ProblemView& pv, int B, int form, bool stepping) {
   Workspace w;
@@ -314,6 +341,7 @@ Workspace carve(void* base, const ProblemView& pv, int B, int form, bool steppin
   if (stepping) {
     w.v = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
     w.ksum = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
+    if (use_small_stage(pv, form, B)) w.g2 = reinterpret_cast<float*>(take(gbytes));
   }
   w.bytes = off;
   return w;
@@ -463,12 +491,43 @@ int launch_combine(const ProblemView& pv, int form, int B, int stage, double dt,
   if (is_mfma_form(form)) {
     launch_mfma_combine(pv, form, B, stage, dt, u, w.v, w.ksum, w.part, nsplit, fr, w.g, k1_out, gamma, s);
   } else {
-    const int with_q = sources_carry_q(form) ? 1 : 0;
-    NFR_LAUNCH_SLOTS(k_rk4_combine, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, stage, dt, u, w.v, w.ksum,
-                     pv.q, with_q, fr, w.g, k1_out, gamma);
+    const Rk4Stage st{stage, dt, u, w.v, w.ksum, pv.q, sources_carry_q(form) ? 1 : 0, fr, k1_out, gamma};
+    NFR_LAUNCH_SLOTS(k_rk4_combine, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, st, w.g);
   }
   NFR_HIP_LAUNCH();
   return NFR_OK;
+}
+
+// One RK4 stage: pair sums of the current sources, then the stage combination
+// (one launch for small single-state problems, see use_small_stage, else two).
+int launch_stage(nfr_context* ctx, const ProblemView& pv, const nfr_kernel& k_in, int form, int B, const void* W,
+                 const Workspace& w, int stage, double dt, double* u, const Firing& fr, double* k1_out = nullptr,
+                 const double* gamma = nullptr) {
+  int st;
+  if (!w.g2) {
+    if ((st = launch_pairs(ctx, pv, k_in, form, B, W, w))) return st;
+    return launch_combine(pv, form, B, stage, dt, u, w, fr, ctx->stream, k1_out, gamma);
+  }
+  const nfr_kernel k = norm_kernel(k_in);
+  const PairParams pp = pair_params_pow(k, pv);
+  const Rk4Stage rs{stage, dt, u, w.v, w.ksum, pv.q, sources_carry_q(form) ? 1 : 0, fr, k1_out, gamma};
+  const float* g_in = (stage & 1) ? w.g : w.g2;
+  float* g_out = (stage & 1) ? w.g2 : w.g;
+  const dim3 grid((unsigned)(pv.npad / kSmallRows));
+  hipStream_t s = ctx->stream;
+  if ((st = timing_mark(ctx))) return st;
+#define NFR_STAGE_CASE(K) \
+  case K: hipLaunchKernelGGL((k_otf_small<K, true>), grid, dim3(kWG), 0, s, pv.src, g_in, pv.n, pv.npad, pp, w.part, rs, g_out); break;
+  switch (kind_code(k, pv) | (sym_pow_code(k) << 2)) {
+    NFR_STAGE_CASE(0) NFR_STAGE_CASE(1) NFR_STAGE_CASE(2) NFR_STAGE_CASE(3)
+    NFR_STAGE_CASE(4) NFR_STAGE_CASE(5) NFR_STAGE_CASE(6) NFR_STAGE_CASE(7)
+    NFR_STAGE_CASE(8) NFR_STAGE_CASE(9) NFR_STAGE_CASE(10) NFR_STAGE_CASE(11)
+    NFR_STAGE_CASE(12) NFR_STAGE_CASE(13) NFR_STAGE_CASE(14) NFR_STAGE_CASE(15)
+    default: return fail(NFR_ERR_INTERNAL, "no small stage kernel for this kernel code");
+  }
+#undef NFR_STAGE_CASE
+  NFR_HIP_LAUNCH();
+  return timing_mark(ctx);
 }
 
 // One Adams-Bashforth 5 step from the partial sums of K(u_n); n_step >= 4.
@@ -805,8 +864,7 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
   auto one_step = [&]() -> int {
     for (int stage = 1; stage <= 4; ++stage) {
       int r;
-      if ((r = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return r;
-      if ((r = launch_combine(pv, form, B, stage, dt, u_dev, w, fr, s))) return r;
+      if ((r = launch_stage(prob->ctx, pv, *kernel, form, B, w_dev, w, stage, dt, u_dev, fr))) return r;
     }
     return NFR_OK;
   };
@@ -966,8 +1024,7 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
     for (int64_t l = 0; l < len; ++l) {
       for (int stage = 1; stage <= 4; ++stage) {
         NFR_HIP(hipMemcpyAsync(a.store + (l * 4 + stage - 1) * n, a.fwd.v, vbytes, hipMemcpyDeviceToDevice, s));
-        if ((r = launch_pairs(ctx, pv, *kernel, form, 1, nullptr, a.fwd))) return r;
-        if ((r = launch_combine(pv, form, 1, stage, dt, a.useg, a.fwd, fr, s))) return r;
+        if ((r = launch_stage(ctx, pv, *kernel, form, 1, nullptr, a.fwd, stage, dt, a.useg, fr))) return r;
       }
     }
     return NFR_OK;
@@ -1437,8 +1494,8 @@ int nfr_integrate_ab5(nfr_problem* prob, const nfr_kernel* kernel, const nfr_fir
     if (n < 4) {
       // classical RK4 start-up; its first stage is F(u_n), kept for the multistep formula
       for (int stage = 1; stage <= 4; ++stage) {
-        if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return st;
-        if ((st = launch_combine(pv, form, B, stage, dt, u_dev, w, fr, s, hist + (n % 5) * nb))) return st;
+        if ((st = launch_stage(prob->ctx, pv, *kernel, form, B, w_dev, w, stage, dt, u_dev, fr, hist + (n % 5) * nb)))
+          return st;
       }
     } else {
       if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return st;
@@ -1530,9 +1587,8 @@ int nfr_integrate_forced(nfr_problem* prob, const nfr_kernel* kernel, const nfr_
   static const int slot_of_stage[5] = {0, 0, 1, 1, 2};
   for (int64_t n = 0; n < steps; ++n) {
     for (int stage = 1; stage <= 4; ++stage) {
-      if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return st;
       const double* gam = forcing_dev + (n * 3 + slot_of_stage[stage]) * nb;
-      if ((st = launch_combine(pv, form, B, stage, dt, u_dev, w, fr, s, nullptr, gam))) return st;
+      if ((st = launch_stage(prob->ctx, pv, *kernel, form, B, w_dev, w, stage, dt, u_dev, fr, nullptr, gam))) return st;
     }
   }
   return NFR_OK;

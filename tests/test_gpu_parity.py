@@ -189,6 +189,35 @@ def test_integrate_deterministic_graph_and_resume(ctx, sphere_case):
     assert np.array_equal(ck[1], _integrate(ctx, *args, 10))
 
 
+@pytest.mark.parametrize("n", [1000, 2000, 5000])
+def test_integrate_ignores_stale_workspace(ctx, n):
+    """A workspace may hold anything before a call (here 0xFF bytes, NaN
+    patterns): RK4 and Adams-Bashforth 5 runs give bitwise the results of a
+    zeroed workspace, and RK4 stays within 1e-5 of the oracle.  Sizes on both
+    sides of the switch between the one-sided small-problem path (one launch
+    per stage, sources alternating between two buffers) and the symmetric one."""
+    w = C.sphere_small(n)
+    q = C.area_share_weights(w.surface)
+    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
+    k = P.kernel_struct(w.kernel_kind, *w.kernel)
+    f = P.Firing(w.beta, float(w.theta[0]))
+    lib = P.lib()
+    out = {}
+    for fill in (0, 255):
+        ws = torch.full((lib.nfr_integrate_ab5_workspace_size(prob.handle, 1, 0),), fill, dtype=torch.uint8,
+                        device="cuda")
+        u = torch.from_numpy(w.u0.copy()).cuda()
+        prob.integrate(k, f, u, 0.05, 12, ws=ws)
+        ws.fill_(fill)
+        v = torch.from_numpy(w.u0.copy()).cuda()
+        prob.integrate_ab5(k, f, v, 0.05, 9, ws=ws)
+        torch.cuda.synchronize()
+        out[fill] = (u.cpu().numpy(), v.cpu().numpy())
+    assert np.array_equal(out[0][0], out[255][0]) and np.array_equal(out[0][1], out[255][1])
+    ref = NF.rk4(NF.DenseOperator(w.surface.xyz, q, w.kernel_kind, w.kernel), w.u0, w.beta, w.theta, 0.05, 12)
+    assert np.all(NF.rel_linf(out[0][0], ref) <= 1e-5)
+
+
 def test_invalid_arguments_rejected(ctx):
     x = S.fibonacci_sphere(100)
     prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.full((100,), 0.1, dtype=torch.float64).cuda())
