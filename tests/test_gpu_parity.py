@@ -128,6 +128,26 @@ def test_integrate_sphere_workload_w_form(ctx, sphere_case):
     assert np.all(NF.rel_linf(u, ref) <= 1e-5)
 
 
+@pytest.mark.parametrize("n", [1, 7, 257, 4096, 4097])
+@pytest.mark.parametrize("kind", [NF.GAUSS_MH, NF.EXP_MH])
+def test_integrate_small_and_ragged(ctx, n, kind):
+    """Single-state RK4 at sizes that are mostly padding (1, 7, 257 nodes in
+    256-node blocks) and on both sides of the switch from the one-sided
+    small-problem path (one launch per stage) to the symmetric one (4096 /
+    4097 nodes): 8 steps against the oracle to 1e-5, with a negative weight."""
+    rng = np.random.default_rng(70 + n + kind)
+    x = S.fibonacci_sphere(n) * rng.uniform(0.9, 1.1)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    if n > 3:
+        q[rng.integers(n)] *= -0.1
+    u0 = rng.normal(0.2, 0.4, size=(1, n))
+    p = GAUSS if kind == NF.GAUSS_MH else EXPK
+    u = _integrate(ctx, x, q, u0, kind, p, 20.0, 0.2, 0.05, 8)
+    ref = NF.rk4(NF.DenseOperator(x, q, kind, p), u0, 20.0, np.array([0.2]), 0.05, 8)
+    err = NF.rel_linf(u, ref)
+    assert np.all(err <= 1e-5), err
+
+
 @pytest.fixture(scope="module")
 def torus_case():
     w = C.torus_exp(4096, steps=100)
