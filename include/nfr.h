@@ -133,7 +133,9 @@ const char* nfr_context_arch(const nfr_context* ctx);
 
 /* Timing of pair-sum launches (the operator's dominant kernel) with HIP events
  * recorded on the context stream around each launch; not recorded for launches
- * replayed from graphs.  set_timing(ctx, 1) starts a fresh measurement;
+ * replayed from graphs.  When time stepping a single state of at most 4096
+ * padded nodes, the timed launch also applies the RK4 stage update (one
+ * launch per stage).  set_timing(ctx, 1) starts a fresh measurement;
  * nfr_context_timing synchronises the stream and returns the number of timed
  * launches and their summed duration in milliseconds, then resets. */
 int nfr_context_set_timing(nfr_context* ctx, int enable);
