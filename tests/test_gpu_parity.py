@@ -300,7 +300,8 @@ def test_apply_large_n_both_sides_of_the_slot_budget(ctx, n):
 # Amplitude edge cases for every form, with one negative weight; tolerances
 # as above (split forms: those derived in test_gpu_mfma_otf / test_gpu_mfma).
 AMP_CASES = [(0.0, 0.5), (-1.0, 0.5), (1e-6, 0.5), (0.7, 0.0), (0.0, 0.0)]
-FORM_TOL = {(0, 1): 1e-5, (0, 5): 1e-5, (1, 5): 2e-6, (2, 40): 3e-5, (3, 40): 2e-6, (4, 40): 4e-5, (5, 40): 1.2e-5}
+FORM_TOL = {(0, 1): 1e-5, (0, 5): 1e-5, (1, 5): 2e-6, (2, 40): 3e-5, (3, 40): 2e-6, (4, 40): 4e-5, (5, 40): 1.2e-5,
+            (6, 40): 1e-5}
 
 
 @pytest.mark.parametrize("form,B", list(FORM_TOL))
