@@ -376,6 +376,14 @@ struct MfmaOtfParams {
 #ifndef NFR_MFMA_OTF_MIN_WGS
 #define NFR_MFMA_OTF_MIN_WGS 2
 #endif
+// LDS buffers of the staged G tile.  FP16 keeps two (one step's tile is
+// written while the other is read; one barrier per step).  BF16 uses one
+// (a second barrier per step) and halves its LDS: 2.29 -> 2.22-2.24 ms per
+// application at N = 65536, B = 64, the same 114 registers and 4 waves per
+// SIMD; FP16, whose two accumulator sets need 152 registers, gained nothing.
+#ifndef NFR_MFMA_OTF_BF16_LDS_BUFS
+#define NFR_MFMA_OTF_BF16_LDS_BUFS 1
+#endif
 template <typename T, int KIND, int NB>
 __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
                                                      const T* __restrict__ Glo, int64_t npad, int B, int64_t kchunk,
@@ -386,10 +394,11 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
   constexpr int NS = 32 * NB;
   constexpr int ROWCH = kMfmaStep / 8;
   constexpr int CHUNKS = NS * 2 * ROWCH / kWG;
-  __shared__ __attribute__((aligned(16))) T sG[2][2][NS][kMfmaLdsStride];
+  constexpr int kOtfBufs = kTwoAcc ? 2 : NFR_MFMA_OTF_BF16_LDS_BUFS;
+  __shared__ __attribute__((aligned(16))) T sG[kOtfBufs][2][NS][kMfmaLdsStride];
   // column coordinates x, y, z (row 3: the packed zero component); wave w
   // loads and stores row w, so no load sits behind a branch
-  __shared__ __attribute__((aligned(16))) float sS[2][4][kMfmaStep];
+  __shared__ __attribute__((aligned(16))) float sS[kOtfBufs][4][kMfmaStep];
   static_assert(kWG == 4 * 64, "one wave per coordinate row");
 
   const int64_t wg = blockIdx.x;
@@ -442,7 +451,7 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     sn = reinterpret_cast<const float*>(src + k_begin + tc * kMfmaStep + lane)[wave];
   };
   auto store_next = [&](int t) {
-    const int buf = t & 1;
+    const int buf = t % kOtfBufs;
 #pragma unroll
     for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[buf][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
     sS[buf][wave][lane] = sn * op.sig;
@@ -492,7 +501,7 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     }
   };
   auto compute = [&](int t) {
-    const int buf = t & 1;
+    const int buf = t % kOtfBufs;
     V h0, l0, h1, l1;
     eval(buf, 0, h0, l0);
 #pragma unroll
@@ -504,7 +513,8 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     }
   };
   // step t: issue the loads of step t + 1, evaluate and multiply step t from
-  // LDS half t & 1, store step t + 1 into the other half, barrier.
+  // LDS buffer t % kOtfBufs, (one buffer: barrier), store step t + 1 into the
+  // next buffer, barrier.
   if (nsteps > 0) {
     load_next(0);
     store_next(0);
@@ -515,6 +525,7 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
       // to just before its LDS store, exposing its latency every step
       __builtin_amdgcn_sched_barrier(0);
       compute(t);
+      if (kOtfBufs == 1) __syncthreads();
       store_next(t + 1);
       __syncthreads();
     }
