@@ -384,6 +384,9 @@ struct MfmaOtfParams {
 #ifndef NFR_MFMA_OTF_BF16_LDS_BUFS
 #define NFR_MFMA_OTF_BF16_LDS_BUFS 1
 #endif
+#ifndef NFR_MFMA_OTF_FP16_LDS_BUFS
+#define NFR_MFMA_OTF_FP16_LDS_BUFS 2
+#endif
 template <typename T, int KIND, int NB>
 __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
                                                      const T* __restrict__ Glo, int64_t npad, int B, int64_t kchunk,
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
   constexpr int NS = 32 * NB;
   constexpr int ROWCH = kMfmaStep / 8;
   constexpr int CHUNKS = NS * 2 * ROWCH / kWG;
-  constexpr int kOtfBufs = kTwoAcc ? 2 : NFR_MFMA_OTF_BF16_LDS_BUFS;
+  constexpr int kOtfBufs = kTwoAcc ? NFR_MFMA_OTF_FP16_LDS_BUFS : NFR_MFMA_OTF_BF16_LDS_BUFS;
   __shared__ __attribute__((aligned(16))) T sG[kOtfBufs][2][NS][kMfmaLdsStride];
   // column coordinates x, y, z (row 3: the packed zero component); wave w
   // loads and stores row w, so no load sits behind a branch
@@ -563,6 +566,13 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
 // through double-buffered LDS tiles; states beyond B read state B - 1 (their
 // outputs are never written).
 constexpr int kF32FoldSteps = 4;     // pipeline steps (of 64 sources) per FP64 fold
+// One LDS buffer for the staged sources and a second barrier per step: 5.19
+// -> 5.10 ms per application at N = 65536, B = 64 (measured alternately
+// against two buffers), same registers and occupancy.
+#ifndef NFR_MFMA_F32_LDS_BUFS
+#define NFR_MFMA_F32_LDS_BUFS 1
+#endif
+constexpr int kF32Bufs = NFR_MFMA_F32_LDS_BUFS;
 
 template <int KIND, int NB>
 __global__ __launch_bounds__(kWG, 2) void k_mfma_otf_f32(const float4* __restrict__ src, const float* __restrict__ g,
@@ -573,10 +583,10 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf_f32(const float4* __restric
   constexpr int ROWCH = kMfmaStep / 4;           // 16-byte chunks per row
   constexpr int CHUNKS = NS * ROWCH / kWG;       // chunks per thread per step
   typedef __attribute__((ext_vector_type(4))) float f4_t;
-  __shared__ __attribute__((aligned(16))) float sG[2][NS][STRIDE];
+  __shared__ __attribute__((aligned(16))) float sG[kF32Bufs][NS][STRIDE];
   // column coordinates x, y, z (row 3: the packed zero component); wave w
   // loads and stores row w, so no load sits behind a branch
-  __shared__ __attribute__((aligned(16))) float sS[2][4][kMfmaStep];
+  __shared__ __attribute__((aligned(16))) float sS[kF32Bufs][4][kMfmaStep];
   static_assert(kWG == 4 * 64, "one wave per coordinate row");
 
   const int64_t wg = blockIdx.x;
@@ -628,13 +638,13 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf_f32(const float4* __restric
     sn = reinterpret_cast<const float*>(src + k_begin + tc * kMfmaStep + lane)[wave];
   };
   auto store_next = [&](int t) {
-    const int buf = t & 1;
+    const int buf = t % kF32Bufs;
 #pragma unroll
     for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<f4_t*>(&sG[buf][g_row[q]][g_col[q]]) = gn[q];
     sS[buf][wave][lane] = sn * pp.sig;
   };
   auto compute = [&](int t) {
-    const int buf = t & 1;
+    const int buf = t % kF32Bufs;
 #pragma unroll
     for (int k4 = 0; k4 < kMfmaStep / 8; ++k4) {
       const int c0 = 32 * h + 4 * k4;
@@ -677,6 +687,7 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf_f32(const float4* __restric
       __builtin_amdgcn_sched_barrier(0);
       compute(t);
       if ((t + 1) % kF32FoldSteps == 0) fold();
+      if (kF32Bufs == 1) __syncthreads();
       store_next(t + 1);
       __syncthreads();
     }
