@@ -207,6 +207,14 @@ constexpr int kMfmaDepth = NFR_MFMA_DEPTH;       // W register stages
 constexpr int kMfmaKb = kMfmaStep / 16;          // 32x32x16 MFMA steps per pipeline step
 constexpr int kMfmaLdsStride = kMfmaStep + 8;    // halves per LDS row (padding against bank conflicts)
 
+// LDS buffers of the staged G tile: two (one step's tile written while the
+// other is read).  One buffer with a second barrier per step, which helped
+// the on-the-fly kernels, measured slower here: 3.01 against 2.90 ms (BF16)
+// at N = 65536, B = 64.
+#ifndef NFR_MFMA_APPLY_LDS_BUFS
+#define NFR_MFMA_APPLY_LDS_BUFS 2
+#endif
+constexpr int kApplyBufs = NFR_MFMA_APPLY_LDS_BUFS;
 template <typename T, int NB>
 __global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Wt, const T* __restrict__ Ghi, const T* __restrict__ Glo,
                                                        int64_t npad, int B, int64_t kchunk,
@@ -215,7 +223,7 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Wt,
   constexpr int NS = 32 * NB;                                  // states per group
   constexpr int ROWCH = kMfmaStep / 8;                         // 16-byte chunks per LDS row
   constexpr int CHUNKS = NS * 2 * ROWCH / kWG;                 // G chunks per thread per step
-  __shared__ __attribute__((aligned(16))) T sG[2][2][NS][kMfmaLdsStride];
+  __shared__ __attribute__((aligned(16))) T sG[kApplyBufs][2][NS][kMfmaLdsStride];
 
   const int64_t wg = blockIdx.x;
   const int split = (int)(wg % kMfmaSplits);
@@ -277,10 +285,10 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Wt,
   };
   auto store_g = [&](int t) {
 #pragma unroll
-    for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[t & 1][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
+    for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[t % kApplyBufs][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
   };
   auto compute = [&](const WSet& w, int t) {
-    const int buf = t & 1;
+    const int buf = t % kApplyBufs;
 #pragma unroll
     for (int kb = 0; kb < kMfmaKb; ++kb) {
       const int col = 16 * kb + 8 * h;
@@ -295,7 +303,7 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Wt,
     }
   };
   // step t (ring slot t mod kMfmaDepth): issue the G loads of t + 1, then the
-  // W loads of step t + kMfmaDepth - 1, compute t from LDS half t & 1, store
+  // W loads of step t + kMfmaDepth - 1, compute t from LDS half t % kApplyBufs, store
   // G of t + 1 into the other half, barrier.  The G loads go first: loads
   // complete in issue order, so waiting for G does not wait for the W
   // prefetch, which stays in flight across the barrier.
@@ -314,6 +322,7 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Wt,
         load_g(t + 1);
         load_w(ring[(d + kMfmaDepth - 1) % kMfmaDepth], t + kMfmaDepth - 1);
         compute(ring[d], t);
+        if (kApplyBufs == 1) __syncthreads();
         store_g(t + 1);
         __syncthreads();
       }
@@ -325,6 +334,7 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Wt,
         load_g(t + 1);
         load_w(ring[(d + kMfmaDepth - 1) % kMfmaDepth], t + kMfmaDepth - 1);
         compute(ring[d], t);
+        if (kApplyBufs == 1) __syncthreads();
         store_g(t + 1);
         __syncthreads();
       }
