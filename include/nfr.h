@@ -96,8 +96,9 @@ typedef struct {
  *                  products on the FP32 matrix cores: for blocks of states
  *                  (32 or 64 at a time), the vector units only evaluate the
  *                  kernel.  No W matrix.
- *   AUTO:          the library picks the form (at present always
- *                  ONTHEFLY_FP32, which needs no W matrix). */
+ *   AUTO:          the library picks an FP32-class form that needs no W
+ *                  matrix: ONTHEFLY_FP32_MFMA for B > 16, ONTHEFLY_FP32
+ *                  otherwise (workspace sizes follow the same choice). */
 enum nfr_form {
   NFR_FORM_AUTO = -1,
   NFR_FORM_ONTHEFLY_FP32 = 0,

@@ -142,3 +142,23 @@ def test_f32_mfma_integrate_ensemble_per_member(ctx, stepper):
     torch.cuda.synchronize()
     err = NF.rel_linf(u.cpu().numpy(), ref)
     assert np.all(err <= TOL), err.max()
+
+
+@pytest.mark.parametrize("B,expect", [(1, 0), (16, 0), (17, 6), (64, 6)])
+def test_auto_form_picks_fp32_class_form(ctx, B, expect):
+    """FORM_AUTO resolves to the FP32 matrix-core form above 16 states and to
+    the vector-unit FP32 sum below: bitwise the result of that form."""
+    n = 700
+    rng = np.random.default_rng(90 + B)
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
+    k = P.kernel_struct(NF.GAUSS_MH, 1.0, 0.15, 0.5, 0.4)
+    th = torch.from_numpy(rng.uniform(0.1, 0.3, size=B)).cuda() if B > 1 else 0.2
+    f = P.Firing(20.0, th)
+    u = torch.from_numpy(U).cuda()
+    a = prob.apply(k, f, u, form=P.FORM_AUTO)
+    b = prob.apply(k, f, u, form=expect)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
