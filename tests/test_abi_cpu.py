@@ -45,13 +45,14 @@ def test_status_strings_and_version(L):
 def test_size_queries(L):
     assert L.nfr_problem_bytes(0) == 0
     assert L.nfr_problem_bytes(1) > 0
+    assert L.nfr_problem_bytes(4_000_000) > 0 and L.nfr_problem_bytes(4_000_001) == 0   # largest N
     npad = 32768
     assert L.nfr_w_bytes(32768, 1) == 32768 * npad * 4
     assert L.nfr_w_bytes(1000, 0) == 0
     npad = 1024
     for form in (2, 3):   # 256-byte header + hi and lo halves
         assert L.nfr_w_bytes(1000, form) == 256 + 2 * npad * npad * 2
-    for form in (4, 5, 6, -1):   # fused on-the-fly forms need no W; 6 is no form
+    for form in (4, 5, 6, -1):   # on-the-fly matrix-core forms and AUTO need no W
         assert L.nfr_w_bytes(1000, form) == 0
 
 

@@ -76,6 +76,46 @@ def test_apply_matches_oracle(ctx, n, B, kind, form):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("form", [0, 6, -1])   # -1: FORM_AUTO
+def test_apply_largest_state_count(ctx, form):
+    """B = 4096, the largest accepted state count, on a small ragged node set
+    (300 nodes): every state against the oracle to 1e-5 of S_i."""
+    n, B = 300, 4096
+    rng = np.random.default_rng(4096 + form)
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.1, 0.3, size=B)
+    y = _run_apply(ctx, x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, form)
+    ref = NF.apply_K(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta)
+    scale = _abs_scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, None)
+    assert np.max(np.abs(y - ref) / scale) <= 1e-5
+
+
+COINCIDENT_TOL = {0: 1e-5, 1: 2e-6, 4: 4e-5, 5: 1.2e-5, 6: 1e-5}
+
+
+@pytest.mark.parametrize("form", list(COINCIDENT_TOL))
+@pytest.mark.parametrize("kind", [NF.GAUSS_MH, NF.EXP_MH])
+def test_apply_coincident_nodes(ctx, form, kind):
+    """Nodes that coincide (50 points, each 4 times: r = 0 between distinct
+    nodes, not only on the diagonal) in every pair kernel: one state (the
+    small-problem path) and 40 states (the matrix-core tiles), against the oracle."""
+    rng = np.random.default_rng(50 + form + 7 * kind)
+    base = S.fibonacci_sphere(50)
+    x = np.repeat(base, 4, axis=0)[rng.permutation(200)]
+    n = x.shape[0]
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    B = 1 if form in (0, 1) else 40
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.1, 0.3, size=B) if B > 1 else 0.2
+    p = GAUSS if kind == NF.GAUSS_MH else EXPK
+    y = _run_apply(ctx, x, q, U, kind, p, 20.0, theta, form)
+    ref = NF.apply_K(x, q, U, kind, p, 20.0, theta)
+    scale = _abs_scale(x, q, U, kind, p, 20.0, theta, None)
+    assert np.max(np.abs(y - ref) / scale) <= COINCIDENT_TOL[form]
+
+
 def test_apply_full_size_torus_sampled_rows(ctx):
     """Torus workload at its full size (N = 32768): one application, 64 sampled rows."""
     w = C.torus_exp()
