@@ -373,20 +373,56 @@ __device__ inline int64_t group_index(int* sub) {
   return gt / L;
 }
 
+// Slot sums shared by a workgroup: its E = kWG / L consecutive elements each
+// get L threads; thread t serves element t mod E as sub r = t / E and adds
+// slots r, r + L, r + 2L, ... in order, and the sub-0 thread then adds the L
+// partial sums in r order (through LDS).  The threads of a wave read
+// consecutive elements of one slot row, so every load is whole cache lines
+// (L lanes of one element side by side would read L rows for few elements),
+// while L threads per element keep enough loads in flight.  Every thread of
+// the workgroup must call it; it returns true in the thread holding an
+// element's total (in *total, the element index in *idx).  `red`: kWG doubles
+// of LDS.
+template <int L>
+__device__ inline bool slot_total(const double* __restrict__ part, int nsplit, int64_t n, int64_t npad, int B,
+                                  double* red, int64_t* idx, double* total) {
+  constexpr int E = kWG / L;
+  const int t = threadIdx.x;
+  const int e = t % E, r = t / E;
+  const int64_t el = (int64_t)blockIdx.x * E + e;
+  const bool valid = el < n * (int64_t)B;
+  double y = 0.0;
+  if (valid) {
+    const int b = (int)(el / n);
+    const int64_t i = el - (int64_t)b * n;
+    for (int sp = r; sp < nsplit; sp += L) y += part[((int64_t)sp * B + b) * npad + i];
+  }
+  if (L > 1) {
+    red[t] = y;
+    __syncthreads();
+    if (r == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < L; ++q) s += red[q * E + e];
+      y = s;
+    }
+  }
+  *idx = el;
+  *total = y;
+  return valid && r == 0;
+}
+
 // y[b*n + i] = sum of the partials of (b, i), FP64.  Grid: n*B*L threads.
 template <int L>
 __global__ __launch_bounds__(kWG) void k_reduce_partials(const double* __restrict__ part, int nsplit, int64_t n,
                                                          int64_t npad, int B, double* __restrict__ y) {
-  int sub;
-  const int64_t idx = group_index<L>(&sub);
-  if (idx >= n * (int64_t)B) return;
-  const int b = (int)(idx / n);
-  const int64_t i = idx - (int64_t)b * n;
-  const double s = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
-  if (sub == 0) y[idx] = s;
+  __shared__ double red[kWG];
+  int64_t idx;
+  double s;
+  if (slot_total<L>(part, nsplit, n, npad, B, red, &idx, &s)) y[idx] = s;
 }
 
-// RK4 stage combination, all FP64 (L threads per (i, b), i < n; see slot_sum):
+// RK4 stage combination, all FP64 (L threads per (i, b), i < n; see slot_total):
 //   y   = sum of partials (= K(v_s)),  k = -v_s + y
 //   s=1: ksum = k,        v <- u + dt/2 k
 //   s=2: ksum += 2k,      v <- u + dt/2 k
@@ -445,13 +481,12 @@ __device__ inline void rk4_update(const Rk4Stage& st, int64_t idx, int b, int64_
 template <int L>
 __global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ part, int nsplit, int64_t n,
                                                      int64_t npad, int B, Rk4Stage st, float* __restrict__ g) {
-  int sub;
-  const int64_t idx = group_index<L>(&sub);
-  if (idx >= n * (int64_t)B) return;
+  __shared__ double red[kWG];
+  int64_t idx;
+  double y;
+  if (!slot_total<L>(part, nsplit, n, npad, B, red, &idx, &y)) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
-  const double y = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
-  if (sub != 0) return;
   rk4_update(st, idx, b, i, npad, y, g);
 }
 
@@ -548,14 +583,13 @@ __global__ __launch_bounds__(kWG) void k_ab5_combine(const double* __restrict__ 
                                                      int slot4, double* __restrict__ u, double* __restrict__ hist,
                                                      const double* __restrict__ qd, int with_q, Firing fr,
                                                      float* __restrict__ g) {
-  int sub;
-  const int64_t idx = group_index<L>(&sub);
+  __shared__ double red[kWG];
   const int64_t nb = n * (int64_t)B;
-  if (idx >= nb) return;
+  int64_t idx;
+  double y;
+  if (!slot_total<L>(part, nsplit, n, npad, B, red, &idx, &y)) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
-  const double y = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
-  if (sub != 0) return;
   const double ui = u[idx];
   const double F = -ui + y;
   hist[slots03.x * nb + idx] = F;
@@ -602,14 +636,13 @@ __global__ __launch_bounds__(kWG) void k_syndep_combine(const double* __restrict
                                                         double* __restrict__ ku_sum, double* __restrict__ ka_sum,
                                                         const double* __restrict__ qd, Firing fr,
                                                         float* __restrict__ g) {
-  int sub;
-  const int64_t idx = group_index<L>(&sub);
-  if (idx >= n * (int64_t)B) return;
+  __shared__ double red[kWG];
+  int64_t idx;
+  double y;
+  if (!slot_total<L>(part, nsplit, n, npad, B, red, &idx, &y)) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
   const double th = state_theta(fr, b);
-  const double y = slot_sum<L>(part, nsplit, B, npad, b, i, sub);
-  if (sub != 0) return;
   const double cu = vu[idx], ca = va[idx];
   const double ku = -cu + y;
   const double ka = (1.0 - ca - beta_d * ca * sigmoid(cu, fr.beta, th)) * inv_tau;
