@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kWG) void k_adj_init(const double* __restrict__ uba
   }
 }
 
-// One reverse stage (L threads per node j < n, see slot_sum); see the file comment.  Block
+// One reverse stage (L threads per node j < n, see slot_total); see the file comment.  Block
 // partial sums of the five parameter terms are added to pblk[block * 8 + c]
 // by thread 0 of the block (the launches are ordered on one stream, so the
 // accumulation order is fixed).
@@ -195,15 +195,14 @@ __global__ __launch_bounds__(kWG) void k_adj_combine(const double* __restrict__ 
                                                      double* __restrict__ unbar, double* __restrict__ lam,
                                                      float* __restrict__ lam32, double* __restrict__ pblk) {
   __shared__ double red[5][kWG];
-  int sub;
-  const int64_t j = group_index<L>(&sub);
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
+  __shared__ double sred[4][kWG];     // one row per channel: the channels' sums never share LDS
+  int64_t j = 0;
+  bool lead = false;
   double S[4] = {0.0, 0.0, 0.0, 0.0};
-  if (j < n) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) S[c] = slot_sum<L>(part + (int64_t)c * nsplit * npad, nsplit, 1, npad, 0, j, sub);
-  }
-  if (j < n && sub == 0) {
+  for (int c = 0; c < 4; ++c) lead = slot_total<L>(part + (int64_t)c * nsplit * npad, nsplit, n, npad, 1, sred[c], &j, &S[c]);
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
+  if (lead) {
     const double z = co.Ae * S[0] - co.Ai * S[1];
     const double f = sigmoid(vs[j], fr.beta, fr.theta);
     const double fp = fr.beta * f * (1.0 - f);

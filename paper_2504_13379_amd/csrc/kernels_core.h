@@ -348,31 +348,9 @@ __global__ __launch_bounds__(64 * SPLIT) void k_otf_sym(const float4* __restrict
 
 // ------------------------------------------------------------------ reductions
 
-// Partial sums part[(s*B + b)*npad + i] of one element (b, i), added by a group
-// of L consecutive lanes (L a power of two, at most 64): lane r of the group
-// adds slots r, r + L, r + 2L, ... in order, then the group adds its L values
-// by an xor butterfly.  Both operands of every butterfly addition are the same
-// in the two lanes that perform it, so all L lanes end with the same,
-// reproducible total.  Many slots (the symmetric kernel has one per tile) are
-// then read by many lanes in parallel instead of one.
-template <int L>
-__device__ inline double slot_sum(const double* __restrict__ part, int nsplit, int B, int64_t npad, int b,
-                                  int64_t i, int sub) {
-  double y = 0.0;
-  for (int sp = sub; sp < nsplit; sp += L) y += part[((int64_t)sp * B + b) * npad + i];
-#pragma unroll
-  for (int off = L / 2; off > 0; off >>= 1) y += __shfl_xor(y, off, L);
-  return y;
-}
-
-// Element index and lane-in-group of the calling thread for L lanes per element.
-template <int L>
-__device__ inline int64_t group_index(int* sub) {
-  const int64_t gt = (int64_t)blockIdx.x * kWG + threadIdx.x;
-  *sub = (int)(gt & (L - 1));
-  return gt / L;
-}
-
+// Partial sums part[(s*B + b)*npad + i] of element (b, i): the symmetric
+// kernel has one slot per tile, so a combine reads many slots per element;
+// it reads them with L threads per element (L a power of two dividing kWG).
 // Slot sums shared by a workgroup: its E = kWG / L consecutive elements each
 // get L threads; thread t serves element t mod E as sub r = t / E and adds
 // slots r, r + L, r + 2L, ... in order, and the sub-0 thread then adds the L
@@ -556,7 +534,7 @@ __global__ __launch_bounds__(kWG) void k_otf_small(const float4* __restrict__ sr
     if (!STAGE) {
       part[i] = pp.amp * y;
     } else if (i < n) {
-      double ys = 0.0;            // as slot_sum adds the single slot
+      double ys = 0.0;            // as slot_total adds the single slot
       ys += pp.amp * y;
       rk4_update(st, i, 0, i, npad, ys, g_next);
     } else {
