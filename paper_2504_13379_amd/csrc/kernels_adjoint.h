@@ -195,12 +195,10 @@ __global__ __launch_bounds__(kWG) void k_adj_combine(const double* __restrict__ 
                                                      double* __restrict__ unbar, double* __restrict__ lam,
                                                      float* __restrict__ lam32, double* __restrict__ pblk) {
   __shared__ double red[5][kWG];
-  __shared__ double sred[4][kWG];     // one row per channel: the channels' sums never share LDS
+  __shared__ double sred[4 * kWG];    // slot sums of the four channels (not shared with red)
   int64_t j = 0;
-  bool lead = false;
-  double S[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int c = 0; c < 4; ++c) lead = slot_total<L>(part + (int64_t)c * nsplit * npad, nsplit, n, npad, 1, sred[c], &j, &S[c]);
+  double S[4];
+  const bool lead = slot_total<L, 4>(part, (int64_t)nsplit * npad, nsplit, n, npad, 1, sred, &j, S);
   double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, c4 = 0.0;
   if (lead) {
     const double z = co.Ae * S[0] - co.Ai * S[1];

@@ -359,34 +359,44 @@ __global__ __launch_bounds__(64 * SPLIT) void k_otf_sym(const float4* __restrict
 // (L lanes of one element side by side would read L rows for few elements),
 // while L threads per element keep enough loads in flight.  Every thread of
 // the workgroup must call it; it returns true in the thread holding an
-// element's total (in *total, the element index in *idx).  `red`: kWG doubles
-// of LDS.
-template <int L>
-__device__ inline bool slot_total(const double* __restrict__ part, int nsplit, int64_t n, int64_t npad, int B,
-                                  double* red, int64_t* idx, double* total) {
+// element's total (in *total, the element index in *idx).  C channels (slot
+// arrays chstride apart, as the adjoint's four) are summed together, their
+// loads in flight at once, with one barrier.  `red`: C * kWG doubles of LDS.
+template <int L, int C = 1>
+__device__ inline bool slot_total(const double* __restrict__ part, int64_t chstride, int nsplit, int64_t n,
+                                  int64_t npad, int B, double* red, int64_t* idx, double* total) {
   constexpr int E = kWG / L;
   const int t = threadIdx.x;
   const int e = t % E, r = t / E;
   const int64_t el = (int64_t)blockIdx.x * E + e;
   const bool valid = el < n * (int64_t)B;
-  double y = 0.0;
+  double y[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) y[c] = 0.0;
   if (valid) {
     const int b = (int)(el / n);
     const int64_t i = el - (int64_t)b * n;
-    for (int sp = r; sp < nsplit; sp += L) y += part[((int64_t)sp * B + b) * npad + i];
+    for (int sp = r; sp < nsplit; sp += L)
+#pragma unroll
+      for (int c = 0; c < C; ++c) y[c] += part[c * chstride + ((int64_t)sp * B + b) * npad + i];
   }
   if (L > 1) {
-    red[t] = y;
+#pragma unroll
+    for (int c = 0; c < C; ++c) red[c * kWG + t] = y[c];
     __syncthreads();
     if (r == 0) {
-      double s = 0.0;
 #pragma unroll
-      for (int q = 0; q < L; ++q) s += red[q * E + e];
-      y = s;
+      for (int c = 0; c < C; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < L; ++q) s += red[c * kWG + q * E + e];
+        y[c] = s;
+      }
     }
   }
   *idx = el;
-  *total = y;
+#pragma unroll
+  for (int c = 0; c < C; ++c) total[c] = y[c];
   return valid && r == 0;
 }
 
@@ -397,7 +407,7 @@ __global__ __launch_bounds__(kWG) void k_reduce_partials(const double* __restric
   __shared__ double red[kWG];
   int64_t idx;
   double s;
-  if (slot_total<L>(part, nsplit, n, npad, B, red, &idx, &s)) y[idx] = s;
+  if (slot_total<L>(part, 0, nsplit, n, npad, B, red, &idx, &s)) y[idx] = s;
 }
 
 // RK4 stage combination, all FP64 (L threads per (i, b), i < n; see slot_total):
@@ -462,7 +472,7 @@ __global__ __launch_bounds__(kWG) void k_rk4_combine(const double* __restrict__ 
   __shared__ double red[kWG];
   int64_t idx;
   double y;
-  if (!slot_total<L>(part, nsplit, n, npad, B, red, &idx, &y)) return;
+  if (!slot_total<L>(part, 0, nsplit, n, npad, B, red, &idx, &y)) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
   rk4_update(st, idx, b, i, npad, y, g);
@@ -565,7 +575,7 @@ __global__ __launch_bounds__(kWG) void k_ab5_combine(const double* __restrict__ 
   const int64_t nb = n * (int64_t)B;
   int64_t idx;
   double y;
-  if (!slot_total<L>(part, nsplit, n, npad, B, red, &idx, &y)) return;
+  if (!slot_total<L>(part, 0, nsplit, n, npad, B, red, &idx, &y)) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
   const double ui = u[idx];
@@ -617,7 +627,7 @@ __global__ __launch_bounds__(kWG) void k_syndep_combine(const double* __restrict
   __shared__ double red[kWG];
   int64_t idx;
   double y;
-  if (!slot_total<L>(part, nsplit, n, npad, B, red, &idx, &y)) return;
+  if (!slot_total<L>(part, 0, nsplit, n, npad, B, red, &idx, &y)) return;
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
   const double th = state_theta(fr, b);
