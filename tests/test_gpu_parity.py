@@ -308,7 +308,7 @@ RATIO_KERNELS = [(NF.GAUSS_MH, (1.0, 0.2, 0.5, 0.2 * math.sqrt(2.0))),     # rho
 
 
 @pytest.mark.parametrize("kind,p", RATIO_KERNELS)
-@pytest.mark.parametrize("n", [383, 3001])
+@pytest.mark.parametrize("n", [383, 3001, 5000, 9000])   # one-sided small; symmetric 64- and 256-node tiles
 def test_apply_integer_ratio_kernels(ctx, kind, p, n):
     rng = np.random.default_rng(n + int(p[3] * 1000))
     x = S.fibonacci_sphere(n)
@@ -318,6 +318,20 @@ def test_apply_integer_ratio_kernels(ctx, kind, p, n):
     ref = NF.apply_K(x, q, U, kind, p, 20.0, 0.2)
     scale = _abs_scale(x, q, U, kind, p, 20.0, 0.2, None)
     assert np.max(np.abs(y - ref) / scale) <= 1e-5
+
+
+@pytest.mark.parametrize("kind,p", RATIO_KERNELS)
+def test_integrate_integer_ratio_kernels_small(ctx, kind, p):
+    """The one-launch RK4 stage of small single-state problems for every
+    integer-ratio kernel: 6 steps against the oracle to 1e-5."""
+    n = 383
+    rng = np.random.default_rng(7 + int(p[3] * 1000))
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    u0 = rng.normal(0.2, 0.4, size=(1, n))
+    u = _integrate(ctx, x, q, u0, kind, p, 20.0, 0.2, 0.05, 6)
+    ref = NF.rk4(NF.DenseOperator(x, q, kind, p), u0, 20.0, np.array([0.2]), 0.05, 6)
+    assert np.all(NF.rel_linf(u, ref) <= 1e-5)
 
 
 @pytest.mark.parametrize("n", [300000, 700000])
