@@ -30,7 +30,20 @@
 namespace nfr {
 
 constexpr bool kMfmaAvailable = true;
-constexpr int kMfmaSplits = 8;        // one source chunk per XCD (workgroup id % 8 picks the XCD)
+#ifndef NFR_MFMA_SPLITS
+#define NFR_MFMA_SPLITS 8
+#endif
+constexpr int kMfmaSplits = NFR_MFMA_SPLITS;   // one source chunk per XCD (workgroup id % 8 picks the XCD)
+// The BF16 split-W kernel streams W in half as many, longer chunks: at
+// N = 65536, B = 64 2.68 against 2.90 ms per application with 8 (2 chunks:
+// 2.59 ms), and the combine reads half the partial sums.  Each chunk is
+// summed in FP32 on the matrix cores, so longer chunks cost accuracy: FP16,
+// the accurate split (2e-6 of the absolute sum per application), keeps 8
+// (with 4 its full-size error reached 2.3e-6); the on-the-fly kernels, 1-2 %
+// slower with 4, keep 8 too.
+#ifndef NFR_MFMA_APPLY_SPLITS_BF16
+#define NFR_MFMA_APPLY_SPLITS_BF16 4
+#endif
 constexpr int kMfmaRowsPerWG = 128;   // 4 waves x 32 rows
 constexpr int kMfmaHeader = 256;
 
@@ -64,7 +77,12 @@ inline bool mfma_has_w(int form) { return form == 2 || form == 3; }
 inline bool mfma_is_bf16(int form) { return form == 2 || form == 4; }
 inline int64_t mfma_bp(int B) { return round_up(B, 64); }
 inline size_t mfma_g_bytes(int64_t npad, int B) { return size_t(2) * mfma_bp(B) * npad * 2; }
-inline int mfma_nsplit(int64_t, int64_t, int) { return kMfmaSplits; }
+// Source chunks of the split-W kernel for element type T (see above).
+template <typename T>
+__host__ __device__ constexpr int apply_splits() {
+  return MfmaTraits<T>::fp16 ? kMfmaSplits : NFR_MFMA_APPLY_SPLITS_BF16;
+}
+inline int mfma_nsplit(int form) { return form == 2 ? NFR_MFMA_APPLY_SPLITS_BF16 : kMfmaSplits; }   // 2: W_BF16X3
 inline size_t mfma_w_bytes(int64_t, int64_t npad) { return kMfmaHeader + size_t(2) * npad * npad * 2; }
 
 // Round-to-nearest-even conversions of a double through float.
@@ -180,8 +198,9 @@ __global__ __launch_bounds__(kWG) void k_mfma_prep(const double* __restrict__ u,
 }
 
 // Y partials on the matrix cores.
-// Workgroup w: source chunk split = w % kMfmaSplits, row block w / kMfmaSplits
-// (kMfmaRowsPerWG rows, 32 per wave); grid.y = state groups of 32*NB states.
+// Workgroup w: source chunk split = w % S, row block w / S, S =
+// apply_splits<T>() (kMfmaRowsPerWG rows, 32 per wave); grid.y = state
+// groups of 32*NB states.
 // Each wave runs over its source chunk kMfmaStep columns at a time.
 //
 // Operand placement: for MFMA step kb of a pipeline step, lane l = m + 32 h
@@ -226,8 +245,8 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_apply(const T* __restrict__ Wt,
   __shared__ __attribute__((aligned(16))) T sG[kApplyBufs][2][NS][kMfmaLdsStride];
 
   const int64_t wg = blockIdx.x;
-  const int split = (int)(wg % kMfmaSplits);
-  const int64_t rb = wg / kMfmaSplits;
+  const int split = (int)(wg % apply_splits<T>());
+  const int64_t rb = wg / apply_splits<T>();
   const int sg = blockIdx.y;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -852,8 +871,8 @@ inline void launch_mfma_apply_t(const ProblemView& pv, int B, const void* W, con
   MfmaBufs m = mfma_bufs(W, pv.npad);
   void *ghi, *glo;
   mfma_g_split(const_cast<void*>(g), pv.npad, B, &ghi, &glo);
-  const int64_t kchunk = round_up(ceil_div(pv.npad, kMfmaSplits), kMfmaStep);
-  const unsigned grid_x = (unsigned)(pv.npad / kMfmaRowsPerWG * kMfmaSplits);
+  const int64_t kchunk = round_up(ceil_div(pv.npad, apply_splits<T>()), kMfmaStep);
+  const unsigned grid_x = (unsigned)(pv.npad / kMfmaRowsPerWG * apply_splits<T>());
   if (B <= 32) {
     hipLaunchKernelGGL((k_mfma_apply<T, 1>), dim3(grid_x, 1), dim3(kWG), 0, s, static_cast<const T*>(m.tiles),
                        static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad, B, kchunk, m.header, part);

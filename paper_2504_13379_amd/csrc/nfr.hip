@@ -308,7 +308,7 @@ int nsplit_for(const ProblemView& pv, int B, int form) {
   if (use_sym(form, B, pv.npad)) return small_onesided(pv.npad) ? 1 : (int)sym_tiles(pv.npad);
   if (form == NFR_FORM_ONTHEFLY_FP32) return plan_otf(pv.npad, B).nsplit;
   if (form == NFR_FORM_W_FP32) return plan_gemv(pv.n, pv.npad, B).nsplit;
-  return mfma_nsplit(pv.n, pv.npad, B);
+  return mfma_nsplit(form);
 }
 
 struct Workspace {
