@@ -380,6 +380,13 @@ int nfr_tune_clear(void);
 
 /* ---------------------------------------------------------------- quadrature weights */
 
+/* Projection of a flat triangle's plane onto the surface (section 3.3). */
+enum nfr_projection {
+  NFR_PROJ_PLANES = 0,      /* central projection from the cutting planes' common point */
+  NFR_PROJ_ORIGIN = 1,      /* central projection from the origin (star-shaped surfaces) */
+  NFR_PROJ_ORTHOGONAL = 2   /* orthogonal projection along each triangle's normal */
+};
+
 /* Workspace bytes for nfr_quad_weights (0 if the sizes are unsupported). */
 size_t nfr_quad_workspace_size(int64_t n, int64_t ntri, int k);
 
@@ -390,12 +397,17 @@ size_t nfr_quad_workspace_size(int64_t n, int64_t ntri, int k);
  *     nearest to the centroid (a + b + c) / 3, ranked by the squared distance
  *     (dx dx + dy dy) + dz dz evaluated without fused multiply-add, ties by
  *     node index;
- *   - projection point p_j: the origin if star_shaped != 0 (every ray from
- *     the origin meets the surface once); otherwise the common point of the
- *     three cutting planes through E_j's edges, the plane of edge e containing
- *     that edge with normal n_j - n_j' (j' the neighbour across it);
- *     if that 3 x 3 system has condition number above 1e8 the triangle uses
- *     orthogonal projection onto its plane instead (a NaN row in proj_dev);
+ *   - projection point p_j, by `projection` (enum nfr_projection):
+ *     NFR_PROJ_ORIGIN: the origin (star-shaped surfaces: every ray from the
+ *     origin meets the surface once);
+ *     NFR_PROJ_PLANES: the common point of the three cutting planes through
+ *     E_j's edges, the plane of edge e containing that edge with normal
+ *     n_j - n_j' (j' the neighbour across it); if that 3 x 3 system has
+ *     condition number above 1e8 the triangle uses orthogonal projection
+ *     onto its plane instead (a NaN row in proj_dev);
+ *     NFR_PROJ_ORTHOGONAL: every triangle projects orthogonally onto its own
+ *     plane (p_j at infinity along n_j; a NaN row in proj_dev), with the
+ *     Jacobian 1 / |n(x) . n_j|;
  *   - the stencil is pulled back to E_j's plane along rays from p_j, planar
  *     RBF-QF with phi = r^3 and polynomials of degree <= 2 gives one weight
  *     per stencil node (a (k+6) x (k+6) saddle-point solve, LU with partial
@@ -404,14 +416,15 @@ size_t nfr_quad_workspace_size(int64_t n, int64_t ntri, int k);
  *     i's weights over all triangles in increasing (triangle, slot) order.
  * xyz_dev, nrm_dev: n x 3 FP64 row-major (device).  tri_host: ntri x 3 int32
  * (host; read during the call).  The triangulation must be closed and
- * consistently oriented when star_shaped == 0 (NFR_ERR_INVALID_ARG otherwise).
+ * consistently oriented for NFR_PROJ_PLANES (NFR_ERR_INVALID_ARG otherwise);
+ * any other `projection` value is NFR_ERR_INVALID_ARG.
  * 6 <= k <= 57, k <= n.  Outputs (device, caller-owned): q_dev (n FP64);
  * stencil_dev (ntri x k int32, may be NULL) receives the stencils; proj_dev
  * (ntri x 3 FP64, may be NULL) the projection points.  ws_dev: >=
  * nfr_quad_workspace_size bytes, 256-byte aligned.  Enqueued on the context
  * stream; the host triangle array may be reused when the call returns. */
 int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* nrm_dev, int64_t ntri,
-                     const int32_t* tri_host, int star_shaped, int k, double* q_dev, int32_t* stencil_dev,
+                     const int32_t* tri_host, int projection, int k, double* q_dev, int32_t* stencil_dev,
                      double* proj_dev, void* ws_dev, size_t ws_bytes);
 
 #ifdef __cplusplus

@@ -146,15 +146,22 @@ def monomial_integrals_deg2(v0, v1, v2):
 # -------------------------------------------------------------- projection
 
 
-def projection_points(surface, tris, cond_max: float = 1e8):
+def projection_points(surface, tris, cond_max: float = 1e8, projection: str = "auto"):
     """p_j for every triangle, or NaN rows meaning "at infinity along n_j".
 
-    Star-shaped surfaces: the origin.  Otherwise the intersection of the three
-    cutting planes {y : (n_j - n_j') . (y - a_e) = 0}, one per edge e shared
-    with neighbour j'; if those planes are nearly parallel (condition number
-    above cond_max) the triangle falls back to orthogonal projection.
+    projection="auto": star-shaped surfaces use the origin; other surfaces the
+    intersection of the three cutting planes {y : (n_j - n_j') . (y - a_e) = 0},
+    one per edge e shared with neighbour j'; if those planes are nearly
+    parallel (condition number above cond_max) the triangle falls back to
+    orthogonal projection.  projection="orthogonal": every triangle projects
+    orthogonally onto its own plane (section 3.3 allows p_j at infinity).
+    Returns (P, number of orthogonal rows).
     """
     m = tris.shape[0]
+    if projection == "orthogonal":
+        return np.full((m, 3), np.nan), m
+    if projection != "auto":
+        raise ValueError("projection must be 'auto' or 'orthogonal'")
     if surface.star_shaped:
         return np.zeros((m, 3)), 0
     x = surface.xyz
@@ -244,14 +251,74 @@ def stencils(xyz: np.ndarray, centres: np.ndarray, k: int) -> np.ndarray:
     return out
 
 
+def element_weights(x, nrm_x, a, b, c, P, st):
+    """Surface RBF-QF weights of a set of triangles E_j (section 3.3, eq. integral).
+
+    x, nrm_x: (N, 3) nodes and their exact unit normals; a, b, c: (m, 3)
+    vertices of each E_j, oriented outward; P: (m, 3) projection points (a NaN
+    row: orthogonal projection along n_j); st: (m, k) stencils.  For every
+    triangle the stencil is pulled back to the plane of E_j (along rays from
+    p_j, or along n_j), expressed in a 2-D frame centred at the centroid and
+    scaled by the stencil radius h_j, and the planar weights of eq.
+    functional_stencil are multiplied by h_j^2 and by the Jacobian J of the
+    map from E_j's plane to the surface at each stencil node:
+      central projection:    J = (|x - p| / |xi - p|)^2 |n_j . u| / |n(x) . u|,
+                             u = (x - p) / |x - p|;
+      orthogonal projection: J = 1 / |n(x) . n_j|.
+    Returns (m, k): the weight of stencil node r in triangle j.
+    """
+    cen = (a + b + c) / 3.0
+    nj = np.cross(b - a, c - a)
+    nj /= np.linalg.norm(nj, axis=1, keepdims=True)
+    xs = x[st]                                   # (m, k, 3)
+    ns = nrm_x[st]
+    nn = nj[:, None, :]
+    orth = np.isnan(P[:, 0])
+    # pre-images on the plane of E_j
+    xi = np.empty_like(xs)
+    J = np.empty(xs.shape[:2])
+    if np.any(~orth):
+        pp = P[~orth][:, None, :]
+        dxp = xs[~orth] - pp
+        num = np.sum(nn[~orth] * (a[~orth][:, None, :] - pp), axis=2)
+        den = np.sum(nn[~orth] * dxp, axis=2)
+        t = num / den
+        xi_c = pp + t[..., None] * dxp
+        xi[~orth] = xi_c
+        u = dxp / np.linalg.norm(dxp, axis=2, keepdims=True)
+        ratio = np.linalg.norm(dxp, axis=2) / np.linalg.norm(xi_c - pp, axis=2)
+        cos_plane = np.abs(np.sum(nn[~orth] * u, axis=2))
+        cos_surf = np.abs(np.sum(ns[~orth] * u, axis=2))
+        J[~orth] = ratio ** 2 * cos_plane / cos_surf
+    if np.any(orth):
+        h_off = np.sum(nn[orth] * (xs[orth] - a[orth][:, None, :]), axis=2)
+        xi[orth] = xs[orth] - h_off[..., None] * nn[orth]
+        cs = np.abs(np.sum(ns[orth] * nn[orth], axis=2))
+        J[orth] = 1.0 / cs
+    # local 2-D frame centred at the centroid, scaled by h_j
+    e1 = b - a
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(nj, e1)
+    rel = xi - cen[:, None, :]
+    h = np.max(np.linalg.norm(rel, axis=2), axis=1)
+    s2 = np.stack([np.sum(rel * e1[:, None, :], axis=2),
+                   np.sum(rel * e2[:, None, :], axis=2)], axis=2) / h[:, None, None]
+    verts = [np.stack([np.sum((v - cen) * e1, axis=1),
+                       np.sum((v - cen) * e2, axis=1)], axis=1) / h[:, None]
+             for v in (a, b, c)]
+    wplan = planar_element_weights(s2, verts[0], verts[1], verts[2])
+    return wplan * (h * h)[:, None] * J
+
+
 def surface_weights(surface, k: int = 32, deg: int = 2, chunk: int = 8192,
-                    return_info: bool = False):
+                    return_info: bool = False, projection: str = "auto"):
     """Surface RBF-QF weights q (length N) with phi(r) = r^3 and degree-deg polynomials.
 
     For every triangle E_j: pull the stencil S(E_j) back to the plane of E_j
-    along rays from p_j, scale by h_j about the centroid, solve
+    (along rays from p_j; with projection="orthogonal", or where the cutting
+    planes are singular, along n_j), scale by h_j about the centroid, solve
       [A  Pi; Pi^T 0] [w; gamma] = [int_E r^3 ; int_E pi]
-    and add w_r * h_j^2 * J_j(xi_r) to q at stencil node r.
+    and add w_r * h_j^2 * J_j(xi_r) to q at stencil node r (`element_weights`).
     """
     if deg != 2:
         raise ValueError("only deg = 2 is implemented")
@@ -262,63 +329,37 @@ def surface_weights(surface, k: int = 32, deg: int = 2, chunk: int = 8192,
     n = x.shape[0]
     tris = triangulate(surface)
     m = tris.shape[0]
-    P, n_orth = projection_points(surface, tris)
+    P, n_orth = projection_points(surface, tris, projection=projection)
     a, b, c = x[tris[:, 0]], x[tris[:, 1]], x[tris[:, 2]]
     cen = (a + b + c) / 3.0
-    nj = np.cross(b - a, c - a)
-    nj /= np.linalg.norm(nj, axis=1, keepdims=True)
     st = stencils(x, cen, k)
     q = np.zeros(n)
     min_cos = np.inf
     for lo in range(0, m, chunk):
-        hi = min(m, lo + chunk)
-        sl = slice(lo, hi)
-        xs = x[st[sl]]                                   # (c, k, 3)
-        ns = nrm_x[st[sl]]
-        nn = nj[sl][:, None, :]
-        p = P[sl]
-        orth = np.isnan(p[:, 0])
-        # pre-images on the plane of E_j
-        xi = np.empty_like(xs)
-        J = np.empty(xs.shape[:2])
-        if np.any(~orth):
-            pp = p[~orth][:, None, :]
-            dxp = xs[~orth] - pp
-            num = np.sum(nn[~orth] * (a[sl][~orth][:, None, :] - pp), axis=2)
-            den = np.sum(nn[~orth] * dxp, axis=2)
-            t = num / den
-            xi_c = pp + t[..., None] * dxp
-            xi[~orth] = xi_c
-            u = dxp / np.linalg.norm(dxp, axis=2, keepdims=True)
-            ratio = np.linalg.norm(dxp, axis=2) / np.linalg.norm(xi_c - pp, axis=2)
-            cos_plane = np.abs(np.sum(nn[~orth] * u, axis=2))
-            cos_surf = np.abs(np.sum(ns[~orth] * u, axis=2))
-            min_cos = min(min_cos, float(cos_surf.min()))
-            J[~orth] = ratio ** 2 * cos_plane / cos_surf
-        if np.any(orth):
-            h_off = np.sum(nn[orth] * (xs[orth] - a[sl][orth][:, None, :]), axis=2)
-            xi[orth] = xs[orth] - h_off[..., None] * nn[orth]
-            cs = np.abs(np.sum(ns[orth] * nn[orth], axis=2))
-            min_cos = min(min_cos, float(cs.min()))
-            J[orth] = 1.0 / cs
-        # local 2-D frame centred at the centroid, scaled by h_j
-        e1 = b[sl] - a[sl]
-        e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
-        e2 = np.cross(nj[sl], e1)
-        rel = xi - cen[sl][:, None, :]
-        h = np.max(np.linalg.norm(rel, axis=2), axis=1)
-        s2 = np.stack([np.sum(rel * e1[:, None, :], axis=2),
-                       np.sum(rel * e2[:, None, :], axis=2)], axis=2) / h[:, None, None]
-        verts = [np.stack([np.sum((v[sl] - cen[sl]) * e1, axis=1),
-                           np.sum((v[sl] - cen[sl]) * e2, axis=1)], axis=1) / h[:, None]
-                 for v in (a, b, c)]
-        wplan = planar_element_weights(s2, verts[0], verts[1], verts[2])
-        wE = wplan * (h * h)[:, None] * J
+        sl = slice(lo, min(m, lo + chunk))
+        wE = element_weights(x, nrm_x, a[sl], b[sl], c[sl], P[sl], st[sl])
         q += np.bincount(st[sl].ravel(), weights=wE.ravel(), minlength=n)
+        min_cos = min(min_cos, _min_cos(x, nrm_x, a[sl], b[sl], c[sl], P[sl], st[sl]))
     if return_info:
         return q, {"triangles": m, "orthogonal_fallbacks": n_orth, "min_cos": min_cos,
                    "tris": tris}
     return q
+
+
+def _min_cos(x, nrm_x, a, b, c, P, st):
+    """Smallest |n(x) . direction of projection| over the stencils (diagnostic)."""
+    nj = np.cross(b - a, c - a)
+    nj /= np.linalg.norm(nj, axis=1, keepdims=True)
+    xs, ns = x[st], nrm_x[st]
+    orth = np.isnan(P[:, 0])
+    out = np.inf
+    if np.any(~orth):
+        d = xs[~orth] - P[~orth][:, None, :]
+        d /= np.linalg.norm(d, axis=2, keepdims=True)
+        out = min(out, float(np.abs(np.sum(ns[~orth] * d, axis=2)).min()))
+    if np.any(orth):
+        out = min(out, float(np.abs(np.sum(ns[orth] * nj[orth][:, None, :], axis=2)).min()))
+    return out
 
 
 def plane_weights(xy: np.ndarray, k: int = 32, chunk: int = 8192, return_info: bool = False):

@@ -24,6 +24,10 @@ NFR_ERR_INTERNAL = -7
 GAUSS_MH = 0
 EXP_MH = 1
 
+PROJ_PLANES = 0
+PROJ_ORIGIN = 1
+PROJ_ORTHOGONAL = 2
+
 FORM_AUTO = -1
 FORM_ONTHEFLY_FP32 = 0
 FORM_W_FP32 = 1

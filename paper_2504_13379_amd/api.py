@@ -18,7 +18,14 @@ def _ptr(t) -> int | None:
     return None if t is None else t.data_ptr()
 
 
-def _dev_buffer(nbytes: int, device) -> torch.Tensor:
+def _dev_buffer(nbytes: int, device, stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """256-byte aligned device bytes.  With `stream`, the block is allocated while
+    that stream is current, so torch's caching allocator orders its reuse after
+    the work the library enqueues there (the library runs on the context's
+    stream, which need not be the caller's current stream)."""
+    if stream is not None:
+        with torch.cuda.stream(stream):
+            return _dev_buffer(nbytes, device)
     buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
     off = (-buf.data_ptr()) % 256
     return buf[off:off + max(int(nbytes), 1)]
@@ -59,6 +66,15 @@ class Context:
         L.check(L.lib().nfr_context_create(device, c_void_p(self.stream.cuda_stream), byref(h)))
         self.handle = h
 
+    def order_after_caller(self) -> None:
+        """Makes the context's stream wait for the caller's current stream, so that
+        inputs the caller produced (or copied with .to()/.contiguous()) are complete
+        before the library reads them.  Results are complete on `self.stream`;
+        a caller on another stream waits for it before reading them."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
     @property
     def arch(self) -> str:
         return L.lib().nfr_context_arch(self.handle).decode()
@@ -89,8 +105,9 @@ class Problem:
         nbytes = L.lib().nfr_problem_bytes(self.n)
         if nbytes == 0:
             raise ValueError("unsupported problem size %d" % self.n)
-        self.pack = _dev_buffer(nbytes, ctx.device)
+        self.pack = _dev_buffer(nbytes, ctx.device, ctx.stream)
         h = c_void_p()
+        ctx.order_after_caller()
         with torch.cuda.stream(ctx.stream):
             L.check(L.lib().nfr_problem_create_periodic(ctx.handle, self.n, xyz.data_ptr(), q.data_ptr(),
                                                         float(period), self.pack.data_ptr(), nbytes, byref(h)))
@@ -116,7 +133,8 @@ class Problem:
         nbytes = L.lib().nfr_w_bytes(self.n, form)
         if nbytes == 0:
             raise ValueError("form %d has no W matrix" % form)
-        W = _dev_buffer(nbytes, self.ctx.device)
+        W = _dev_buffer(nbytes, self.ctx.device, self.ctx.stream)
+        self.ctx.order_after_caller()
         L.check(L.lib().nfr_w_build(self.handle, byref(kernel), form, W.data_ptr(), nbytes))
         return W
 
@@ -132,10 +150,14 @@ class Problem:
     def apply(self, kernel: L.NfrKernel, firing: Firing, u: torch.Tensor, form: int = L.FORM_ONTHEFLY_FP32,
               W: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
         B = self._check_state(u)
-        y = torch.empty_like(u) if out is None else out
+        if out is None:
+            with torch.cuda.stream(self.ctx.stream):
+                out = torch.empty_like(u)
+        y = out
         ws_bytes = L.lib().nfr_apply_workspace_size(self.handle, B, form)
-        ws = _dev_buffer(ws_bytes, self.ctx.device)
+        ws = _dev_buffer(ws_bytes, self.ctx.device, self.ctx.stream)
         fs = firing.struct(self.ctx.device)
+        self.ctx.order_after_caller()
         L.check(L.lib().nfr_apply(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), y.data_ptr(), form,
                                   _ptr(W), ws.data_ptr(), ws_bytes))
         self._last_ws = ws
@@ -148,11 +170,13 @@ class Problem:
         B = self._check_state(u)
         ws_bytes = L.lib().nfr_integrate_workspace_size(self.handle, B, form)
         if ws is None or ws.numel() < ws_bytes:
-            ws = _dev_buffer(ws_bytes, self.ctx.device)
+            ws = _dev_buffer(ws_bytes, self.ctx.device, self.ctx.stream)
         ck = None
         if ckpt_every:
-            ck = torch.empty((1 + steps // ckpt_every, B, self.n), dtype=torch.float64, device=self.ctx.device)
+            with torch.cuda.stream(self.ctx.stream):
+                ck = torch.empty((1 + steps // ckpt_every, B, self.n), dtype=torch.float64, device=self.ctx.device)
         fs = firing.struct(self.ctx.device)
+        self.ctx.order_after_caller()
         L.check(L.lib().nfr_integrate(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), float(dt), int(steps),
                                       form, _ptr(W), _ptr(ck), int(ckpt_every), int(bool(use_graph)),
                                       ws.data_ptr(), ws_bytes))
@@ -167,8 +191,9 @@ class Problem:
             raise ValueError("forcing must be a (steps, 3, B, N) float64 tensor")
         forcing = forcing.to(self.ctx.device).contiguous()
         ws_bytes = L.lib().nfr_integrate_workspace_size(self.handle, B, form)
-        ws = _dev_buffer(ws_bytes, self.ctx.device)
+        ws = _dev_buffer(ws_bytes, self.ctx.device, self.ctx.stream)
         fs = firing.struct(self.ctx.device)
+        self.ctx.order_after_caller()
         L.check(L.lib().nfr_integrate_forced(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), float(dt),
                                              int(steps), forcing.data_ptr(), form, _ptr(W), ws.data_ptr(), ws_bytes))
         self._last_ws = (ws, forcing)
@@ -179,8 +204,9 @@ class Problem:
         B = self._check_state(u)
         ws_bytes = L.lib().nfr_integrate_ab5_workspace_size(self.handle, B, form)
         if ws is None or ws.numel() < ws_bytes:
-            ws = _dev_buffer(ws_bytes, self.ctx.device)
+            ws = _dev_buffer(ws_bytes, self.ctx.device, self.ctx.stream)
         fs = firing.struct(self.ctx.device)
+        self.ctx.order_after_caller()
         L.check(L.lib().nfr_integrate_ab5(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), float(dt),
                                           int(steps), form, _ptr(W), ws.data_ptr(), ws_bytes))
         self._last_ws = ws
@@ -193,8 +219,9 @@ class Problem:
             raise ValueError("u and a must have the same shape")
         ws_bytes = L.lib().nfr_integrate_syndep_workspace_size(self.handle, B)
         if ws is None or ws.numel() < ws_bytes:
-            ws = _dev_buffer(ws_bytes, self.ctx.device)
+            ws = _dev_buffer(ws_bytes, self.ctx.device, self.ctx.stream)
         fs = firing.struct(self.ctx.device)
+        self.ctx.order_after_caller()
         L.check(L.lib().nfr_integrate_syndep(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), a.data_ptr(),
                                              float(tau), float(beta_d), float(dt), int(steps), ws.data_ptr(),
                                              ws_bytes))
@@ -211,17 +238,19 @@ class Problem:
         if ckpt.numel() < need * self.n:
             raise ValueError("ckpt holds %d states, %d needed" % (ckpt.numel() // self.n, need))
         ws_bytes = L.lib().nfr_adjoint_workspace_size(self.handle, int(steps), int(ckpt_every))
-        ws = _dev_buffer(ws_bytes, self.ctx.device)
-        ubar0 = torch.empty(self.n, dtype=torch.float64, device=self.ctx.device)
+        ws = _dev_buffer(ws_bytes, self.ctx.device, self.ctx.stream)
+        with torch.cuda.stream(self.ctx.stream):
+            ubar0 = torch.empty(self.n, dtype=torch.float64, device=self.ctx.device)
         pbar = (c_double * 5)()
         fs = firing.struct(self.ctx.device)
+        self.ctx.order_after_caller()
         L.check(L.lib().nfr_adjoint(self.handle, byref(kernel), byref(fs), ckpt.data_ptr(), int(ckpt_every),
                                     int(steps), float(dt), ubarT.data_ptr(), ubar0.data_ptr(), pbar,
                                     ws.data_ptr(), ws_bytes))
         return ubar0, torch.tensor(list(pbar), dtype=torch.float64)
 
     def integrate_workspace(self, B: int, form: int) -> torch.Tensor:
-        return _dev_buffer(L.lib().nfr_integrate_workspace_size(self.handle, B, form), self.ctx.device)
+        return _dev_buffer(L.lib().nfr_integrate_workspace_size(self.handle, B, form), self.ctx.device, self.ctx.stream)
 
 
 class Batch:
@@ -251,7 +280,7 @@ class Batch:
         return (c_void_p * len(states))(*[u.data_ptr() for u in states])
 
     def workspace(self) -> torch.Tensor:
-        return _dev_buffer(L.lib().nfr_batch_workspace_size(self.handle), self.ctx.device)
+        return _dev_buffer(L.lib().nfr_batch_workspace_size(self.handle), self.ctx.device, self.ctx.stream)
 
     @property
     def config(self):
@@ -266,12 +295,14 @@ class Batch:
     def tune(self, states, ws: torch.Tensor | None = None) -> float:
         ws = self.workspace() if ws is None else ws
         best = c_double()
+        self.ctx.order_after_caller()
         L.check(L.lib().nfr_batch_tune(self.handle, self._states(states), ws.data_ptr(), ws.numel(), byref(best)))
         return best.value
 
     def integrate(self, states, dt: float, steps: int, use_graph: bool = False, ws: torch.Tensor | None = None):
         ptrs = self._states(states)
         ws = self.workspace() if ws is None else ws
+        self.ctx.order_after_caller()
         L.check(L.lib().nfr_batch_integrate(self.handle, ptrs, float(dt), int(steps), int(bool(use_graph)),
                                             ws.data_ptr(), ws.numel()))
 
@@ -292,7 +323,7 @@ def tune(ctx: Context, cache_path: str | None = None, n_max: int = 65536, B_max:
     ws_bytes = L.lib().nfr_tune_workspace_size(int(n_max), int(B_max))
     if ws_bytes == 0:
         raise ValueError("unsupported tuning sizes n_max=%d, B_max=%d" % (n_max, B_max))
-    ws = _dev_buffer(ws_bytes, ctx.device)
+    ws = _dev_buffer(ws_bytes, ctx.device, ctx.stream)
     path = cache_path.encode() if cache_path else None
     L.check(L.lib().nfr_tune(ctx.handle, path, int(n_max), int(B_max), ws.data_ptr(), ws_bytes))
 
@@ -301,12 +332,14 @@ def tune_load(cache_path: str) -> None:
     L.check(L.lib().nfr_tune_load(cache_path.encode()))
 
 
-def quad_weights(ctx: Context, xyz: torch.Tensor, normals: torch.Tensor, tris, star_shaped: bool, k: int = 32,
+def quad_weights(ctx: Context, xyz: torch.Tensor, normals: torch.Tensor, tris, projection, k: int = 32,
                  details: bool = False):
     """Surface quadrature weights q (N,) float64 on the GPU (nfr_quad_weights).
 
     xyz, normals: (N, 3) float64 (moved to the context's device); tris: (M, 3)
-    integer array-like (host), oriented outward.  With details=True also
+    integer array-like (host), oriented outward.  projection: L.PROJ_PLANES,
+    L.PROJ_ORIGIN or L.PROJ_ORTHOGONAL (a bool is read as "star-shaped":
+    True -> PROJ_ORIGIN, False -> PROJ_PLANES).  With details=True also
     returns the stencils (M, k) int32 and projection points (M, 3) float64.
     """
     import numpy as np
@@ -319,13 +352,14 @@ def quad_weights(ctx: Context, xyz: torch.Tensor, normals: torch.Tensor, tris, s
     ws_bytes = L.lib().nfr_quad_workspace_size(n, m, k)
     if ws_bytes == 0:
         raise ValueError("unsupported sizes n=%d, triangles=%d, k=%d" % (n, m, k))
-    ws = _dev_buffer(ws_bytes, ctx.device)
-    q = torch.empty(n, dtype=torch.float64, device=ctx.device)
-    st = torch.empty((m, k), dtype=torch.int32, device=ctx.device) if details else None
-    pj = torch.empty((m, 3), dtype=torch.float64, device=ctx.device) if details else None
+    ws = _dev_buffer(ws_bytes, ctx.device, ctx.stream)
+    ctx.order_after_caller()
     with torch.cuda.stream(ctx.stream):
+        q = torch.empty(n, dtype=torch.float64, device=ctx.device)
+        st = torch.empty((m, k), dtype=torch.int32, device=ctx.device) if details else None
+        pj = torch.empty((m, 3), dtype=torch.float64, device=ctx.device) if details else None
         L.check(L.lib().nfr_quad_weights(ctx.handle, n, xyz.data_ptr(), normals.data_ptr(), m,
-                                         tri.ctypes.data_as(c_void_p), int(bool(star_shaped)), int(k),
+                                         tri.ctypes.data_as(c_void_p), int(projection), int(k),
                                          q.data_ptr(), _ptr(st), _ptr(pj), ws.data_ptr(), ws_bytes))
     if details:
         return q, st, pj

@@ -276,7 +276,8 @@ __device__ inline double cond3(const double m[3][3]) {
 }
 
 // p_j for every triangle (written to proj[3*t]; a NaN row means "orthogonal
-// projection onto E_j's plane").  star != 0: p_j = 0.  Otherwise row e of the
+// projection onto E_j's plane").  mode 1 (origin): p_j = 0; mode 2
+// (orthogonal): a NaN row for every triangle.  Mode 0 (planes): row e of the
 // 3 x 3 system is the unit normal of the cutting plane through edge e
 // (vertex e to vertex e+1), n_j - n_{neighbour across e} normalised, with
 // right-hand side its product with (vertex e - c_j); p_j = c_j + solution.
@@ -284,12 +285,17 @@ __device__ inline double cond3(const double m[3][3]) {
 // to orthogonal projection.
 __global__ __launch_bounds__(kWG) void k_quad_proj(const double* __restrict__ xyz, const int* __restrict__ tri,
                                                    const int* __restrict__ nbr, const double* __restrict__ cen,
-                                                   const double* __restrict__ nrm_tri, int64_t ntri, int star,
+                                                   const double* __restrict__ nrm_tri, int64_t ntri, int mode,
                                                    double cond_max, double* __restrict__ proj) {
   const int64_t t = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (t >= ntri) return;
-  if (star) {
+  if (mode == 1) {
     proj[3 * t] = proj[3 * t + 1] = proj[3 * t + 2] = 0.0;
+    return;
+  }
+  if (mode == 2) {
+    const double nan = __builtin_nan("");
+    proj[3 * t] = proj[3 * t + 1] = proj[3 * t + 2] = nan;
     return;
   }
   double m[3][3], rhs[3];

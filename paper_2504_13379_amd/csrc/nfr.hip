@@ -304,19 +304,28 @@ bool use_sym(int form, int B, int64_t npad) {
 // the W forms hold f(u) (q sits in W).
 bool sources_carry_q(int form) { return form == NFR_FORM_ONTHEFLY_FP32 || form == NFR_FORM_ONTHEFLY_FP32_MFMA; }
 
-int nsplit_for(const ProblemView& pv, int B, int form) {
+// Partial-sum slots per node of one pair launch; `otf` is the plan of the
+// multi-state on-the-fly FP32 sum (the only plan that reads the tune table).
+int nsplit_of(const ProblemView& pv, int B, int form, const OtfPlan& otf) {
   if (use_sym(form, B, pv.npad)) return small_onesided(pv.npad) ? 1 : (int)sym_tiles(pv.npad);
-  if (form == NFR_FORM_ONTHEFLY_FP32) return plan_otf(pv.npad, B).nsplit;
+  if (form == NFR_FORM_ONTHEFLY_FP32) return otf.nsplit;
   if (form == NFR_FORM_W_FP32) return plan_gemv(pv.n, pv.npad, B).nsplit;
   return mfma_nsplit(form);
 }
 
+// A carved workspace also fixes the launch plan of the call that carved it:
+// the tune table is read once, in carve(), and every pair launch and combine
+// of that call uses `otf` and `nsplit` from here, so a concurrent nfr_tune*
+// on another thread cannot change the slot count between the launch that
+// writes the partial sums and the combine that adds them.
 struct Workspace {
   float* g = nullptr;
   float* g2 = nullptr;         // second source buffer of the one-launch small stage (null: two launches)
   double* part = nullptr;
   double* v = nullptr;
   double* ksum = nullptr;
+  OtfPlan otf;                 // multi-state on-the-fly FP32 plan (unused by other forms)
+  int nsplit = 1;              // partial-sum slots per node and state in `part`
   size_t bytes = 0;
 };
 
@@ -337,9 +346,11 @@ Workspace carve(void* base, const ProblemView& pv, int B, int form, bool steppin
     off += align256(bytes);
     return r;
   };
+  if (form == NFR_FORM_ONTHEFLY_FP32 && !use_sym(form, B, pv.npad)) w.otf = plan_otf(pv.npad, B);
+  w.nsplit = nsplit_of(pv, B, form, w.otf);
   const size_t gbytes = is_mfma_form(form) ? mfma_g_bytes(pv.npad, B) : size_t(pv.npad) * B * sizeof(float);
   w.g = reinterpret_cast<float*>(take(gbytes));
-  w.part = reinterpret_cast<double*>(take(size_t(nsplit_for(pv, B, form)) * B * pv.npad * sizeof(double)));
+  w.part = reinterpret_cast<double*>(take(size_t(w.nsplit) * B * pv.npad * sizeof(double)));
   if (stepping) {
     w.v = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
     w.ksum = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
@@ -421,7 +432,7 @@ int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k_in, int form, in
     }
 #undef NFR_SYM_CASE
   } else if (form == NFR_FORM_ONTHEFLY_FP32) {
-    const OtfPlan pl = plan_otf(pv.npad, B);
+    const OtfPlan& pl = w.otf;
     const PairParams pp = pair_params(k, pv);
     switch (kind_code(k, pv)) {
       case 0: launch_otf_kind<0>(pv, pp, B, w.g, w.part, pl, s); break;
@@ -488,7 +499,7 @@ int slot_lanes(int nsplit) { return nsplit <= 4 ? 1 : (nsplit <= 16 ? 4 : (nspli
 
 int launch_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, const Workspace& w,
                    const Firing& fr, hipStream_t s, double* k1_out = nullptr, const double* gamma = nullptr) {
-  const int nsplit = nsplit_for(pv, B, form);
+  const int nsplit = w.nsplit;
   const int64_t total = pv.n * (int64_t)B;
   if (is_mfma_form(form)) {
     launch_mfma_combine(pv, form, B, stage, dt, u, w.v, w.ksum, w.part, nsplit, fr, w.g, k1_out, gamma, s);
@@ -539,7 +550,7 @@ int launch_ab5(const ProblemView& pv, int form, int B, int64_t n_step, double dt
   auto slot = [&](int64_t m) { return (int)(m % 5); };
   const int4 s03 = make_int4(slot(n_step), slot(n_step - 1), slot(n_step - 2), slot(n_step - 3));
   const int s4 = slot(n_step - 4);
-  const int nsplit = nsplit_for(pv, B, form);
+  const int nsplit = w.nsplit;
   const int64_t total = pv.n * (int64_t)B;
   if (is_mfma_form(form)) {
     launch_mfma_ab5(pv, form, B, dt, wt, s03, s4, u, hist, w.part, nsplit, fr, w.g, s);
@@ -820,7 +831,7 @@ int nfr_apply(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* fir
   const Firing fr = firing_of(*firing);
   if ((st = launch_prep(pv, form, B, u_dev, fr, w, nullptr, s))) return st;
   if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return st;
-  const int nsplit = nsplit_for(pv, B, form);
+  const int nsplit = w.nsplit;
   const int64_t total = pv.n * (int64_t)B;
   if (is_mfma_form(form))
     launch_mfma_reduce(pv, form, B, w.part, nsplit, y_dev, s);
@@ -1545,7 +1556,7 @@ int nfr_integrate_syndep(nfr_problem* prob, const nfr_kernel* kernel, const nfr_
   hipLaunchKernelGGL(k_syndep_prep, dim3((unsigned)ceil_div(pv.npad * (int64_t)B, kWG)), dim3(kWG), 0, s, u_dev, a_dev,
                      pv.n, pv.npad, B, pv.q, fr, w.g, w.v, va);
   NFR_HIP_LAUNCH();
-  const int nsplit = nsplit_for(pv, B, form);
+  const int nsplit = w.nsplit;
   const int64_t total = pv.n * (int64_t)B;
   for (int64_t n = 0; n < steps; ++n) {
     for (int stage = 1; stage <= 4; ++stage) {
@@ -1711,9 +1722,12 @@ size_t nfr_quad_workspace_size(int64_t n, int64_t ntri, int k) {
 }
 
 int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* nrm_dev, int64_t ntri,
-                     const int32_t* tri_host, int star_shaped, int k, double* q_dev, int32_t* stencil_dev,
+                     const int32_t* tri_host, int projection, int k, double* q_dev, int32_t* stencil_dev,
                      double* proj_dev, void* ws_dev, size_t ws_bytes) {
   if (!xyz_dev || !nrm_dev || !tri_host || !q_dev) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
+  if (projection != NFR_PROJ_PLANES && projection != NFR_PROJ_ORIGIN && projection != NFR_PROJ_ORTHOGONAL)
+    return fail(NFR_ERR_INVALID_ARG, "unknown projection %d", projection);
+  const bool planes = projection == NFR_PROJ_PLANES;
   if (!quad_sizes_ok(n, ntri, k))
     return fail(NFR_ERR_INVALID_ARG, "sizes n = %lld, ntri = %lld, k = %d outside the supported range (6 <= k <= %d, k <= n)",
                 (long long)n, (long long)ntri, k, kQuadMaxK);
@@ -1727,7 +1741,7 @@ int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const d
   }
   std::vector<int> nbr;
   int st;
-  if (!star_shaped && (st = quad_neighbours(tri_host, ntri, n, nbr))) return st;
+  if (planes && (st = quad_neighbours(tri_host, ntri, n, nbr))) return st;
   if (!ctx) return fail(NFR_ERR_INVALID_ARG, "context is NULL");
   const QuadWorkspace w = carve_quad(ws_dev, n, ntri, k);
   if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
@@ -1738,7 +1752,7 @@ int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const d
   double* proj = proj_dev ? proj_dev : w.proj;
   const size_t tk = size_t(ntri) * k;
   NFR_HIP(hipMemcpyAsync(w.tri, tri_host, 3 * size_t(ntri) * sizeof(int), hipMemcpyHostToDevice, s));
-  if (!star_shaped)
+  if (planes)
     NFR_HIP(hipMemcpyAsync(w.nbr, nbr.data(), 3 * size_t(ntri) * sizeof(int), hipMemcpyHostToDevice, s));
   NFR_HIP(hipMemsetAsync(w.cnt, 0, size_t(n) * sizeof(int), s));
   NFR_HIP(hipMemsetAsync(w.cursor, 0, size_t(n) * sizeof(int), s));
@@ -1748,7 +1762,7 @@ int nfr_quad_weights(nfr_context* ctx, int64_t n, const double* xyz_dev, const d
   const unsigned tb = (unsigned)ceil_div(ntri, kWG);
   hipLaunchKernelGGL(k_quad_centroids, dim3(tb), dim3(kWG), 0, s, xyz_dev, w.tri, ntri, w.cen, w.nrm_tri);
   hipLaunchKernelGGL(k_quad_proj, dim3(tb), dim3(kWG), 0, s, xyz_dev, w.tri, w.nbr, w.cen, w.nrm_tri, ntri,
-                     star_shaped ? 1 : 0, 1e8, proj);
+                     projection, 1e8, proj);
   // k nearest nodes: bin the nodes into a grid, then search rings of cells
   const unsigned nbn = (unsigned)ceil_div(n, kWG);
   const int64_t nbc = ceil_div(mc, kWG);

@@ -78,3 +78,71 @@ def ellipsoid_area_numeric(a, b, c, n=400):
     xp = np.stack([-a * st * np.sin(Pp), b * st * np.cos(Pp), np.zeros_like(T)], -1)
     dA = np.linalg.norm(np.cross(xt, xp), axis=-1)
     return float(np.sum(dA * wt[:, None]) * (2 * np.pi / (2 * n)))
+
+
+def implicit_surface(kind: str, params: dict):
+    """Level-set function F (F = 0 on the surface) and its gradient, for the
+    ellipsoid sum (x_i / a_i)^2 = 1 and the torus (sqrt(x^2 + y^2) - R)^2 + z^2 = r^2."""
+    if kind in ("sphere", "ellipsoid"):
+        ax = np.asarray(params.get("axes", (1.0, 1.0, 1.0)), dtype=np.float64)
+
+        def F(x):
+            return np.sum((x / ax) ** 2, axis=-1) - 1.0
+
+        def G(x):
+            return 2.0 * x / ax ** 2
+        return F, G
+    if kind == "torus":
+        R, r = params["R"], params["r"]
+
+        def F(x):
+            rho = np.sqrt(x[..., 0] ** 2 + x[..., 1] ** 2)
+            return (rho - R) ** 2 + x[..., 2] ** 2 - r * r
+
+        def G(x):
+            rho = np.sqrt(x[..., 0] ** 2 + x[..., 1] ** 2)
+            k = 2.0 * (rho - R) / rho
+            return np.stack([k * x[..., 0], k * x[..., 1], 2.0 * x[..., 2]], axis=-1)
+        return F, G
+    raise ValueError(kind)
+
+
+def patch_integral(fun, F, G, a, b, c, p=None, n=24, h=1e-5):
+    """Integral of fun(x) dA over the curved patch that a projection maps onto
+    the flat triangle (a, b, c), from the definition of the area element.
+
+    A point s of the triangle's plane (2-D coordinates in the frame e1 = b - a,
+    e2 = n x e1) is carried to the surface along the line through it with
+    direction n (p None: orthogonal projection) or s - p (central projection
+    from p); the surface point x(s) is the root of F on that line nearest to
+    s (Newton).  dA = |dx/ds1 x dx/ds2| ds1 ds2 with the derivatives taken by
+    central differences of step h, and the plane integral is a Duffy
+    Gauss-Legendre rule (`triangle_integral`).
+    """
+    nj = np.cross(b - a, c - a)
+    nj = nj / np.linalg.norm(nj)
+    e1 = (b - a) / np.linalg.norm(b - a)
+    e2 = np.cross(nj, e1)
+
+    def on_plane(s):
+        return a + s[..., 0:1] * e1 + s[..., 1:2] * e2
+
+    def X(s):
+        xi = on_plane(s)
+        d = np.broadcast_to(nj, xi.shape) if p is None else xi - p
+        t = np.zeros(xi.shape[:-1])
+        for _ in range(30):
+            x = xi + t[..., None] * d
+            t = t - F(x) / np.sum(G(x) * d, axis=-1)
+        return xi + t[..., None] * d
+
+    def integrand(s):
+        d1 = np.array([h, 0.0])
+        d2 = np.array([0.0, h])
+        x1 = (X(s + d1) - X(s - d1)) / (2 * h)
+        x2 = (X(s + d2) - X(s - d2)) / (2 * h)
+        return fun(X(s)) * np.linalg.norm(np.cross(x1, x2), axis=-1)
+
+    def to2(v):
+        return np.array([np.dot(v - a, e1), np.dot(v - a, e2)])
+    return triangle_integral(integrand, to2(a), to2(b), to2(c), n=n)

@@ -128,6 +128,10 @@ def test_quadrature_host_validation(L):
     assert call(tet, 0, k=9) == _lib.NFR_ERR_INVALID_ARG and b"sizes" in L.nfr_last_error()
     assert call(tet, 0) == _lib.NFR_ERR_INVALID_ARG and b"context" in L.nfr_last_error()
     assert call(tet[:3], 1) == _lib.NFR_ERR_INVALID_ARG and b"context" in L.nfr_last_error()
+    # orthogonal projection needs no neighbours: an open mesh passes the host checks
+    assert call(tet[:3], _lib.PROJ_ORTHOGONAL) == _lib.NFR_ERR_INVALID_ARG and b"context" in L.nfr_last_error()
+    assert call(tet, 3) == _lib.NFR_ERR_INVALID_ARG and b"projection" in L.nfr_last_error()
+    assert call(tet, -1) == _lib.NFR_ERR_INVALID_ARG and b"projection" in L.nfr_last_error()
 
 
 def test_tuning_cache_load_query_clear(L, tmp_path):

@@ -72,3 +72,27 @@ def test_quad_weights_full_size_ellipsoid(ctx):
     q_ref = Q.surface_weights(surf, k=32)
     assert np.max(np.abs(q - q_ref)) / np.max(np.abs(q_ref)) <= TOL
     assert abs(q.sum() - C.surface_area(surf)) <= 1e-6 * C.surface_area(surf)
+
+
+@pytest.mark.parametrize("kind,n", [("torus", 3000), ("ellipsoid", 2500), ("sphere", 1500)])
+def test_quad_weights_orthogonal_projection_match_oracle(ctx, kind, n):
+    """Every triangle projected orthogonally along its normal (p_j at infinity,
+    Jacobian 1 / |n(x) . n_j|): the branch the cutting-plane path takes only
+    for singular systems, forced for all triangles on both sides."""
+    surf = S.make_surface(kind, n, np.random.default_rng(n))
+    tris = meshes.triangulate(surf)
+    q, st, pj = P.quad_weights(ctx, torch.from_numpy(surf.xyz), torch.from_numpy(surf.normals), tris,
+                               P.PROJ_ORTHOGONAL, 32, details=True)
+    torch.cuda.synchronize()
+    q, pj = q.cpu().numpy(), pj.cpu().numpy()
+    assert np.all(np.isnan(pj))
+    q_ref, info = Q.surface_weights(surf, k=32, projection="orthogonal", return_info=True)
+    assert info["orthogonal_fallbacks"] == tris.shape[0]
+    err = np.max(np.abs(q - q_ref)) / np.max(np.abs(q_ref))
+    assert err <= TOL, err
+
+
+def test_quad_weights_rejects_unknown_projection(ctx):
+    surf = S.sphere(200)
+    with pytest.raises(P.NfrError):
+        P.quad_weights(ctx, torch.from_numpy(surf.xyz), torch.from_numpy(surf.normals), meshes.triangulate(surf), 3)
