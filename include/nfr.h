@@ -244,6 +244,22 @@ int nfr_apply(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* fir
               const double* u_dev, double* y_dev, int form, const void* w_dev,
               void* ws_dev, size_t ws_bytes);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): nfr_apply without a
+ * workspace.  Same arguments, kernels and results as nfr_apply (bit for bit);
+ * its scratch (the sources g and the partial sums) lives in a fixed device
+ * array of NFR_APPLY_NOALLOC_MAX_BYTES inside the library, one per GPU,
+ * held until the process ends.  An application whose
+ * nfr_apply_workspace_size exceeds that size fails with NFR_ERR_WORKSPACE
+ * before anything is enqueued.  The call allocates nothing (no hipMalloc, no
+ * library allocation).  Every call on one GPU shares that GPU's array and the
+ * kernels overwrite every scratch byte they read (nothing needs clearing), so
+ * calls whose work overlaps on one GPU (other streams, other threads, other
+ * contexts on the same device) race: serialise them. */
+#define NFR_APPLY_NOALLOC_MAX_BYTES (64u << 20)
+int nfr_apply_noalloc(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B,
+                      const double* u_dev, double* y_dev, int form, const void* w_dev);
+
 /* ---------------------------------------------------------------- time stepping */
 
 size_t nfr_integrate_workspace_size(const nfr_problem* prob, int B, int form);

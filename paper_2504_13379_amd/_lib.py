@@ -24,6 +24,8 @@ NFR_ERR_INTERNAL = -7
 GAUSS_MH = 0
 EXP_MH = 1
 
+NFR_APPLY_NOALLOC_MAX_BYTES = 64 << 20   # fixed scratch of nfr_apply_noalloc (include/nfr.h)
+
 PROJ_PLANES = 0
 PROJ_ORIGIN = 1
 PROJ_ORTHOGONAL = 2
@@ -85,6 +87,7 @@ def _declare(lib):
         "nfr_w_build": (c_int, [P, POINTER(NfrKernel), c_int, P, c_size_t]),
         "nfr_apply_workspace_size": (c_size_t, [P, c_int, c_int]),
         "nfr_apply": (c_int, [P, POINTER(NfrKernel), POINTER(NfrFiring), c_int, P, P, c_int, P, P, c_size_t]),
+        "nfr_apply_noalloc": (c_int, [P, POINTER(NfrKernel), POINTER(NfrFiring), c_int, P, P, c_int, P]),
         "nfr_integrate_workspace_size": (c_size_t, [P, c_int, c_int]),
         "nfr_integrate": (c_int, [P, POINTER(NfrKernel), POINTER(NfrFiring), c_int, P, c_double, c_int64, c_int, P,
                                   P, c_int64, c_int, P, c_size_t]),

@@ -163,6 +163,19 @@ class Problem:
         self._last_ws = ws
         return y
 
+    def apply_noalloc(self, kernel: L.NfrKernel, firing: Firing, u: torch.Tensor, out: torch.Tensor,
+                      form: int = L.FORM_ONTHEFLY_FP32, W: torch.Tensor | None = None) -> torch.Tensor:
+        """nfr_apply_noalloc: the operator into the caller's `out` with the library's
+        fixed device scratch (no allocation by the library or by this method)."""
+        B = self._check_state(u)
+        if out.shape != u.shape or out.dtype != torch.float64 or not out.is_contiguous() or out.device != u.device:
+            raise ValueError("out must be a contiguous float64 tensor shaped like u, on its device")
+        fs = firing.struct(self.ctx.device)
+        self.ctx.order_after_caller()
+        L.check(L.lib().nfr_apply_noalloc(self.handle, byref(kernel), byref(fs), B, u.data_ptr(), out.data_ptr(),
+                                          form, _ptr(W)))
+        return out
+
     def integrate(self, kernel: L.NfrKernel, firing: Firing, u: torch.Tensor, dt: float, steps: int,
                   form: int = L.FORM_ONTHEFLY_FP32, W: torch.Tensor | None = None, ckpt_every: int = 0,
                   use_graph: bool = False, ws: torch.Tensor | None = None):

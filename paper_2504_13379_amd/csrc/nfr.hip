@@ -164,6 +164,42 @@ Firing firing_of(const nfr_firing& f) { return Firing{f.beta, f.theta, f.theta_d
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// ---------------------------------------------------------------- fixed scratch
+
+// Device memory of nfr_apply_noalloc: one file-scope array that every GPU the
+// library runs on holds (its own copy) until the process ends.  Host code
+// never passes the array's name to a kernel or a copy (on the host it is a
+// stand-in, not a device address); it uses the address hipGetSymbolAddress
+// returns for the device, taken once per device by nfr_context_create.
+constexpr size_t kScratchBytes = NFR_APPLY_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // by device ordinal; null until a context is created there
+
+// Takes the scratch array's device address for `device` (once), with that
+// device current; the caller's current device is restored.
+int scratch_init(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((size_t)device < g_scratch_ptr.size() && g_scratch_ptr[(size_t)device]) return NFR_OK;
+  int prev = 0;
+  NFR_HIP(hipGetDevice(&prev));
+  NFR_HIP(hipSetDevice(device));
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  NFR_HIP(hipSetDevice(prev));
+  if (e != hipSuccess) return fail(NFR_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  if (!p) return fail(NFR_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+  if (g_scratch_ptr.size() <= (size_t)device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+  g_scratch_ptr[(size_t)device] = p;
+  return NFR_OK;
+}
+
+void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (size_t)device < g_scratch_ptr.size() ? g_scratch_ptr[(size_t)device] : nullptr;
+}
+
 // ---------------------------------------------------------------- plans
 
 constexpr int64_t kTargetWGs = 1024;   // about four workgroups per compute unit
@@ -616,6 +652,8 @@ int nfr_context_create(int device, void* hip_stream, nfr_context** out) {
   NFR_HIP(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(NFR_ERR_UNSUPPORTED_ARCH, "device %d is %s, this library is built for gfx950", device, prop.gcnArchName);
+  int st;
+  if ((st = scratch_init(device))) return st;
   nfr_context* c = new (std::nothrow) nfr_context;
   if (!c) return fail(NFR_ERR_INTERNAL, "out of host memory");
   c->device = device;
@@ -814,18 +852,28 @@ size_t nfr_apply_workspace_size(const nfr_problem* prob, int B, int form) {
   return carve(nullptr, prob->view, B, form, false).bytes;
 }
 
-int nfr_apply(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, const double* u_dev,
-              double* y_dev, int form, const void* w_dev, void* ws_dev, size_t ws_bytes) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by nfr_apply and nfr_apply_noalloc; resolves AUTO.
+int apply_check(const nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, const double* u_dev,
+                const double* y_dev, int* form, const void* w_dev) {
   int st;
-  if ((st = check_problem(prob)) || (st = check_kernel(kernel)) || (st = check_firing(firing)) || (st = check_form(form)))
+  if ((st = check_problem(prob)) || (st = check_kernel(kernel)) || (st = check_firing(firing)) || (st = check_form(*form)))
     return st;
   if (B < 1 || B > kMaxB) return fail(NFR_ERR_INVALID_ARG, "B = %d outside [1, %d]", B, kMaxB);
   if (!u_dev || !y_dev) return fail(NFR_ERR_INVALID_ARG, "NULL state pointer");
+  *form = resolve_form(*form, prob->view.n, B);
+  return check_w(prob, *form, w_dev);
+}
+
+// Prep, pair sums and reduction of one application into y_dev, with the
+// scratch of `w` (carved by the caller).
+int apply_launch(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, const double* u_dev,
+                 double* y_dev, int form, const void* w_dev, const Workspace& w) {
+  int st;
   const ProblemView& pv = prob->view;
-  form = resolve_form(form, pv.n, B);
-  if ((st = check_w(prob, form, w_dev))) return st;
-  const Workspace w = carve(ws_dev, pv, B, form, false);
-  if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
   NFR_HIP(hipSetDevice(prob->ctx->device));
   hipStream_t s = prob->ctx->stream;
   const Firing fr = firing_of(*firing);
@@ -839,6 +887,33 @@ int nfr_apply(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* fir
     NFR_LAUNCH_SLOTS(k_reduce_partials, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, y_dev);
   NFR_HIP_LAUNCH();
   return NFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nfr_apply(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, const double* u_dev,
+              double* y_dev, int form, const void* w_dev, void* ws_dev, size_t ws_bytes) {
+  int st;
+  if ((st = apply_check(prob, kernel, firing, B, u_dev, y_dev, &form, w_dev))) return st;
+  const Workspace w = carve(ws_dev, prob->view, B, form, false);
+  if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
+  return apply_launch(prob, kernel, firing, B, u_dev, y_dev, form, w_dev, w);
+}
+
+int nfr_apply_noalloc(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B,
+                      const double* u_dev, double* y_dev, int form, const void* w_dev) {
+  int st;
+  if ((st = apply_check(prob, kernel, firing, B, u_dev, y_dev, &form, w_dev))) return st;
+  void* base = scratch_of(prob->ctx->device);
+  if (!base) return fail(NFR_ERR_INTERNAL, "no scratch address for device %d", prob->ctx->device);
+  // carved once (the plan is read once); nothing is launched unless it fits
+  const Workspace w = carve(base, prob->view, B, form, false);
+  if (w.bytes > kScratchBytes)
+    return fail(NFR_ERR_WORKSPACE, "this application needs %zu scratch bytes; the fixed scratch holds %zu (use nfr_apply with a workspace)",
+                w.bytes, kScratchBytes);
+  return apply_launch(prob, kernel, firing, B, u_dev, y_dev, form, w_dev, w);
 }
 
 size_t nfr_integrate_workspace_size(const nfr_problem* prob, int B, int form) {
