@@ -142,6 +142,11 @@ const char* nfr_context_arch(const nfr_context* ctx);
 int nfr_context_set_timing(nfr_context* ctx, int enable);
 int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms);
 
+/* Size of the HIP graph that the last graph-replayed nfr_integrate or
+ * nfr_batch_integrate call on this context replayed: its node count (kernel
+ * launches) and the RK4 steps it holds (both 0 if none yet).  Host-only. */
+int nfr_context_last_graph(const nfr_context* ctx, int64_t* nodes, int64_t* steps);
+
 /* Roofline microbenchmarks (synchronous).  Rates returned in *rate:
  *   FMA, EXP, SQRT: FP32 lane-operations per second (v_fma / v_exp / v_sqrt),
  *                   `size` = iterations of 8 independent chains per thread;
@@ -271,8 +276,13 @@ size_t nfr_integrate_workspace_size(const nfr_problem* prob, int B, int form);
  * with every state update in FP64.  u_dev (n x B FP64) holds u(0) on entry and
  * u(steps * dt) on exit; integration can resume from any state.  If ckpt_dev is
  * non-NULL it receives u at steps 0, ckpt_every, 2 ckpt_every, ... (each n x B,
- * consecutive; 1 + steps / ckpt_every of them).  use_graph != 0 replays each
- * RK4 step from a captured HIP graph (same results, fewer launches). */
+ * consecutive; 1 + steps / ckpt_every of them).  use_graph != 0 (a
+ * non-default stream is required) replays groups of up to 64 RK4 steps from
+ * one captured HIP graph (with checkpoints the group length divides
+ * ckpt_every); the graph is kept with the problem and replayed again by later
+ * calls with the same arguments and workspace, so repeated integrations pay
+ * one capture.  Steps beyond the last whole group are launched directly.
+ * Results are bitwise those of use_graph == 0. */
 int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B,
                   double* u_dev, double dt, int64_t steps, int form, const void* w_dev,
                   double* ckpt_dev, int64_t ckpt_every, int use_graph,

@@ -68,6 +68,7 @@ def _declare(lib):
         "nfr_context_arch": (c_char_p, [P]),
         "nfr_context_set_timing": (c_int, [P, c_int]),
         "nfr_context_timing": (c_int, [P, POINTER(c_int64), POINTER(c_double)]),
+        "nfr_context_last_graph": (c_int, [P, POINTER(c_int64), POINTER(c_int64)]),
         "nfr_probe": (c_int, [P, c_int, c_int64, P, c_size_t, POINTER(c_double)]),
         "nfr_problem_bytes": (c_size_t, [c_int64]),
         "nfr_problem_create": (c_int, [P, c_int64, P, P, P, c_size_t, POINTER(P)]),

@@ -34,12 +34,33 @@ struct nfr_context {
   bool capturing = false;
   std::vector<hipEvent_t> events;
   size_t events_used = 0;
+  // nodes and RK4 steps of the graph the last graph-replayed call used (0: none yet)
+  int64_t last_graph_nodes = 0;
+  int64_t last_graph_steps = 0;
+};
+
+// Everything a captured RK4 graph of nfr_integrate depends on: the kernel
+// arguments it baked in (pointers, parameters, the launch plan) and its length.
+struct StepGraphKey {
+  int form, B, kind;
+  double dt, A_e, s_e, A_i, s_i, beta, theta;
+  const void* theta_dev;
+  const void* u;
+  const void* w;
+  const void* ws;
+  int64_t steps_per_graph, otf_chunk, otf_tiles;
+  int nsplit, otf_bs, otf_nsb;
 };
 
 struct nfr_problem {
   nfr_context* ctx = nullptr;
   ProblemView view;
   void* pack = nullptr;
+  // the last RK4 graph nfr_integrate captured for this problem, reused while
+  // the key matches (zero-filled before assignment so memcmp sees no padding)
+  hipGraphExec_t step_graph = nullptr;
+  StepGraphKey step_key;
+  int64_t step_graph_nodes = 0;
 };
 
 namespace {
@@ -203,6 +224,8 @@ void* scratch_of(int device) {
 // ---------------------------------------------------------------- plans
 
 constexpr int64_t kTargetWGs = 1024;   // about four workgroups per compute unit
+constexpr int64_t kGraphMaxSteps = 64;  // RK4 steps per captured graph of nfr_integrate
+constexpr int64_t kBatchGraphMaxSteps = 16;  // RK4 steps per captured graph of nfr_batch_integrate
 
 struct OtfPlan {
   int bs = 1, nsb = 1;
@@ -678,6 +701,13 @@ int nfr_context_set_timing(nfr_context* ctx, int enable) {
   return NFR_OK;
 }
 
+int nfr_context_last_graph(const nfr_context* ctx, int64_t* nodes, int64_t* steps) {
+  if (!ctx || !nodes || !steps) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
+  *nodes = ctx->last_graph_nodes;
+  *steps = ctx->last_graph_steps;
+  return NFR_OK;
+}
+
 int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms) {
   if (!ctx || !launches || !total_ms) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
   NFR_HIP(hipSetDevice(ctx->device));
@@ -809,6 +839,12 @@ int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const
 double nfr_problem_period(const nfr_problem* prob) { return prob ? prob->view.period : -1.0; }
 
 int nfr_problem_destroy(nfr_problem* prob) {
+  if (prob && prob->step_graph) {
+    // the executable graph may only be released once its launches have run
+    (void)hipSetDevice(prob->ctx->device);
+    (void)hipStreamSynchronize(prob->ctx->stream);
+    (void)hipGraphExecDestroy(prob->step_graph);
+  }
   delete prob;
   return NFR_OK;
 }
@@ -956,51 +992,90 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
     }
     return NFR_OK;
   };
+  auto checkpoint = [&](int64_t done) -> int {
+    if (ckpt_dev && done % ckpt_every == 0)
+      NFR_HIP(hipMemcpyAsync(ckpt_dev + (done / ckpt_every) * (int64_t)pv.n * B, u_dev, state_bytes,
+                             hipMemcpyDeviceToDevice, s));
+    return NFR_OK;
+  };
 
-  hipGraphExec_t exec = nullptr;
+  // Graph replay: groups of g consecutive RK4 steps are captured once into one
+  // graph, kept with the problem and replayed by this and later calls with the
+  // same arguments (one graph launch per g steps).  With checkpoints g divides
+  // ckpt_every, so every checkpoint falls between two replays; the steps left
+  // over after the last whole group are launched directly (same kernels).
+  int64_t g = 0;
   if (use_graph) {
-    hipGraph_t graph = nullptr;
-    NFR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    prob->ctx->capturing = true;
-    const int r = one_step();
-    prob->ctx->capturing = false;
-    const hipError_t e_end = hipStreamEndCapture(s, &graph);
-    if (r) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return r;
-    }
-    if (e_end != hipSuccess) return fail(NFR_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e_end));
-    const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e_inst != hipSuccess) return fail(NFR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e_inst));
+    g = std::min<int64_t>(steps, kGraphMaxSteps);
+    if (ckpt_dev)
+      while (ckpt_every % g) --g;
   }
-  int result = NFR_OK;
-  for (int64_t step = 0; step < steps; ++step) {
-    if (exec) {
-      const hipError_t e = hipGraphLaunch(exec, s);
-      if (e != hipSuccess) {
-        result = fail(NFR_ERR_HIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
-        break;
+  if (g > 0) {
+    StepGraphKey key;
+    std::memset(&key, 0, sizeof key);
+    key.form = form;
+    key.B = B;
+    key.kind = kernel->kind;
+    key.dt = dt;
+    key.A_e = kernel->A_e;
+    key.s_e = kernel->s_e;
+    key.A_i = kernel->A_i;
+    key.s_i = kernel->s_i;
+    key.beta = firing->beta;
+    key.theta = firing->theta;
+    key.theta_dev = firing->theta_dev;
+    key.u = u_dev;
+    key.w = w_dev;
+    key.ws = ws_dev;
+    key.steps_per_graph = g;
+    key.otf_chunk = w.otf.chunk;
+    key.otf_tiles = w.otf.tiles;
+    key.nsplit = w.nsplit;
+    key.otf_bs = w.otf.bs;
+    key.otf_nsb = w.otf.nsb;
+    if (prob->step_graph && std::memcmp(&key, &prob->step_key, sizeof key) != 0) {
+      NFR_HIP(hipStreamSynchronize(s));   // earlier replays of the old graph must have run
+      (void)hipGraphExecDestroy(prob->step_graph);
+      prob->step_graph = nullptr;
+    }
+    if (!prob->step_graph) {
+      hipGraph_t graph = nullptr;
+      NFR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      prob->ctx->capturing = true;
+      int r = NFR_OK;
+      for (int64_t i = 0; i < g && r == NFR_OK; ++i) r = one_step();
+      prob->ctx->capturing = false;
+      const hipError_t e_end = hipStreamEndCapture(s, &graph);
+      if (r) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
       }
-    } else if ((result = one_step())) {
-      break;
+      if (e_end != hipSuccess) return fail(NFR_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e_end));
+      size_t nodes = 0;
+      (void)hipGraphGetNodes(graph, nullptr, &nodes);
+      hipGraphExec_t exec = nullptr;
+      const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e_inst != hipSuccess) return fail(NFR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e_inst));
+      prob->step_graph = exec;
+      prob->step_key = key;
+      prob->step_graph_nodes = (int64_t)nodes;
     }
-    if (ckpt_dev && (step + 1) % ckpt_every == 0) {
-      const hipError_t e = hipMemcpyAsync(ckpt_dev + ((step + 1) / ckpt_every) * (int64_t)pv.n * B, u_dev, state_bytes,
-                                          hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) {
-        result = fail(NFR_ERR_HIP, "checkpoint copy failed: %s", hipGetErrorString(e));
-        break;
-      }
+    prob->ctx->last_graph_nodes = prob->step_graph_nodes;
+    prob->ctx->last_graph_steps = g;
+  }
+  int64_t done = 0;
+  if (g > 0) {
+    for (; done + g <= steps; done += g) {
+      NFR_HIP(hipGraphLaunch(prob->step_graph, s));
+      if ((st = checkpoint(done + g))) return st;
     }
   }
-  if (exec) {
-    // the executable graph may only be released once its launches have run
-    const hipError_t e = hipStreamSynchronize(s);
-    (void)hipGraphExecDestroy(exec);
-    if (e != hipSuccess && result == NFR_OK) result = fail(NFR_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+  for (; done < steps; ++done) {
+    if ((st = one_step())) return st;
+    if ((st = checkpoint(done + 1))) return st;
   }
-  return result;
+  return NFR_OK;
 }
 
 }  // extern "C"
@@ -1506,12 +1581,16 @@ int nfr_batch_integrate(nfr_batch* b, double* const* u_devs, double dt, int64_t 
     return NFR_OK;
   };
 
+  // Graph replay: g consecutive steps captured into one graph per call, the
+  // steps left over after the last whole group launched directly.
+  const int64_t g = use_graph ? std::min<int64_t>(steps, kBatchGraphMaxSteps) : 0;
   hipGraphExec_t exec = nullptr;
-  if (use_graph) {
+  if (g > 0) {
     hipGraph_t graph = nullptr;
     NFR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     b->ctx->capturing = true;
-    const int r = one_step();
+    int r = NFR_OK;
+    for (int64_t i = 0; i < g && r == NFR_OK; ++i) r = one_step();
     b->ctx->capturing = false;
     const hipError_t e_end = hipStreamEndCapture(s, &graph);
     if (r) {
@@ -1519,23 +1598,28 @@ int nfr_batch_integrate(nfr_batch* b, double* const* u_devs, double dt, int64_t 
       return r;
     }
     if (e_end != hipSuccess) return fail(NFR_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e_end));
+    size_t nodes = 0;
+    (void)hipGraphGetNodes(graph, nullptr, &nodes);
     const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e_inst != hipSuccess) return fail(NFR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e_inst));
+    b->ctx->last_graph_nodes = (int64_t)nodes;
+    b->ctx->last_graph_steps = g;
   }
   int result = NFR_OK;
-  for (int64_t step = 0; step < steps; ++step) {
-    if (exec) {
+  int64_t done = 0;
+  if (exec) {
+    for (; done + g <= steps; done += g) {
       const hipError_t e = hipGraphLaunch(exec, s);
       if (e != hipSuccess) {
         result = fail(NFR_ERR_HIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
         break;
       }
-    } else if ((result = one_step())) {
-      break;
     }
   }
+  for (; result == NFR_OK && done < steps; ++done) result = one_step();
   if (exec) {
+    // the executable graph may only be released once its launches have run
     const hipError_t e = hipStreamSynchronize(s);
     (void)hipGraphExecDestroy(exec);
     if (e != hipSuccess && result == NFR_OK) result = fail(NFR_ERR_HIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
