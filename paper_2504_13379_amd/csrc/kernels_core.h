@@ -247,6 +247,29 @@ __device__ inline float wave_ror1(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, false));
 }
 
+// v from another lane by the DPP pattern CTRL, in the rows of ROW_MASK (0 in
+// the other rows); a double moves as its two 32-bit halves.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// FP64 sum over the 64 lanes of a wave in a fixed pattern of DPP moves (pairs,
+// quads, half-rows, rows of 16, then rows 0 + 1 and 0..3 through the row
+// broadcasts); the total is valid in lane 63.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v += dpp_f64<0xB1, 0xF>(v);     // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E, 0xF>(v);     // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141, 0xF>(v);    // row_half_mirror
+  v += dpp_f64<0x140, 0xF>(v);    // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);    // row_bcast15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);    // row_bcast31 into rows 2 and 3
+  return v;
+}
+
 __host__ __device__ inline int64_t sym_pairs(int64_t nt) { return nt * (nt + 1) / 2; }
 
 __device__ inline void sym_decode(int64_t p, int64_t* I, int64_t* J) {
@@ -515,24 +538,42 @@ __global__ __launch_bounds__(kWG) void k_otf_small(const float4* __restrict__ sr
     tz[r] = p.z * pp.sig;
     acc[r] = 0.0f;
   }
-  for (int64_t j = threadIdx.x; j < npad; j += kWG) {
-    const float4 s4 = src[j];
-    const float sx = s4.x * pp.sig, sy = s4.y * pp.sig, sz = s4.z * pp.sig, sg = g[j];
+  // thread t takes sources t, t + kWG, ... (npad is a multiple of kWG) in
+  // order: batches of 8, then of 4, then single sources, each batch's loads
+  // issued together before any of its evaluations (no branch inside a batch)
+  const int cnt = (int)(npad / kWG);
+  auto batch = [&](auto nb_tag, int k0) {
+    constexpr int NBT = decltype(nb_tag)::value;
+    float4 s4[NBT];
+    float sg[NBT];
 #pragma unroll
-    for (int r = 0; r < kSmallRows; ++r) {
-      const float r2 = pair_r2<KIND>(tx[r] - sx, ty[r] - sy, tz[r] - sz, pp.per);
-      const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
-      acc[r] = fmaf(pair_u<KIND>(t, pp.rho, pp.kappa), sg, acc[r]);
+    for (int e = 0; e < NBT; ++e) {
+      const int64_t j = threadIdx.x + (int64_t)(k0 + e) * kWG;
+      s4[e] = src[j];
+      sg[e] = g[j];
     }
+#pragma unroll
+    for (int e = 0; e < NBT; ++e) {
+      const float sx = s4[e].x * pp.sig, sy = s4[e].y * pp.sig, sz = s4[e].z * pp.sig;
+#pragma unroll
+      for (int r = 0; r < kSmallRows; ++r) {
+        const float r2 = pair_r2<KIND>(tx[r] - sx, ty[r] - sy, tz[r] - sz, pp.per);
+        const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+        acc[r] = fmaf(pair_u<KIND>(t, pp.rho, pp.kappa), sg[e], acc[r]);
+      }
+    }
+  };
+  int k0 = 0;
+  for (; k0 + 8 <= cnt; k0 += 8) batch(std::integral_constant<int, 8>{}, k0);
+  if (k0 + 4 <= cnt) {
+    batch(std::integral_constant<int, 4>{}, k0);
+    k0 += 4;
   }
+  for (; k0 < cnt; ++k0) batch(std::integral_constant<int, 1>{}, k0);
   double d[kSmallRows];
 #pragma unroll
-  for (int r = 0; r < kSmallRows; ++r) d[r] = (double)acc[r];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int r = 0; r < kSmallRows; ++r) d[r] += __shfl_xor(d[r], off, 64);
-  if (lane == 0)
+  for (int r = 0; r < kSmallRows; ++r) d[r] = wave_sum_f64((double)acc[r]);
+  if (lane == 63)
 #pragma unroll
     for (int r = 0; r < kSmallRows; ++r) red[wave][r] = d[r];
   __syncthreads();

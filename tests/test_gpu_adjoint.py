@@ -153,3 +153,55 @@ def test_adjoint_full_size_torus_against_oracle(ctx):
     assert np.max(np.abs(uT - g["uT"])) <= 1e-5 * np.max(np.abs(g["uT"]))
     assert np.max(np.abs(gu - g["grad_u0"][0])) <= TOL * np.max(np.abs(g["grad_u0"]))
     assert _param_err(gp, g["grad_p"]) <= TOL
+
+
+def test_central_fd_h1e4_through_gpu_forward(ctx):
+    """Central differences with the absolute step h = 1e-4 taken through the GPU
+    forward integration (five parameters and one unit u0 direction), on the
+    torus with N = 700 nodes and 37 RK4 steps.
+
+    FD(h) = (L(p + h) - L(p - h)) / 2h differs from the derivative by its
+    truncation error, O(h^2) times the third derivative of L, which the steep
+    sigmoid (beta = 20) can make visible; the FP64 oracle's FD with the same h
+    carries the same truncation error.  The GPU's FD adds the rounding of its
+    FP32 pair sums: the two losses carry independent errors
+    dL ~ 2 |u - target| |du| with |du| ~ 1e-7 |u|, divided by 2h = 2e-4,
+    about 1e-4 of the largest gradient component here (measured: 1.05e-4 for
+    s_e; the oracle's FD and adjoint agree to 2e-6).  So, norm-wise against
+    the largest component: the GPU's FD matches the oracle's FD, and the GPU
+    adjoint matches the GPU's FD up to the oracle's own FD-versus-adjoint gap,
+    both within 3e-4."""
+    w, q, target = _case(NF.EXP_MH)
+    x, th = w.surface.xyz, float(w.theta[0])
+    h = 1e-4
+    _, gu, gp = _gpu_grads(ctx, x, q, w.kernel_kind, w.kernel, w.u0, w.beta, th, w.dt, w.steps, 10, target)
+    prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
+
+    def loss_gpu(params, u0):
+        u = torch.from_numpy(np.atleast_2d(u0).copy()).cuda()
+        prob.integrate(P.kernel_struct(w.kernel_kind, *params[:4]), P.Firing(w.beta, float(params[4])), u, w.dt,
+                       w.steps)
+        torch.cuda.synchronize()
+        return NF.loss(u.cpu().numpy(), target)
+    base = np.array(list(w.kernel) + [th])
+    fd_gpu = np.zeros(5)
+    for m in range(5):
+        e = np.zeros(5)
+        e[m] = h
+        fd_gpu[m] = (loss_gpu(base + e, w.u0) - loss_gpu(base - e, w.u0)) / (2 * h)
+    fd_orc = NF.fd_param_gradients(x, q, w.kernel_kind, w.kernel, w.u0, w.beta, th, w.dt, w.steps, target, h=h)
+    op = NF.ParamOperator(x, q, w.kernel_kind, w.kernel)
+    _, gu_orc, gp_orc = NF.adjoint_gradients(op, w.u0, w.beta, th, w.dt, w.steps, target)
+    print("fd_gpu", fd_gpu, "fd_orc", fd_orc, "adj_gpu", gp, "adj_orc", gp_orc, flush=True)
+    scale = np.max(np.abs(fd_orc))
+    assert np.max(np.abs(fd_gpu - fd_orc)) <= 3e-4 * scale
+    trunc = np.abs(fd_orc - gp_orc)
+    assert np.all(np.abs(fd_gpu - gp) <= trunc + 3e-4 * scale)
+    d = np.random.default_rng(2).normal(size=w.n)
+    d /= np.linalg.norm(d)
+    fdu_gpu = (loss_gpu(base, w.u0 + h * d) - loss_gpu(base, w.u0 - h * d)) / (2 * h)
+    fdu_orc = NF.fd_u0_directional(x, q, w.kernel_kind, w.kernel, w.u0, w.beta, th, w.dt, w.steps, target, d, h=h)
+    print("u0 direction: fd_gpu %.8e fd_orc %.8e adj_gpu %.8e" % (fdu_gpu, fdu_orc, float(gu @ d)), flush=True)
+    # the rounding allowance is absolute (dL / 2h), the same as for the parameters
+    assert abs(fdu_gpu - fdu_orc) <= 3e-4 * scale
+    assert abs(fdu_gpu - float(gu @ d)) <= abs(fdu_orc - float(gu_orc[0] @ d)) + 3e-4 * scale
