@@ -1,17 +1,22 @@
 """Throughput of the neural-field hot path on one MI355X.
 
-Workload (one "step" = one whole integration): torus R = 1, r = 0.4 with
-N = 32768 jittered-ring nodes, exponential Mexican hat
-w(r) = 2 exp(-r/0.1) - exp(-r/0.3), sigmoid beta = 20, theta = 0.25, two
-bumps as u0, classical RK4 with dt = 0.02 for 500 steps (2000 operator
-applications of N^2 pairs each).  Inputs are resident on the GPU before the
-timed region.  Quadrature weights are the area-share stand-in |D|/N (the
-oracle's RBF-QF weights are used by the parity tests; the weight values do not
-change the work).
+Headline workload (one "step" = one whole integration): the ellipsoid
+(1, .8, .6) ensemble, N = 65536 nodes with the FP64 oracle's RBF-QF weights,
+Gaussian Mexican hat w(r) = exp(-r^2/.15^2) - .5 exp(-r^2/.4^2), B = 64 states
+(one seeded bump each, thresholds theta_b ~ U(.15, .3), sigmoid beta = 20),
+classical RK4 with dt = 0.05 for 200 steps (800 operator applications of
+N^2 B pair-interactions each), FP64 state updates.  Inputs are resident on the
+GPU before the timed region.  Every form runs: the split-precision ones (W or
+fused on-the-fly, BF16 or FP16 hi + lo products on the matrix cores) and the
+FP32 ones (vector-unit and matrix-core pair sums); `value` is the fastest
+split form's median over the timed integrations, and every form's u(T) is
+compared member by member with the oracle's stored u(T)
+(tests/golden/ellipsoid65536_rk4.npz, written by the oracle alone).
 
-Both evaluation forms run: on-the-fly FP32 pair sums, and precomputed FP32 W
-(its build is inside every timed step).  `value` is the faster form's
-pair-interactions per second; both forms are listed under "forms".
+Sub-legs: the torus (N = 32768, B = 1, 500 steps; on-the-fly FP32 and FP32 W,
+against the oracle's whole u(T)), the small sphere (N = 2000, time per step),
+the 48-problem uneven batch (100 steps, against the oracle), the adjoint and
+the GPU quadrature weights.
 
 Prints one JSON line.
 """
@@ -106,23 +111,32 @@ def measured_traffic(kernel: str):
     return rec[kernel]["bytes"]
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def load_golden(name):
+    """Stored FP64 oracle results (written by tests/golden/make_trajectory_goldens.py)."""
+    import numpy as np
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        raise SystemExit("bench.py: missing %s (the oracle's stored trajectory)" % path)
+    return np.load(path)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--rk4-steps", type=int, default=500)
-    ap.add_argument("--forms", default="otf,w32")
-    ap.add_argument("--no-graph", action="store_true", help="launch every kernel instead of replaying graphs")
+    ap.add_argument("--steps", type=int, default=3, help="timed integrations of the headline form")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed integrations of the headline form")
+    ap.add_argument("--forms", default="otf_bf16x3,bf16x3,otf_fp16x3,fp16x3,otf_fp32_mfma,otf_fp32",
+                    help="ensemble forms to run (the split ones compete for the headline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-torus", action="store_true", help="skip the N = 32768 torus leg")
     ap.add_argument("--no-small", action="store_true", help="skip the N = 2000 sphere time-per-step leg")
     ap.add_argument("--probes", action="store_true", help="also run the roofline microbenchmarks")
     ap.add_argument("--probes-only", action="store_true",
                     help="run only the roofline microbenchmarks and print their rates as one JSON line")
-    ap.add_argument("--ens-rk4-steps", type=int, default=10,
-                    help="RK4 steps of the ellipsoid-ensemble comparison leg (0 = skip it)")
-    ap.add_argument("--batch-rk4-steps", type=int, default=20,
-                    help="RK4 steps of the 48-problem uneven-batch leg (0 = skip it)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 48-problem uneven-batch leg")
     ap.add_argument("--adjoint-rk4-steps", type=int, default=400,
                     help="RK4 steps of the torus adjoint leg (0 = skip it)")
     ap.add_argument("--quad-n", type=int, default=65536,
@@ -130,167 +144,361 @@ def parse():
     return ap.parse_args()
 
 
-def run_form(P, torch, prob, w, q_t, form, args, u0_t):
-    k = P.kernel_struct(w.kernel_kind, *w.kernel)
-    f = P.Firing(w.beta, float(w.theta[0]))
+def kernel_timing(P, ctx, fn):
+    """Runs fn() with HIP events around every pair-sum launch on the context's stream;
+    returns (launches, average ms per launch)."""
+    import ctypes
     L = P.lib()
-    ctx = prob.ctx
-    u = torch.empty_like(u0_t)
-    ws = prob.integrate_workspace(1, form)
-    wbytes = L.nfr_w_bytes(w.n, form) if form != P.FORM_ONTHEFLY_FP32 else 0
-    Wbuf = None
-    if wbytes:
-        from paper_2504_13379_amd.api import _dev_buffer
-        Wbuf = _dev_buffer(wbytes, ctx.device)
-
-    def one():
-        u.copy_(u0_t)
-        if Wbuf is not None:
-            P._lib.check(L.nfr_w_build(prob.handle, __import__("ctypes").byref(k), form, Wbuf.data_ptr(), wbytes))
-        prob.integrate(k, f, u, w.dt, args.rk4_steps, form=form, W=Wbuf, ws=ws, use_graph=not args.no_graph)
-
-    for _ in range(args.warmup):
-        one()
-    torch.cuda.synchronize()
-    import ctypes
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # dominant-kernel duration: HIP events around every pair-sum launch of one
-    # more integration (events are not recorded inside replayed graphs)
     L.nfr_context_set_timing(ctx.handle, 1)
-    u.copy_(u0_t)
-    prob.integrate(k, f, u, w.dt, args.rk4_steps, form=form, W=Wbuf, ws=ws, use_graph=False)
-    launches = ctypes.c_int64()
-    tot_ms = ctypes.c_double()
-    P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot_ms)))
+    fn()
+    launches, tot = ctypes.c_int64(), ctypes.c_double()
+    P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot)))
     L.nfr_context_set_timing(ctx.handle, 0)
-    sec = (t1 - t0) / args.steps
-    pairs = 4.0 * args.rk4_steps * float(w.n) ** 2
-    return {
-        "ms_per_step": sec * 1e3,
-        "value": pairs / sec,
-        "kernel_launches": int(launches.value),
-        "kernel_avg_ms": tot_ms.value / max(1, launches.value),
-        "u": u,
-    }
+    return int(launches.value), tot.value / max(1, launches.value)
 
 
-def roofline(form_name, res, n, npad, kernel):
-    avg_s = res["kernel_avg_ms"] * 1e-3
-    if form_name == "w32":
-        bytes_per_launch = float(n) * npad * 4.0          # every W element once per application
-        ach = bytes_per_launch / avg_s
-        return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": ach / HBM_PEAK, "traffic": measured_traffic("k_w_gemv_f32<1>"), "kernel": "k_w_gemv_f32<1>"}
-    # on-the-fly: slots per unordered pair x npad^2 / 2 pairs per launch
-    kind, s_e, s_i = kernel[0], kernel[2], kernel[4]
-    m = sym_pow(kind, s_e, s_i)
-    name = sym_kernel_name(kind, m)
-    ops = slots_per_unordered_pair(kind, m) * float(npad) * npad / 2.0
-    ach = ops / avg_s
-    return {"bound": "alu", "achieved": ach / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tlane-op/s",
-            "frac": ach / VALU_LANES_PER_S, "traffic": measured_traffic(name), "kernel": name,
-            "slots_per_unordered_pair": slots_per_unordered_pair(kind, m)}
-
-
-def ensemble_leg(P, torch, args):
-    """Ellipsoid (1, .8, .6), N = 65536, B = 64 Gaussian-kernel ensemble: the split-precision
-    MFMA W forms against the plain FP32 on-the-fly path on the same GPU."""
+def launches_per_step(P, ctx):
+    """Kernel nodes per RK4 step of the graph the last graph-replayed call used."""
     import ctypes
+    nodes, steps = ctypes.c_int64(), ctypes.c_int64()
+    P._lib.check(P.lib().nfr_context_last_graph(ctx.handle, ctypes.byref(nodes), ctypes.byref(steps)))
+    return {"graph_nodes": int(nodes.value), "graph_rk4_steps": int(steps.value),
+            "launches_per_rk4_step": nodes.value / steps.value if steps.value else None}
+
+
+# ------------------------------------------------------------------ headline: ellipsoid ensemble
+
+ENS_FORMS = {"otf_bf16x3": 4, "bf16x3": 2, "otf_fp16x3": 5, "fp16x3": 3, "otf_fp32_mfma": 6, "otf_fp32": 0}
+SPLIT_FORMS = ("otf_bf16x3", "bf16x3", "otf_fp16x3", "fp16x3")
+
+
+def ensemble_roofline(nm, npad, kind, kernel, avg_s):
+    """Roofline of the dominant (pair-sum) kernel of form `nm` at one launch per operator application."""
+    m = sym_pow(kind, kernel[1], kernel[3])
+    if nm in ("bf16x3", "fp16x3"):
+        wbytes = 2.0 * 2 * npad * npad     # hi + lo, 2 bytes each, every element once
+        kname = "k_mfma_apply<%s,2>" % nm[:4]
+        return {"bound": "hbm", "achieved": wbytes / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": wbytes / avg_s / HBM_PEAK, "traffic": measured_traffic(kname), "kernel": kname,
+                "algorithmic_bytes_per_launch": wbytes}
+    if nm == "otf_fp32_mfma":
+        kname = "k_mfma_otf_f32<%d,2>" % (kind + 4 * (m - 1 if m else 0))
+        flops = 2.0 * float(npad) ** 2 * 64
+        return {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": MFMA_F32_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": flops / avg_s / MFMA_F32_PEAK, "traffic": measured_traffic(kname), "kernel": kname,
+                "alu_frac": float(npad) ** 2 * eval_slots(kind, m) / avg_s / VALU_LANES_PER_S}
+    if nm == "otf_fp32":
+        # one-sided multi-state pair sum: per target-source pair one evaluation of u per block
+        # of 16 states (no integer-ratio shortcut in this kernel) + 1 FMA per state
+        kname = "k_otf_pair_sum<%d,2,16>" % kind
+        slots = float(npad) ** 2 * (-(-64 // 16) * eval_slots(kind, 0) + 64)
+        return {"bound": "alu", "achieved": slots / avg_s / 1e12, "peak": VALU_LANES_PER_S / 1e12,
+                "unit": "Tslot/s", "frac": slots / avg_s / VALU_LANES_PER_S, "traffic": measured_traffic(kname),
+                "kernel": kname}
+    # fused on-the-fly split forms: every W entry evaluated once per launch on the vector
+    # units; the matrix cores do 3 products x 2 flop x 64 states per entry
+    fp16 = nm == "otf_fp16x3"
+    kname = "k_mfma_otf<%s,%d,2>" % ("fp16" if fp16 else "bf16", kind + 4 * (m - 1 if m else 0))
+    wvals = float(npad) ** 2
+    achieved = wvals * fused_slots_per_w(kind, m, fp16) / avg_s
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tslot/s",
+            "frac": achieved / VALU_LANES_PER_S, "traffic": measured_traffic(kname), "kernel": kname,
+            "slots_per_w": fused_slots_per_w(kind, m, fp16), "mfma_tflops": wvals * 384.0 / avg_s / 1e12,
+            "mfma_frac": wvals * 384.0 / avg_s / MFMA_BF16_PEAK}
+
+
+def ensemble_headline(P, torch, args):
+    """Every requested form of the ellipsoid ensemble: one warm-up step and one timed whole
+    integration each, u(T) per member against the oracle; then the fastest split form again
+    with args.warmup + args.steps whole integrations (the headline, median)."""
+    import numpy as np
 
     from workloads import configs as C
-    w = C.ellipsoid_ensemble(65536, 64, steps=args.ens_rk4_steps)
-    q = C.area_share_weights(w.surface)
-    ctx = P.Context(0)
-    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
-    L = P.lib()
+    gold = load_golden("ellipsoid65536_rk4.npz")
+    w = C.ellipsoid_ensemble()
+    assert w.n == int(gold["n"]) and w.steps == int(gold["steps"])
+    rows, ref_rows, ref_max = gold["rows"], gold["uT_rows"], gold["uT_absmax"]
+    ctx = P.Context(0, torch.cuda.Stream())
+    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(gold["q"]).cuda())
     k = P.kernel_struct(w.kernel_kind, *w.kernel)
     f = P.Firing(w.beta, torch.from_numpy(w.theta).cuda())
     u0 = torch.from_numpy(w.u0.copy()).cuda()
-    out = {"workload": "ellipsoid (1,.8,.6), N=65536, B=64, Gauss Mexican hat, RK4 dt=0.05 x %d steps"
-                       % args.ens_rk4_steps}
-    finals = {}
-    for nm, form in (("bf16x3", P.FORM_W_BF16X3), ("fp16x3", P.FORM_W_FP16X3), ("otf_bf16x3", P.FORM_ONTHEFLY_BF16X3),
-                     ("otf_fp16x3", P.FORM_ONTHEFLY_FP16X3), ("otf_fp32_mfma", P.FORM_ONTHEFLY_FP32_MFMA),
-                     ("otf_fp32", P.FORM_ONTHEFLY_FP32)):
-        print("bench: ensemble form %s" % nm, file=sys.stderr, flush=True)
-        W = None
-        t_build = 0.0
+    u = u0.clone()
+    pairs = 4.0 * w.steps * float(w.n) ** 2 * w.b
+    forms = {}
+    keep = {}
+
+    def integrate(form, W, ws, steps, graph=True):
+        u.copy_(u0)
+        prob.integrate(k, f, u, w.dt, steps, form=form, W=W, ws=ws, use_graph=graph)
+
+    def timed(form, W, ws):
+        ctx.stream.synchronize()
+        t0 = time.perf_counter()
+        integrate(form, W, ws, w.steps)
+        ctx.stream.synchronize()
+        return time.perf_counter() - t0
+
+    def setup(form):
+        W, t_build = None, 0.0
         if form in (P.FORM_W_BF16X3, P.FORM_W_FP16X3):
-            torch.cuda.synchronize()
+            ctx.stream.synchronize()
             tb = time.perf_counter()
             W = prob.w_build(k, form)
-            torch.cuda.synchronize()
+            ctx.stream.synchronize()
             t_build = time.perf_counter() - tb
-        ws = prob.integrate_workspace(64, form)
-        u = u0.clone()
-        prob.integrate(k, f, u, w.dt, 1, form=form, W=W, ws=ws)          # warm-up
-        u.copy_(u0)
-        torch.cuda.synchronize()
-        L.nfr_context_set_timing(ctx.handle, 1)
+        return W, t_build, prob.integrate_workspace(w.b, form)
+
+    for nm in args.forms.split(","):
+        form = ENS_FORMS[nm]
+        print("bench: ensemble form %s" % nm, file=sys.stderr, flush=True)
+        W, t_build, ws = setup(form)
+        integrate(form, W, ws, 1)                         # warm-up (captures the step graph)
+        sec = timed(form, W, ws)
+        lps = launches_per_step(P, ctx)
+        err = np.max(np.abs(u.cpu().numpy()[:, rows] - ref_rows), axis=1) / ref_max
+        n_l, avg_ms = kernel_timing(P, ctx, lambda: integrate(form, W, ws, w.steps // 4, graph=False))
+        forms[nm] = {"value": pairs / sec, "unit": "pair-interactions/s", "ms_per_integration": sec * 1e3,
+                     "w_build_ms": t_build * 1e3, "kernel_avg_ms": avg_ms, **lps,
+                     "rel_linf_vs_fp64_max": float(err.max()), "rel_linf_vs_fp64_median": float(np.median(err)),
+                     "roofline": ensemble_roofline(nm, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3)}
+        keep[nm] = err
+        del W
+        torch.cuda.empty_cache()
+    split = [nm for nm in forms if nm in SPLIT_FORMS]
+    best = max(split, key=lambda nm: forms[nm]["value"])
+    form = ENS_FORMS[best]
+    print("bench: headline form %s, %d warmup + %d timed integrations" % (best, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    W, _, ws = setup(form)
+    for _ in range(args.warmup):
+        integrate(form, W, ws, w.steps, graph=False)
+    ctx.stream.synchronize()
+    # the timed region: args.steps whole integrations launched directly, with HIP
+    # events around every pair-sum launch on the context's stream (the kernel's
+    # duration for the roofline comes from the same runs as the throughput)
+    L = P.lib()
+    L.nfr_context_set_timing(ctx.handle, 1)
+    times = []
+    t_all0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.stream.synchronize()
         t0 = time.perf_counter()
-        prob.integrate(k, f, u, w.dt, args.ens_rk4_steps, form=form, W=W, ws=ws)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        integrate(form, W, ws, w.steps, graph=False)
+        ctx.stream.synchronize()
+        times.append(time.perf_counter() - t0)
+    t_all = time.perf_counter() - t_all0
+    import ctypes
+    launches, tot = ctypes.c_int64(), ctypes.c_double()
+    P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot)))
+    L.nfr_context_set_timing(ctx.handle, 0)
+    n_l, avg_ms = int(launches.value), tot.value / max(1, launches.value)
+    err = np.max(np.abs(u.cpu().numpy()[:, rows] - ref_rows), axis=1) / ref_max
+    med = sorted(times)[len(times) // 2]
+    head = {"form": best, "value": pairs / med, "ms_per_step": med * 1e3, "ms_all_timed": t_all * 1e3,
+            "times_ms": [t * 1e3 for t in times], "kernel_avg_ms": avg_ms, "kernel_launches_timed": n_l,
+            "timed_launch": "directly launched (HIP events around each pair-sum launch)",
+            "rel_linf_vs_fp64": [float(e) for e in err], "rel_linf_vs_fp64_max": float(err.max()),
+            "roofline": ensemble_roofline(best, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3),
+            "launches": launches_per_step(P, ctx)}
+    del W
+    torch.cuda.empty_cache()
+    return w, gold, head, forms
+
+
+# ------------------------------------------------------------------ torus (B = 1)
+
+
+def torus_leg(P, torch, args):
+    """Torus N = 32768, B = 1, exponential Mexican hat, 500 RK4 steps with the oracle's
+    weights: on-the-fly FP32 (symmetric kernel) and FP32 W (built inside each timed run),
+    three timed integrations each, u(T) against the oracle's whole u(T)."""
+    import numpy as np
+
+    from workloads import configs as C
+    gold = load_golden("torus32768_rk4.npz")
+    w = C.torus_exp()
+    ctx = P.Context(0, torch.cuda.Stream())
+    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(gold["q"]).cuda())
+    k = P.kernel_struct(w.kernel_kind, *w.kernel)
+    f = P.Firing(w.beta, float(w.theta[0]))
+    u0 = torch.from_numpy(w.u0.copy()).cuda()
+    u = u0.clone()
+    ref = gold["uT"]
+    out = {"workload": "torus R=1 r=0.4, N=32768, exp Mexican hat, B=1, RK4 dt=0.02 x %d steps, oracle weights"
+                       % w.steps}
+    pairs = 4.0 * w.steps * float(w.n) ** 2
+    for nm, form in (("otf_fp32", P.FORM_ONTHEFLY_FP32), ("w_fp32", P.FORM_W_FP32)):
+        ws = prob.integrate_workspace(1, form)
+        W = prob.w_build(k, form) if form == P.FORM_W_FP32 else None
+
+        def one(graph=True, steps=w.steps):
+            u.copy_(u0)
+            if W is not None:
+                P._lib.check(P.lib().nfr_w_build(prob.handle, __import__("ctypes").byref(k), form, W.data_ptr(),
+                                                 W.numel()))
+            prob.integrate(k, f, u, w.dt, steps, form=form, W=W, ws=ws, use_graph=graph)
+
+        one()                                     # warm-up with graph replay (captures the step graph)
+        lps = launches_per_step(P, ctx)
+        one(graph=False)
+        import ctypes
+        L = P.lib()
+        L.nfr_context_set_timing(ctx.handle, 1)   # events around every pair launch of the timed runs
+        times = []
+        for _ in range(3):
+            ctx.stream.synchronize()
+            t0 = time.perf_counter()
+            one(graph=False)
+            ctx.stream.synchronize()
+            times.append(time.perf_counter() - t0)
         launches, tot = ctypes.c_int64(), ctypes.c_double()
         P._lib.check(L.nfr_context_timing(ctx.handle, ctypes.byref(launches), ctypes.byref(tot)))
         L.nfr_context_set_timing(ctx.handle, 0)
-        pairs = 4.0 * args.ens_rk4_steps * float(w.n) ** 2 * 64
-        avg = tot.value / max(1, launches.value) * 1e-3
-        entry = {"value": pairs / (t1 - t0), "unit": "pair-interactions/s", "ms_per_integration": (t1 - t0) * 1e3,
-                 "w_build_ms": t_build * 1e3, "kernel_avg_ms": avg * 1e3}
-        if W is not None:
-            wbytes = 2.0 * 2 * prob.npad * prob.npad     # hi + lo, 2 bytes each, every element once
-            kname = "k_mfma_apply<%s,2>" % ("bf16" if nm == "bf16x3" else "fp16")
-            entry["roofline"] = {"bound": "hbm", "achieved": wbytes / avg / 1e9, "peak": HBM_PEAK / 1e9,
-                                 "unit": "GB/s", "frac": wbytes / avg / HBM_PEAK,
-                                 "traffic": measured_traffic(kname), "kernel": kname}
-        elif form == P.FORM_ONTHEFLY_FP32_MFMA:
-            # products on the FP32 matrix cores: 2 flop per pair-interaction (64 states, each
-            # kernel value once per launch on the vector units)
+        avg_ms = tot.value / max(1, launches.value)
+        gtimes = []
+        for _ in range(3):
+            ctx.stream.synchronize()
+            t0 = time.perf_counter()
+            one()
+            ctx.stream.synchronize()
+            gtimes.append(time.perf_counter() - t0)
+        err = float(np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref)))
+        med = min(sorted(times)[1], sorted(gtimes)[1])
+        entry = {"value": pairs / med, "unit": "pair-interactions/s", "ms_per_integration": med * 1e3,
+                 "ms_launched": sorted(times)[1] * 1e3, "ms_graph": sorted(gtimes)[1] * 1e3,
+                 "kernel_avg_ms": avg_ms, "rel_linf_vs_fp64": err, **lps}
+        if nm == "otf_fp32":
             m = sym_pow(w.kernel_kind, w.kernel[1], w.kernel[3])
-            kname = "k_mfma_otf_f32<%d,2>" % (w.kernel_kind + 4 * (m - 1 if m else 0))
-            flops = 2.0 * float(prob.npad) ** 2 * 64
-            entry["roofline"] = {"bound": "mfma", "achieved": flops / avg / 1e12, "peak": MFMA_F32_PEAK / 1e12,
-                                 "unit": "TFLOP/s", "frac": flops / avg / MFMA_F32_PEAK,
-                                 "traffic": measured_traffic(kname), "kernel": kname,
-                                 "alu_frac": float(prob.npad) ** 2 * eval_slots(w.kernel_kind, m) / avg / VALU_LANES_PER_S}
-        elif form == P.FORM_ONTHEFLY_FP32:
-            # one-sided multi-state pair sum: per target-source pair one evaluation of u per
-            # block of 16 states (no integer-ratio shortcut in this kernel) + 1 FMA per state
-            kname = "k_otf_pair_sum<%d,2,16>" % w.kernel_kind
-            slots = float(prob.npad) ** 2 * (-(-64 // 16) * eval_slots(w.kernel_kind, 0) + 64)
-            entry["roofline"] = {"bound": "alu", "achieved": slots / avg / 1e12, "peak": VALU_LANES_PER_S / 1e12,
-                                 "unit": "Tslot/s", "frac": slots / avg / VALU_LANES_PER_S,
-                                 "traffic": measured_traffic(kname), "kernel": kname}
-        elif form in (P.FORM_ONTHEFLY_BF16X3, P.FORM_ONTHEFLY_FP16X3):
-            # every W entry evaluated once per launch (64 states share it) on the vector
-            # units; the matrix cores do 3 products x 2 flops x 64 states per entry
-            m = sym_pow(w.kernel_kind, w.kernel[1], w.kernel[3])
-            wvals = float(prob.npad) ** 2
-            kname = "k_mfma_otf<%s,%d,2>" % ("bf16" if nm == "otf_bf16x3" else "fp16",
-                                             w.kernel_kind + 4 * (m - 1 if m else 0))
-            fp16 = nm == "otf_fp16x3"
-            achieved = wvals * fused_slots_per_w(w.kernel_kind, m, fp16) / avg
-            entry["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANES_PER_S / 1e12,
-                                 "unit": "Tslot/s", "frac": achieved / VALU_LANES_PER_S,
-                                 "traffic": measured_traffic(kname), "kernel": kname,
-                                 "slots_per_w": fused_slots_per_w(w.kernel_kind, m, fp16),
-                                 "mfma_tflops": wvals * 384.0 / avg / 1e12,
-                                 "mfma_frac": wvals * 384.0 / avg / MFMA_BF16_PEAK}
+            name = sym_kernel_name(w.kernel_kind, m)
+            ops = slots_per_unordered_pair(w.kernel_kind, m) * float(prob.npad) ** 2 / 2.0
+            entry["roofline"] = {"bound": "alu", "achieved": ops / (avg_ms * 1e-3) / 1e12,
+                                 "peak": VALU_LANES_PER_S / 1e12, "unit": "Tslot/s",
+                                 "frac": ops / (avg_ms * 1e-3) / VALU_LANES_PER_S, "traffic": measured_traffic(name),
+                                 "kernel": name, "slots_per_unordered_pair": slots_per_unordered_pair(w.kernel_kind, m)}
+        else:
+            b = float(w.n) * prob.npad * 4.0
+            entry["roofline"] = {"bound": "hbm", "achieved": b / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                                 "unit": "GB/s", "frac": b / (avg_ms * 1e-3) / HBM_PEAK,
+                                 "traffic": measured_traffic("k_w_gemv_f32<1>"), "kernel": "k_w_gemv_f32<1>"}
         out[nm] = entry
-        finals[nm] = u.cpu().numpy()
         del W
         torch.cuda.empty_cache()
-    import numpy as np
-    ref = finals["otf_fp32"]
-    for nm in ("bf16x3", "fp16x3", "otf_bf16x3", "otf_fp16x3", "otf_fp32_mfma"):
-        out[nm]["max_rel_linf_vs_otf_fp32"] = float(np.max(np.max(np.abs(finals[nm] - ref), axis=1) /
-                                                            np.max(np.abs(ref), axis=1)))
     return out
+
+
+# ------------------------------------------------------------------ uneven batch
+
+
+def batch_leg(P, torch, args):
+    """The 48-problem uneven batch (N log-uniform in [1000, 40000], B in {1, 4, 16}) with the
+    oracle's weights: tuned persistent launches, graph-replayed steps, 100 RK4 steps, every
+    state against the oracle's stored u(T) (sampled rows)."""
+    import numpy as np
+
+    from workloads import configs as C
+    gold = load_golden("batch48_rk4.npz")
+    ws_list = C.uneven_batch()
+    steps, dt = ws_list[0].steps, ws_list[0].dt
+    stream = torch.cuda.Stream()
+    ctx = P.Context(0, stream)
+    probs, ks, fs, Bs, u0s = [], [], [], [], []
+    with torch.cuda.stream(stream):
+        for p, w in enumerate(ws_list):
+            probs.append(P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(),
+                                   torch.from_numpy(gold["q%02d" % p]).cuda()))
+            ks.append(P.kernel_struct(w.kernel_kind, *w.kernel))
+            fs.append(P.Firing(w.beta, torch.from_numpy(w.theta).cuda()))
+            Bs.append(w.b)
+            u0s.append(torch.from_numpy(w.u0.copy()).cuda())
+    torch.cuda.synchronize()
+    batch = P.Batch(ctx, probs, ks, fs, Bs)
+    ws = batch.workspace()
+    states = [u.clone() for u in u0s]
+    t0 = time.perf_counter()
+    best = batch.tune(states, ws)
+    t_tune = time.perf_counter() - t0
+    batch.integrate(states, dt, 1, use_graph=True, ws=ws)       # warm-up
+    for s_, u in zip(states, u0s):
+        s_.copy_(u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.integrate(states, dt, steps, use_graph=True, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    worst = 0.0
+    for p, u in enumerate(states):
+        rows = gold["rows%02d" % p]
+        err = np.max(np.abs(u.cpu().numpy()[:, rows] - gold["uT%02d" % p]), axis=1) / gold["absmax%02d" % p]
+        worst = max(worst, float(err.max()))
+    pair_ints = sum(4.0 * steps * float(w.n) ** 2 * w.b for w in ws_list)
+    # algorithmic slots of the pair kernel per stage: per target-source pair and state block
+    # one evaluation of u (eval_slots: 16 for the Gaussian), plus 1 FMA per state; blocks of
+    # 1, 4 or 16 states
+    slots = 0.0
+    for w in ws_list:
+        npad = -(-w.n // 256) * 256
+        bs = 1 if w.b == 1 else (4 if w.b <= 4 else 16)
+        slots += float(npad) ** 2 * (-(-w.b // bs) * eval_slots(0, 0) + w.b)
+    slots *= 4.0 * steps
+    chunk, wgs = batch.config
+    return {"workload": "48 problems, N log-uniform [1000, 40000], sphere/torus/ellipsoid/bumpy, Gauss Mexican hat, "
+                        "B in {1,4,16}, RK4 dt=0.05 x %d steps, graph-replayed, oracle weights" % steps,
+            "value": pair_ints / (t1 - t0), "unit": "pair-interactions/s", "ms_per_integration": (t1 - t0) * 1e3,
+            "rel_linf_vs_fp64_max": worst,
+            "roofline": {"bound": "alu", "achieved": slots / (t1 - t0) / 1e12, "peak": VALU_LANES_PER_S / 1e12,
+                         "unit": "Tslot/s", "frac": slots / (t1 - t0) / VALU_LANES_PER_S,
+                         "note": "whole integration time (pair kernel, combine, launch gaps)"},
+            "tuned": {"chunk": chunk, "wgs_per_cu": wgs, "best_stage_ms": best, "tune_ms": t_tune * 1e3},
+            **launches_per_step(P, ctx)}
+
+
+# ------------------------------------------------------------------ CPU baseline
+
+
+def host_info():
+    import platform
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"api": i.get("internal_api"), "threads": i.get("num_threads")} for i in threadpool_info()]
+    except Exception:                       # noqa: BLE001 - diagnostics only
+        blas = []
+    return {"os_cpu_count": os.cpu_count(), "sched_cores": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "blas": blas}
+
+
+def cpu_baseline(w, q, n_rows):
+    """The FP64 oracle's operator (its apply_K: kernel rows from the definition, then a
+    BLAS product with the 64 states' q f(u)) on a bounded sample of one application of the
+    headline workload: n_rows target rows x all sources x all states; one thread, then every
+    host thread the process may use."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import neural_field as NF
+    rows = np.random.default_rng(7).choice(w.n, n_rows, replace=False)
+    cores = len(os.sched_getaffinity(0))
+    out = {}
+    for threads in (1, cores):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            NF.apply_K(w.surface.xyz, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows=rows)
+            t1 = time.perf_counter()
+        out[threads] = float(n_rows) * w.n * w.b / (t1 - t0)
+    return {"value": out[cores], "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
+            "value_1_thread": out[1],
+            "sample": "one operator application of the ellipsoid ensemble: %d of %d target rows x all %d sources "
+                      "x %d states, FP64 NumPy (elementwise kernel rows, BLAS product)" % (n_rows, w.n, w.n, w.b),
+            "host": host_info()}
 
 
 def small_leg(P, torch, args):
@@ -327,61 +535,6 @@ def small_leg(P, torch, args):
         finals[nm] = u.cpu().numpy()
     out["graph_equals_launched"] = bool(np.array_equal(finals["graph"], finals["launched"]))
     return out
-
-
-def batch_leg(P, torch, args):
-    """The 48-problem uneven batch (N log-uniform in [1000, 40000], B in {1, 4, 16}):
-    tuned persistent launches with graph-captured steps."""
-    import ctypes
-
-    from workloads import configs as C
-    ws_list = C.uneven_batch(steps=args.batch_rk4_steps)
-    stream = torch.cuda.Stream()
-    ctx = P.Context(0, stream)
-    probs, ks, fs, Bs, u0s = [], [], [], [], []
-    with torch.cuda.stream(stream):
-        for w in ws_list:
-            q = C.area_share_weights(w.surface)
-            probs.append(P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda()))
-            ks.append(P.kernel_struct(w.kernel_kind, *w.kernel))
-            fs.append(P.Firing(w.beta, torch.from_numpy(w.theta).cuda()))
-            Bs.append(w.b)
-            u0s.append(torch.from_numpy(w.u0.copy()).cuda())
-    torch.cuda.synchronize()
-    batch = P.Batch(ctx, probs, ks, fs, Bs)
-    ws = batch.workspace()
-    states = [u.clone() for u in u0s]
-    t0 = time.perf_counter()
-    best = batch.tune(states, ws)
-    t_tune = time.perf_counter() - t0
-    batch.integrate(states, 0.05, 1, use_graph=True, ws=ws)       # warm-up
-    for s_, u in zip(states, u0s):
-        s_.copy_(u)
-    torch.cuda.synchronize()
-    L = P.lib()
-    t0 = time.perf_counter()
-    batch.integrate(states, 0.05, args.batch_rk4_steps, use_graph=True, ws=ws)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    pair_ints = sum(4.0 * args.batch_rk4_steps * float(w.n) ** 2 * w.b for w in ws_list)
-    # algorithmic slots of the (one-sided) pair kernel per stage: per target-source pair and
-    # state block one evaluation of u (eval_slots: 16 for the Gaussian), plus 1 FMA per
-    # state; blocks of 1, 4 or 16 states
-    slots = 0.0
-    for w in ws_list:
-        npad = -(-w.n // 256) * 256
-        bs = 1 if w.b == 1 else (4 if w.b <= 4 else 16)
-        slots += float(npad) ** 2 * (-(-w.b // bs) * eval_slots(0, 0) + w.b)
-    slots *= 4.0 * args.batch_rk4_steps
-    chunk, wgs = batch.config
-    return {"workload": "48 problems, N log-uniform [1000, 40000], sphere/torus/ellipsoid/bumpy, Gauss Mexican hat, "
-                        "B in {1,4,16}, RK4 dt=0.05 x %d steps, graph-captured" % args.batch_rk4_steps,
-            "value": pair_ints / (t1 - t0), "unit": "pair-interactions/s", "ms_per_integration": (t1 - t0) * 1e3,
-            "roofline": {"bound": "alu", "achieved": slots / (t1 - t0) / 1e12, "peak": VALU_LANES_PER_S / 1e12,
-                         "unit": "Tlane-op/s", "frac": slots / (t1 - t0) / VALU_LANES_PER_S,
-                         "note": "whole integration time (pair kernel, combine, launch gaps)"},
-            "tuned": {"chunk": chunk, "wgs_per_cu": wgs, "best_stage_ms": best, "tune_ms": t_tune * 1e3},
-            "launches_per_rk4_step": 1}
 
 
 def adjoint_leg(P, torch, args):
@@ -495,23 +648,6 @@ def cpu_baseline_quad(surf, q_gpu):
             "max_rel_diff_gpu_vs_oracle": float(np.max(np.abs(q_gpu - q_ref)) / np.max(np.abs(q_ref)))}
 
 
-def cpu_baseline(w, q, gpu_y_rows, rows):
-    """The FP64 oracle's operator on a bounded sample: all sources, a subset of target rows."""
-    from threadpoolctl import threadpool_limits
-
-    from oracle import neural_field as NF
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        ref = NF.apply_K(w.surface.xyz, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows=rows)
-        t1 = time.perf_counter()
-    import numpy as np
-    err = float(np.max(np.abs(gpu_y_rows - ref)) / np.max(np.abs(ref)))
-    return {"value": float(len(rows)) * w.n / (t1 - t0), "unit": "pair-interactions/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "one operator application, %d of %d target rows x all %d sources, FP64 NumPy, 1 thread"
-                      % (len(rows), w.n, w.n)}, err
-
-
 def probes(P, torch, ctx):
     import ctypes
     L = P.lib()
@@ -541,84 +677,60 @@ def probes(P, torch, ctx):
     return out
 
 
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (the path shards by target rows, "
               "see the design notes)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2504_13379_amd as P
-    from workloads import configs as C
 
     if args.probes_only:
         print(json.dumps({"probes": probes(P, torch, P.Context(0))}), flush=True)
         return
-    w = C.torus_exp(32768, steps=args.rk4_steps)
-    q = C.area_share_weights(w.surface)
-    stream = torch.cuda.Stream()
-    torch.cuda.set_stream(stream)
-    ctx = P.Context(0, stream)
-    xyz_t = torch.from_numpy(w.surface.xyz).cuda()
-    q_t = torch.from_numpy(q).cuda()
-    prob = P.Problem(ctx, xyz_t, q_t)
-    u0_t = torch.from_numpy(w.u0.copy()).cuda()
-    torch.cuda.synchronize()
-
-    names = {"otf": P.FORM_ONTHEFLY_FP32, "w32": P.FORM_W_FP32}
-    results = {}
-    for nm in args.forms.split(","):
-        print("bench: form %s, %d warmup + %d timed integrations of %d RK4 steps" % (nm, args.warmup, args.steps,
-              args.rk4_steps), file=sys.stderr, flush=True)
-        results[nm] = run_form(P, torch, prob, w, q_t, names[nm], args, u0_t)
-        print("bench: form %s %.3f ms/step" % (nm, results[nm]["ms_per_step"]), file=sys.stderr, flush=True)
-    best = max(results, key=lambda k: results[k]["value"])
-    r = results[best]
-    kern = (w.kernel_kind,) + tuple(w.kernel)
-    rl = roofline(best, r, w.n, prob.npad, kern)
-
-    forms = {}
-    for nm, rr in results.items():
-        rlf = roofline(nm, rr, w.n, prob.npad, kern)
-        forms[nm] = {"value": rr["value"], "ms_per_step": rr["ms_per_step"], "kernel_avg_ms": rr["kernel_avg_ms"],
-                     "roofline_frac": rlf["frac"]}
-    if len(results) == 2:
-        ua, ub = results["otf"]["u"].cpu().numpy(), results["w32"]["u"].cpu().numpy()
-        forms["otf_vs_w32_rel_linf"] = float(np.max(np.abs(ua - ub)) / np.max(np.abs(ub)))
-
+    w, gold, head, forms = ensemble_headline(P, torch, args)
+    best = head["form"]
     line = {
-        "metric": "kernel pair-interactions/s (RK4 integration, FP32 pair sums, FP64 state)",
-        "value": r["value"],
+        "metric": "kernel pair-interactions/s at stated rel err vs FP64; batched+MFMA vs plain FP32",
+        "value": head["value"],
         "unit": "pair-interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": best.replace("otf_", ""),
         "data": "synthetic",
-        "config": {"workload": "torus R=1 r=0.4, N=32768, exp Mexican hat, B=1, RK4 dt=0.02 x %d steps"
-                               % args.rk4_steps, "form": best, "n": w.n, "B": 1},
-        "roofline": rl,
+        "config": {"workload": "ellipsoid (1,.8,.6), N=65536, B=64 states, Gauss Mexican hat (1,.15,.5,.4), "
+                               "beta=20, theta_b~U(.15,.3), RK4 dt=0.05 x %d steps, FP64 oracle RBF-QF weights"
+                               % w.steps,
+                   "form": best, "n": w.n, "B": w.b, "rk4_steps": w.steps},
+        "rel_linf_vs_fp64": {"max": head["rel_linf_vs_fp64_max"], "per_member": head["rel_linf_vs_fp64"],
+                             "rows": "%d sampled rows per member, normalised by max|u(T)| over all rows"
+                                     % len(gold["rows"])},
+        "roofline": head["roofline"],
+        "launches": head["launches"],
+        "timed": {"times_ms": head["times_ms"], "ms_all_timed": head["ms_all_timed"],
+                  "kernel_avg_ms": head["kernel_avg_ms"]},
         "forms": forms,
     }
+    if "otf_fp32" in forms:
+        line["vs_plain_fp32"] = head["value"] / forms["otf_fp32"]["value"]
     if not args.no_cpu_baseline:
-        rows = np.random.default_rng(7).choice(w.n, 12288, replace=False)
-        y = prob.apply(P.kernel_struct(w.kernel_kind, *w.kernel), P.Firing(w.beta, float(w.theta[0])), u0_t)
-        torch.cuda.synchronize()
-        cb, err = cpu_baseline(w, q, y.cpu().numpy()[:, rows], rows)
-        line["cpu_baseline"] = cb
-        line["rel_err_vs_fp64_sampled_apply"] = err
+        print("bench: CPU baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, gold["q"], 1024)
+    if not args.no_torus:
+        print("bench: torus", file=sys.stderr, flush=True)
+        line["torus"] = torus_leg(P, torch, args)
     if not args.no_small:
         print("bench: small sphere", file=sys.stderr, flush=True)
         line["small"] = small_leg(P, torch, args)
-    if args.ens_rk4_steps > 0:
-        line["ensemble"] = ensemble_leg(P, torch, args)
-    if args.batch_rk4_steps > 0:
+    if not args.no_batch:
         print("bench: uneven batch", file=sys.stderr, flush=True)
         line["batch"] = batch_leg(P, torch, args)
     if args.adjoint_rk4_steps > 0:
@@ -628,7 +740,7 @@ def main():
         print("bench: quadrature weights", file=sys.stderr, flush=True)
         line["quadrature"] = quad_leg(P, torch, args)
     if args.probes:
-        line["probes"] = probes(P, torch, ctx)
+        line["probes"] = probes(P, torch, P.Context(0))
     print(json.dumps(line), flush=True)
 
 
