@@ -455,38 +455,55 @@ struct Rk4Stage {
   const double* gamma;
 };
 
+// Values of element idx = (b, i) that the stage update reads, loaded ahead
+// of time by kernels that can hide their latency behind the pair sum.
+struct Rk4Pre {
+  double v, u, ksum, gamma, q;
+};
+
+__device__ inline Rk4Pre rk4_preload(const Rk4Stage& st, int64_t idx, int64_t i) {
+  Rk4Pre p;
+  p.v = st.v[idx];
+  p.u = st.u[idx];
+  p.ksum = st.stage > 1 ? st.ksum[idx] : 0.0;
+  p.gamma = st.gamma ? st.gamma[idx] : 0.0;
+  p.q = st.with_q ? st.qd[i] : 1.0;
+  return p;
+}
+
+// The update of element idx = (b, i) from its pair sum y (see above), with
+// its operands already loaded.
+__device__ inline void rk4_update_from(const Rk4Stage& st, const Rk4Pre& p, int64_t idx, int b, int64_t i,
+                                       int64_t npad, double y, float* __restrict__ g) {
+  const int stage = st.stage;
+  const double dt = st.dt;
+  const Firing& fr = st.fr;
+  const double k = -p.v + y + p.gamma;
+  double ui = p.u;
+  double vn;
+  if (stage == 1) {
+    if (st.k1_out) st.k1_out[idx] = k;
+    st.ksum[idx] = k;
+    vn = ui + 0.5 * dt * k;
+  } else if (stage == 2) {
+    st.ksum[idx] = p.ksum + 2.0 * k;
+    vn = ui + 0.5 * dt * k;
+  } else if (stage == 3) {
+    st.ksum[idx] = p.ksum + 2.0 * k;
+    vn = ui + dt * k;
+  } else {
+    ui = ui + (dt / 6.0) * (p.ksum + k);
+    st.u[idx] = ui;
+    vn = ui;
+  }
+  st.v[idx] = vn;
+  g[(int64_t)b * npad + i] = (float)(p.q * sigmoid(vn, fr.beta, state_theta(fr, b)));
+}
+
 // The update of element idx = (b, i) from its pair sum y (see above).
 __device__ inline void rk4_update(const Rk4Stage& st, int64_t idx, int b, int64_t i, int64_t npad, double y,
                                   float* __restrict__ g) {
-  const int stage = st.stage;
-  const double dt = st.dt;
-  double* __restrict__ u = st.u;
-  double* __restrict__ v = st.v;
-  double* __restrict__ ksum = st.ksum;
-  double* __restrict__ k1_out = st.k1_out;
-  const double* __restrict__ gamma = st.gamma;
-  const Firing& fr = st.fr;
-  const double k = -v[idx] + y + (gamma ? gamma[idx] : 0.0);
-  double ui = u[idx];
-  double vn;
-  if (stage == 1) {
-    if (k1_out) k1_out[idx] = k;
-    ksum[idx] = k;
-    vn = ui + 0.5 * dt * k;
-  } else if (stage == 2) {
-    ksum[idx] += 2.0 * k;
-    vn = ui + 0.5 * dt * k;
-  } else if (stage == 3) {
-    ksum[idx] += 2.0 * k;
-    vn = ui + dt * k;
-  } else {
-    ui = ui + (dt / 6.0) * (ksum[idx] + k);
-    u[idx] = ui;
-    vn = ui;
-  }
-  v[idx] = vn;
-  const double s = st.with_q ? st.qd[i] : 1.0;
-  g[(int64_t)b * npad + i] = (float)(s * sigmoid(vn, fr.beta, state_theta(fr, b)));
+  rk4_update_from(st, rk4_preload(st, idx, i), idx, b, i, npad, y, g);
 }
 
 template <int L>
@@ -529,6 +546,12 @@ __global__ __launch_bounds__(kWG) void k_otf_small(const float4* __restrict__ sr
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * kSmallRows;
+  // the stage update's operands of this workgroup's targets, loaded now so
+  // their latency hides behind the pair sum
+  const int64_t ti = r0 + threadIdx.x;
+  const bool updater = STAGE && threadIdx.x < kSmallRows && ti < n;
+  Rk4Pre pre{};
+  if (updater) pre = rk4_preload(st, ti, ti);
   float tx[kSmallRows], ty[kSmallRows], tz[kSmallRows], acc[kSmallRows];
 #pragma unroll
   for (int r = 0; r < kSmallRows; ++r) {
@@ -584,10 +607,10 @@ __global__ __launch_bounds__(kWG) void k_otf_small(const float4* __restrict__ sr
     const int64_t i = r0 + threadIdx.x;
     if (!STAGE) {
       part[i] = pp.amp * y;
-    } else if (i < n) {
+    } else if (updater) {
       double ys = 0.0;            // as slot_total adds the single slot
       ys += pp.amp * y;
-      rk4_update(st, i, 0, i, npad, ys, g_next);
+      rk4_update_from(st, pre, i, 0, i, npad, ys, g_next);
     } else {
       g_next[i] = 0.0f;           // padding sources stay zero in both buffers
     }
