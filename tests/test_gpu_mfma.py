@@ -88,6 +88,8 @@ def test_mfma_full_size_ellipsoid_sampled_rows(ctx, form):
     y = _apply(ctx, x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, form)
     ref = NF.apply_K(x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows=rows)
     err = np.max(np.abs(y[:, rows] - ref) / _scale(x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows))
+    print("split W form %d, N = %d, B = %d: one application, max |dy| / S over 24 rows = %.3e" % (form, w.n, w.b, err),
+          flush=True)
     assert err <= TOL_APPLY[form], err
 
 
