@@ -3,8 +3,7 @@
 // combine launch per RK4 stage for the whole batch.
 //
 // Work items are (problem, target tile of kWG * batch_tpt(bs) targets, source
-// chunk, state block), or for single-state problems (problem, symmetric tile
-// pair); they are sorted by decreasing cost on the host and a fixed grid of
+// chunk, state block); they are sorted by decreasing cost on the host and a fixed grid of
 // workgroups walks them round-robin, so every stage is a single launch whose
 // largest items start first.
 #pragma once
@@ -19,7 +18,6 @@ struct BatchProblemDev {
   const double* q;
   int64_t n, npad;
   int B, bs, kind, nsplit;   // kind: pair-kernel code (kernel kind, + 2 if periodic)
-  int sym;                   // 1: single state, symmetric tile pairs (nsplit = tiles of kSymTile)
   int64_t chunk;
   PairParams pp;
   Firing fr;
@@ -32,8 +30,6 @@ struct BatchProblemDev {
   int64_t gel_off;    // prefix sum of npad * B
 };
 
-// One work item: a target tile, source chunk and state block of problem p;
-// for a symmetric problem `tile` is the index of a tile pair (I <= J).
 struct BatchItem {
   int p;
   int tile;
@@ -56,22 +52,8 @@ __host__ __device__ constexpr int batch_bs(int B) { return B == 1 ? 1 : (B <= 4 
 #endif
 __host__ __device__ constexpr int batch_tpt(int bs) { return bs == 16 ? NFR_BATCH_TPT16 : otf_tpt(bs); }
 
-// Single-state problems take the symmetric tile pairs of k_otf_sym (one
-// kernel evaluation per unordered pair, row sums to slot J of the nodes of I,
-// column sums to slot I of the nodes of J), the others the one-sided tiles.
 template <int KIND>
-__device__ inline void batch_item(const BatchProblemDev& P, const BatchItem& w, float4* s_src, float (*s_g)[kWG],
-                                  double (*rowsum)[kSymTile]) {
-  if (P.sym) {
-    int64_t I, J;
-    sym_decode(w.tile, &I, &J);
-    if (I == J)
-      sym_tile<KIND, false, kSymTPT, kSymSplit>(P.src, P.g, P.npad, P.pp, P.part, I, J, rowsum);
-    else
-      sym_tile<KIND, true, kSymTPT, kSymSplit>(P.src, P.g, P.npad, P.pp, P.part, I, J, rowsum);
-    __syncthreads();   // rowsum is read at the end of the tile; the next item rewrites it
-    return;
-  }
+__device__ inline void batch_item(const BatchProblemDev& P, const BatchItem& w, float4* s_src, float (*s_g)[kWG]) {
   if (P.bs == 1)
     otf_tile<KIND, batch_tpt(1), 1>(P.src, P.g, P.npad, P.B, P.chunk, P.pp, P.part, w.tile, w.split, w.sb, s_src, s_g);
   else if (P.bs == 4)
@@ -82,21 +64,18 @@ __device__ inline void batch_item(const BatchProblemDev& P, const BatchItem& w, 
                                     s_src, s_g);
 }
 
-static_assert(kSymThreads == kWG, "a symmetric tile pair takes the batch kernel's whole workgroup");
-
 __global__ __launch_bounds__(kWG) void k_batch_pairs(const BatchProblemDev* __restrict__ probs,
                                                      const BatchItem* __restrict__ items, int nitems) {
   __shared__ float4 s_src[kWG];
   __shared__ float s_g[16][kWG];
-  __shared__ double rowsum[kSymSplit][kSymTile];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const BatchItem w = items[it];
     const BatchProblemDev& P = probs[w.p];
     switch (P.kind) {
-      case 0: batch_item<0>(P, w, s_src, s_g, rowsum); break;
-      case 1: batch_item<1>(P, w, s_src, s_g, rowsum); break;
-      case 2: batch_item<2>(P, w, s_src, s_g, rowsum); break;
-      default: batch_item<3>(P, w, s_src, s_g, rowsum); break;
+      case 0: batch_item<0>(P, w, s_src, s_g); break;
+      case 1: batch_item<1>(P, w, s_src, s_g); break;
+      case 2: batch_item<2>(P, w, s_src, s_g); break;
+      default: batch_item<3>(P, w, s_src, s_g); break;
     }
   }
 }

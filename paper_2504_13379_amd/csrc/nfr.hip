@@ -1324,19 +1324,10 @@ struct BatchLayout {
   size_t max_items = 0;
 };
 
-// Single-state problems of a batch use symmetric tile pairs of kSymTile nodes.
-int64_t batch_sym_tiles(const nfr_problem* p) { return ceil_div(p->view.npad, (int64_t)kSymTile); }
-
 int64_t batch_items_for(const nfr_problem* p, int B, int64_t chunk) {
   const int64_t npad = p->view.npad;
-  if (B == 1) return sym_pairs(batch_sym_tiles(p));
   const int bs = batch_bs(B);
   return ceil_div(npad, (int64_t)kWG * batch_tpt(bs)) * ceil_div(npad, chunk) * ceil_div(B, bs);
-}
-
-// Partial-sum slots per node and state: source chunks, or tiles (symmetric problems).
-int64_t batch_slots_max(const nfr_problem* p, int B) {
-  return B == 1 ? batch_sym_tiles(p) : ceil_div(p->view.npad, kBatchMinChunk);
 }
 
 BatchLayout batch_layout(const nfr_batch* b) {
@@ -1354,7 +1345,7 @@ BatchLayout batch_layout(const nfr_batch* b) {
     L.g_off.push_back(off);
     off += align256(size_t(pv.npad) * Bp * sizeof(float));
     L.part_off.push_back(off);
-    off += align256(size_t(batch_slots_max(b->probs[p], Bp)) * Bp * pv.npad * sizeof(double));
+    off += align256(size_t(ceil_div(pv.npad, kBatchMinChunk)) * Bp * pv.npad * sizeof(double));
     L.v_off.push_back(off);
     off += align256(size_t(pv.n) * Bp * sizeof(double));
     L.ksum_off.push_back(off);
@@ -1384,8 +1375,7 @@ void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_
     const nfr_kernel kn = norm_kernel(b->kernels[p]);
     d.kind = kind_code(kn, pv);
     d.chunk = b->chunk;
-    d.sym = Bp == 1 ? 1 : 0;
-    d.nsplit = d.sym ? (int)batch_sym_tiles(b->probs[p]) : (int)ceil_div(pv.npad, b->chunk);
+    d.nsplit = (int)ceil_div(pv.npad, b->chunk);
     d.pp = pair_params(kn, pv);
     d.fr = firing_of(b->firings[p]);
     d.g = reinterpret_cast<float*>(ws + L.g_off[p]);
@@ -1397,21 +1387,6 @@ void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_
     d.gel_off = goff;
     eoff += pv.n * Bp;
     goff += pv.npad * Bp;
-    const double per_eval = ((d.kind & 1) ? 1.3 : 1.0) + ((d.kind & 2) ? 0.2 : 0.0);
-    if (d.sym) {
-      // tile pair (I, J): every pair of the two tiles evaluated once (plus a
-      // column accumulation off the diagonal)
-      // (pair index J (J + 1) / 2 + I, as sym_decode reads it)
-      const int64_t nt = batch_sym_tiles(b->probs[p]);
-      for (int64_t J = 0; J < nt; ++J) {
-        const double nsrc = (double)std::min<int64_t>(kSymTile, pv.npad - J * kSymTile);
-        for (int64_t I = 0; I <= J; ++I) {
-          b->items.push_back(BatchItem{p, (int)(J * (J + 1) / 2 + I), -1, 0});
-          cost.push_back((double)kSymTile * nsrc * (per_eval + 0.25));
-        }
-      }
-      continue;
-    }
     const int tpt = batch_tpt(d.bs);
     const int64_t tiles = ceil_div(pv.npad, (int64_t)kWG * tpt);
     const int sbs = (int)ceil_div(Bp, d.bs);
@@ -1421,7 +1396,7 @@ void batch_build(nfr_batch* b, const BatchLayout& L, char* ws, double* const* u_
           const double tg = (double)std::min<int64_t>(kWG * tpt, pv.npad - t * kWG * tpt);
           const double sc = (double)std::min<int64_t>(b->chunk, pv.npad - sp * b->chunk);
           const double st = (double)std::min(d.bs, Bp - sb * d.bs);
-          const double per_pair = per_eval + 0.25 * (st - 1.0);
+          const double per_pair = ((d.kind & 1) ? 1.3 : 1.0) + ((d.kind & 2) ? 0.2 : 0.0) + 0.25 * (st - 1.0);
           b->items.push_back(BatchItem{p, (int)t, sp, sb});
           cost.push_back(tg * sc * per_pair);
         }
