@@ -72,12 +72,35 @@ def slots_per_unordered_pair(kind, m):
     return eval_slots(kind, m) + 2
 
 
-def fused_slots_per_w(kind, m, fp16=False):
+def fused_slots_per_w(kind, m, fp16=False, norm=False):
     """Slots per W entry of the fused on-the-fly split forms: the evaluation of u
     above (the weights sit in G), and 3 for the hi/lo split (two conversions of a pair of entries at half a slot each, the hi value
     back to FP32, the subtraction); FP16 adds the lift of u (its 2^11 remainder
-    scaling fuses into the subtraction)."""
-    return eval_slots(kind, m) + 3 + (1 if fp16 else 0)
+    scaling fuses into the subtraction).  With the norm expansion of r^2 (BF16,
+    see fused_norm_path) the 3 subtractions, the square and 2 multiply-adds of
+    r^2 are 3 multiply-adds, the row's |x_i|^2 being a row factor: 3 slots fewer."""
+    return eval_slots(kind, m) - (3 if norm else 0) + 3 + (1 if fp16 else 0)
+
+
+# The fused BF16 kernel evaluates r^2 of Gaussian kernels on non-periodic
+# surfaces by the norm expansion while sig^2 max|x|^2, for the steeper of the
+# two exponentials, is at most this bound.
+NORM_MAX_T = 96.0
+
+
+def fused_norm_path(kind, kernel, m, max_r2):
+    """Whether the fused BF16 kernel takes the norm expansion for this Gaussian or
+    exponential kernel on a non-periodic surface with max |x|^2 = max_r2 (of the
+    FP32 coordinates)."""
+    import math
+    if kind != 0:
+        return False
+    s_e, s_i = kernel[1], kernel[3]
+    if m:
+        sig2, steep = math.log2(math.e) / (s_i * s_i), m
+    else:
+        sig2, steep = math.log2(math.e) / (s_e * s_e), max(1.0, (s_e / s_i) ** 2)
+    return sig2 * steep * max_r2 <= NORM_MAX_T
 
 
 def sym_kernel_name(kind, m, periodic=False):
@@ -183,7 +206,7 @@ ENS_FORMS = {"otf_bf16x3": 4, "bf16x3": 2, "otf_fp16x3": 5, "fp16x3": 3, "otf_fp
 SPLIT_FORMS = ("otf_bf16x3", "bf16x3", "otf_fp16x3", "fp16x3")
 
 
-def ensemble_roofline(nm, npad, kind, kernel, avg_s):
+def ensemble_roofline(nm, npad, kind, kernel, avg_s, max_r2):
     """Roofline of the dominant (pair-sum) kernel of form `nm` at one launch per operator application."""
     m = sym_pow(kind, kernel[1], kernel[3])
     if nm in ("bf16x3", "fp16x3"):
@@ -209,13 +232,15 @@ def ensemble_roofline(nm, npad, kind, kernel, avg_s):
     # fused on-the-fly split forms: every W entry evaluated once per launch on the vector
     # units; the matrix cores do 3 products x 2 flop x 64 states per entry
     fp16 = nm == "otf_fp16x3"
+    norm = not fp16 and fused_norm_path(kind, kernel, m, max_r2)
     kname = "k_mfma_otf<%s,%d,2>" % ("fp16" if fp16 else "bf16", kind + 4 * (m - 1 if m else 0))
     wvals = float(npad) ** 2
-    achieved = wvals * fused_slots_per_w(kind, m, fp16) / avg_s
+    spw = fused_slots_per_w(kind, m, fp16, norm)
+    achieved = wvals * spw / avg_s
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tslot/s",
             "frac": achieved / VALU_LANES_PER_S, "traffic": measured_traffic(kname), "kernel": kname,
-            "slots_per_w": fused_slots_per_w(kind, m, fp16), "mfma_tflops": wvals * 384.0 / avg_s / 1e12,
-            "mfma_frac": wvals * 384.0 / avg_s / MFMA_BF16_PEAK}
+            "slots_per_w": spw, "r2": "norm expansion" if norm else "differences",
+            "mfma_tflops": wvals * 384.0 / avg_s / 1e12, "mfma_frac": wvals * 384.0 / avg_s / MFMA_BF16_PEAK}
 
 
 def ensemble_headline(P, torch, args):
@@ -230,6 +255,9 @@ def ensemble_headline(P, torch, args):
     assert w.n == int(gold["n"])
     compare = w.steps == int(gold["steps"])
     rows, ref_rows, ref_max = gold["rows"], gold["uT_rows"], gold["uT_absmax"]
+    # max |x|^2 of the FP32 coordinates, as the library's problem packing computes it
+    xf = w.surface.xyz.astype(np.float32).astype(np.float64)
+    max_r2 = float(np.max(np.sum(xf * xf, axis=1).astype(np.float32)))
 
     def member_err():
         if not compare:
@@ -278,7 +306,7 @@ def ensemble_headline(P, torch, args):
         forms[nm] = {"value": pairs / sec, "unit": "pair-interactions/s", "ms_per_integration": sec * 1e3,
                      "w_build_ms": t_build * 1e3, "kernel_avg_ms": avg_ms, **lps,
                      "rel_linf_vs_fp64_max": finite(err.max()), "rel_linf_vs_fp64_median": finite(np.median(err)),
-                     "roofline": ensemble_roofline(nm, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3)}
+                     "roofline": ensemble_roofline(nm, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3, max_r2)}
         keep[nm] = err
         del W
         torch.cuda.empty_cache()
@@ -316,7 +344,7 @@ def ensemble_headline(P, torch, args):
             "times_ms": [t * 1e3 for t in times], "kernel_avg_ms": avg_ms, "kernel_launches_timed": n_l,
             "timed_launch": "directly launched (HIP events around each pair-sum launch)",
             "rel_linf_vs_fp64": [finite(e) for e in err], "rel_linf_vs_fp64_max": finite(err.max()),
-            "roofline": ensemble_roofline(best, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3),
+            "roofline": ensemble_roofline(best, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3, max_r2),
             "launches": launches_per_step(P, ctx)}
     del W
     torch.cuda.empty_cache()

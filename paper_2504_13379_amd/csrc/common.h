@@ -13,7 +13,7 @@ constexpr int kPad = 256;       // node padding granule
 constexpr double kLog2e = 1.4426950408889634074;
 
 // Device-side view of a packed problem.  Layout inside the caller's buffer:
-//   float4 src[npad]   (x, y, z, 0) in FP32
+//   float4 src[npad]   (x, y, z, |x|^2) in FP32 (|x|^2 = 0 when periodic)
 //   double q[npad]     quadrature weights, 0 on padding nodes
 //   double xyz[3*npad] FP64 coordinates (row-major), 0 on padding nodes
 // A periodic problem (period > 0) has its (x, y) plane doubly periodic with
@@ -25,7 +25,7 @@ struct ProblemView {
   const float4* src = nullptr;
   const double* q = nullptr;
   const double* xyz = nullptr;
-  const double* qmax = nullptr;   // max_j |q_j| (one FP64 value on the device)
+  const double* qmax = nullptr;   // on the device: [0] max_j |q_j|, [1] max_j |x_j|^2 (FP32 coordinates)
 };
 
 // Kernel evaluation in the on-the-fly pair sum.  Coordinates are multiplied by

@@ -16,7 +16,9 @@ namespace nfr {
 // FP64 coordinates, each padded to npad with zeros (weight 0: padding sources
 // never contribute; padding targets are computed and discarded).  With
 // period > 0, x and y are first reduced by whole periods to [-period/2,
-// period/2] (the same points of the periodic plane).
+// period/2] (the same points of the periodic plane).  The fourth component is
+// the squared norm of the FP32 coordinates, rounded once from FP64 (0 with
+// period > 0), for kernels that expand r^2 = |x_i|^2 + |x_j|^2 - 2 x_i . x_j.
 __global__ __launch_bounds__(kWG) void k_pack(const double* __restrict__ xyz, const double* __restrict__ q,
                                               int64_t n, int64_t npad, double period, float4* __restrict__ src,
                                               double* __restrict__ qd, double* __restrict__ xyz64) {
@@ -33,25 +35,39 @@ __global__ __launch_bounds__(kWG) void k_pack(const double* __restrict__ xyz, co
       y -= period * rint(y / period);
     }
   }
-  src[i] = make_float4((float)x, (float)y, (float)z, 0.0f);
+  const float xf = (float)x, yf = (float)y, zf = (float)z;
+  const double nrm = period > 0.0 ? 0.0 : (double)xf * xf + (double)yf * yf + (double)zf * zf;
+  src[i] = make_float4(xf, yf, zf, (float)nrm);
   qd[i] = w;
   xyz64[3 * i + 0] = x;
   xyz64[3 * i + 1] = y;
   xyz64[3 * i + 2] = z;
 }
 
-// qmax[0] = max_j |q_j| over the npad packed weights (one workgroup).
-__global__ __launch_bounds__(kWG) void k_qmax(const double* __restrict__ qd, int64_t npad, double* __restrict__ qmax) {
-  __shared__ double red[kWG];
-  double m = 0.0;
-  for (int64_t j = threadIdx.x; j < npad; j += kWG) m = fmax(m, fabs(qd[j]));
-  red[threadIdx.x] = m;
+// qmax[0] = max_j |q_j| and qmax[1] = max_j |x_j|^2 (the packed FP32 norms) over
+// the npad packed nodes (one workgroup).
+__global__ __launch_bounds__(kWG) void k_qmax(const double* __restrict__ qd, const float4* __restrict__ src, int64_t npad,
+                                              double* __restrict__ qmax) {
+  __shared__ double red[2][kWG];
+  double m = 0.0, r = 0.0;
+  for (int64_t j = threadIdx.x; j < npad; j += kWG) {
+    m = fmax(m, fabs(qd[j]));
+    r = fmax(r, (double)src[j].w);
+  }
+  red[0][threadIdx.x] = m;
+  red[1][threadIdx.x] = r;
   __syncthreads();
   for (int s = kWG / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) qmax[0] = red[0];
+  if (threadIdx.x == 0) {
+    qmax[0] = red[0][0];
+    qmax[1] = red[1][0];
+  }
 }
 
 // ------------------------------------------------------------------ sources

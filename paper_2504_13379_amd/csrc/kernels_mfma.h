@@ -399,7 +399,7 @@ struct MfmaOtfParams {
   float sig, rho, per;
   float kappa;         // -A_i / A_e (PairParams)
   double amp;          // A_e
-  const double* qmax;  // max_j |q_j| (for the FP16 source lift sG)
+  const double* qmax;  // [0] max_j |q_j| (FP16 source lift sG), [1] max_j |x_j|^2 (norm expansion)
 };
 
 #ifndef NFR_MFMA_OTF_MIN_WGS
@@ -416,6 +416,25 @@ struct MfmaOtfParams {
 #ifndef NFR_MFMA_OTF_FP16_LDS_BUFS
 #define NFR_MFMA_OTF_FP16_LDS_BUFS 2
 #endif
+// Gaussian kernels on non-periodic surfaces (BF16) evaluate t = sig^2 r^2 by
+// the norm expansion sig^2 (|x_i|^2 + |x_j|^2 - 2 x_i . x_j): three
+// multiply-adds against staged column values (-2 sig^2 x_j, sig^2 |x_j|^2),
+// the row's sig^2 |x_i|^2 folded into a row factor, instead of three
+// subtractions and three multiply-adds (13 -> 10 vector instructions per
+// entry).  Its
+// partial sums reach sig^2 (|x_i| + |x_j|)^2, so its rounding error in t is
+// absolute, a few units in the last place of that size rather than of t:
+// the expansion is taken only while sig^2 max_j |x_j|^2 <= kNormMaxT (for
+// the steeper of the kernel's two exponentials).  There,
+// for the entries that matter (t up to a few tens), the column values' and
+// norms' roundings (at most 1.1e-5 and 1.1e-5 in t) and the three
+// multiply-adds' (partial sums near sig^2 |x|^2: 1.1e-5) keep t within 4e-5,
+// i.e. an entry within 3e-5 of itself; larger coordinates (relative to the
+// kernel's width) take the differences.
+#ifndef NFR_MFMA_OTF_NORM
+#define NFR_MFMA_OTF_NORM 1
+#endif
+constexpr double kNormMaxT = 96.0;
 template <typename T, int KIND, int NB>
 __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
                                                      const T* __restrict__ Glo, int64_t npad, int B, int64_t kchunk,
@@ -427,10 +446,14 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
   constexpr int ROWCH = kMfmaStep / 8;
   constexpr int CHUNKS = NS * 2 * ROWCH / kWG;
   constexpr int kOtfBufs = kTwoAcc ? NFR_MFMA_OTF_FP16_LDS_BUFS : NFR_MFMA_OTF_BF16_LDS_BUFS;
+  constexpr bool kNormCapable = (KIND & 3) == 0 && !kTwoAcc && NFR_MFMA_OTF_NORM;
   __shared__ __attribute__((aligned(16))) T sG[kOtfBufs][2][NS][kMfmaLdsStride];
-  // column coordinates x, y, z (row 3: the packed zero component); wave w
-  // loads and stores row w, so no load sits behind a branch
+  // column values: rows 0-2 the coordinates scaled by sig (norm expansion:
+  // by -2 sig^2), row 3 unused (norm expansion: sig^2 |x_j|^2); wave w loads
+  // and stores row w, so no load sits behind a branch
   __shared__ __attribute__((aligned(16))) float sS[kOtfBufs][4][kMfmaStep];
+  // norm expansion: row factors of the wave's 32 rows, applied in the epilogue
+  __shared__ double sR[4][32];
   static_assert(kWG == 4 * 64, "one wave per coordinate row");
 
   const int64_t wg = blockIdx.x;
@@ -452,7 +475,7 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
   const int sU = mfma_scale_exp(1.0 + fabs((double)op.kappa), kTwoAcc);
   const float lift = (float)ldexp(1.0, sU);
   const float4 pr = src[row0 + m];
-  const float xi = pr.x * op.sig, yi = pr.y * op.sig, zi = pr.z * op.sig;
+  const double s2d = (double)op.sig * op.sig;
 
   const T* gsrc[CHUNKS];
   int g_hl[CHUNKS], g_st[CHUNKS], g_col[CHUNKS];
@@ -482,40 +505,6 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     for (int q = 0; q < CHUNKS; ++q) gn[q] = *reinterpret_cast<const u32x4_t*>(gsrc[q] + tc * kMfmaStep);
     sn = reinterpret_cast<const float*>(src + k_begin + tc * kMfmaStep + lane)[wave];
   };
-  auto store_next = [&](int t) {
-    const int buf = t % kOtfBufs;
-#pragma unroll
-    for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[buf][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
-    sS[buf][wave][lane] = sn * op.sig;
-  };
-  auto eval = [&](int buf, int kb, V& whi, V& wlo) {
-    const int col = 16 * kb + 8 * h;
-    float w[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float r2 = pair_r2<KIND>(xi - sS[buf][0][col + e], yi - sS[buf][1][col + e], zi - sS[buf][2][col + e],
-                                     op.per);
-      const float tt = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
-      w[e] = pair_u<KIND>(tt, op.rho, op.kappa);
-      if (kTwoAcc) w[e] *= lift;
-    }
-    // split pairwise: one conversion instruction rounds two entries
-#pragma unroll
-    for (int e = 0; e < 8; e += 2) {
-      typedef __attribute__((ext_vector_type(2))) float f2_t;
-      typedef __attribute__((ext_vector_type(2))) T h2_t;
-      const f2_t wv = {w[e], w[e + 1]};
-      const h2_t hv = __builtin_convertvector(wv, h2_t);
-      const f2_t hf = __builtin_convertvector(hv, f2_t);
-      f2_t rv = wv - hf;
-      if (c) rv *= (float)(1 << c);
-      const h2_t lv = __builtin_convertvector(rv, h2_t);
-      whi[e] = hv[0];
-      whi[e + 1] = hv[1];
-      wlo[e] = lv[0];
-      wlo[e + 1] = lv[1];
-    }
-  };
   auto mma = [&](int buf, int kb, const V& whi, const V& wlo) {
     const int col = 16 * kb + 8 * h;
 #pragma unroll
@@ -532,35 +521,113 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
       }
     }
   };
-  auto compute = [&](int t) {
-    const int buf = t % kOtfBufs;
-    V h0, l0, h1, l1;
-    eval(buf, 0, h0, l0);
+  // The whole pipeline for one way of evaluating t (kNorm: norm expansion).
+  auto run = [&](auto norm_tag) {
+    constexpr bool kNorm = decltype(norm_tag)::value;
+    const float xi = kNorm ? pr.x : pr.x * op.sig, yi = kNorm ? pr.y : pr.y * op.sig,
+                zi = kNorm ? pr.z : pr.z * op.sig;
+    // norm expansion: the row's sig^2 |x_i|^2 and the column values rounded
+    // once from FP64 (wave-uniform scale: -2 sig^2 for rows 0-2, sig^2 for 3)
+    // norm expansion: t = n_i + a with n_i = sig^2 |x_i|^2 and a the sum of the
+    // three multiply-adds.  The row's n_i is folded into a row factor: with
+    // e = exp2(-t) = 2^-n_i exp2(-a), u = R_i u'(a), where u' is u with kappa
+    // replaced by kappa_i (R_i = 2^-n_i, kappa_i = kappa 2^((1 - rho) n_i);
+    // length ratio 1/m: R_i = 2^-m n_i, kappa_i = kappa 2^((m - 1) n_i)), so
+    // an entry needs no add for n_i.  u' stays below (1 + |kappa|) 2^96 (the
+    // bound on the steeper exponent's n_i), inside FP32 and BF16 range.
+    const double ni = s2d * ((double)pr.x * pr.x + (double)pr.y * pr.y + (double)pr.z * pr.z);
+    float kap = op.kappa;
+    if (kNorm) {
+      constexpr int M = sym_pow<KIND>();
+      kap = (float)((double)op.kappa * (M ? exp2((M - 1) * ni) : exp2((1.0 - (double)op.rho) * ni)));
+      if (h == 0) sR[wave][m] = M ? exp2(-M * ni) : exp2(-ni);
+    }
+    const double wsd = wave < 3 ? -2.0 * s2d : s2d;
+    auto store_next = [&](int t) {
+      const int buf = t % kOtfBufs;
 #pragma unroll
-    for (int kb = 0; kb < kMfmaKb; kb += 2) {
-      if (kb + 1 < kMfmaKb) eval(buf, kb + 1, h1, l1);
-      mma(buf, kb, h0, l0);
-      if (kb + 2 < kMfmaKb) eval(buf, kb + 2, h0, l0);
-      if (kb + 1 < kMfmaKb) mma(buf, kb + 1, h1, l1);
+      for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[buf][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
+      sS[buf][wave][lane] = kNorm ? (float)((double)sn * wsd) : sn * op.sig;
+    };
+    auto eval = [&](int buf, int kb, V& whi, V& wlo) {
+      const int col = 16 * kb + 8 * h;
+      float w[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float tt;
+        if (kNorm) {
+          tt = fmaf(xi, sS[buf][0][col + e], fmaf(yi, sS[buf][1][col + e], fmaf(zi, sS[buf][2][col + e], sS[buf][3][col + e])));
+        } else {
+          const float r2 = pair_r2<KIND>(xi - sS[buf][0][col + e], yi - sS[buf][1][col + e],
+                                         zi - sS[buf][2][col + e], op.per);
+          tt = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
+        }
+        w[e] = pair_u<KIND>(tt, op.rho, kap);
+        if (kTwoAcc) w[e] *= lift;
+      }
+      // split pairwise: one conversion instruction rounds two entries
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        typedef __attribute__((ext_vector_type(2))) float f2_t;
+        typedef __attribute__((ext_vector_type(2))) T h2_t;
+        const f2_t wv = {w[e], w[e + 1]};
+        const h2_t hv = __builtin_convertvector(wv, h2_t);
+        const f2_t hf = __builtin_convertvector(hv, f2_t);
+        f2_t rv = wv - hf;
+        if (c) rv *= (float)(1 << c);
+        const h2_t lv = __builtin_convertvector(rv, h2_t);
+        whi[e] = hv[0];
+        whi[e + 1] = hv[1];
+        wlo[e] = lv[0];
+        wlo[e + 1] = lv[1];
+      }
+    };
+    auto compute = [&](int t) {
+      const int buf = t % kOtfBufs;
+      V h0, l0, h1, l1;
+      eval(buf, 0, h0, l0);
+#pragma unroll
+      for (int kb = 0; kb < kMfmaKb; kb += 2) {
+        if (kb + 1 < kMfmaKb) eval(buf, kb + 1, h1, l1);
+        mma(buf, kb, h0, l0);
+        if (kb + 2 < kMfmaKb) eval(buf, kb + 2, h0, l0);
+        if (kb + 1 < kMfmaKb) mma(buf, kb + 1, h1, l1);
+      }
+    };
+    // step t: issue the loads of step t + 1, evaluate and multiply step t from
+    // LDS buffer t % kOtfBufs, (one buffer: barrier), store step t + 1 into the
+    // next buffer, barrier.
+    if (nsteps > 0) {
+      load_next(0);
+      store_next(0);
+      __syncthreads();
+      for (int t = 0; t < nsteps; ++t) {
+        load_next(t + 1);
+        // keep the prefetch at the top: left to itself the scheduler sinks it
+        // to just before its LDS store, exposing its latency every step
+        __builtin_amdgcn_sched_barrier(0);
+        compute(t);
+        if (kOtfBufs == 1) __syncthreads();
+        store_next(t + 1);
+        __syncthreads();
+      }
     }
   };
-  // step t: issue the loads of step t + 1, evaluate and multiply step t from
-  // LDS buffer t % kOtfBufs, (one buffer: barrier), store step t + 1 into the
-  // next buffer, barrier.
-  if (nsteps > 0) {
-    load_next(0);
-    store_next(0);
-    __syncthreads();
-    for (int t = 0; t < nsteps; ++t) {
-      load_next(t + 1);
-      // keep the prefetch at the top: left to itself the scheduler sinks it
-      // to just before its LDS store, exposing its latency every step
-      __builtin_amdgcn_sched_barrier(0);
-      compute(t);
-      if (kOtfBufs == 1) __syncthreads();
-      store_next(t + 1);
-      __syncthreads();
-    }
+  bool norm = false;
+  if constexpr (kNormCapable) {
+    // qmax[1] = max_j |x_j|^2 of the problem's FP32 coordinates; the bound
+    // holds for the steeper exponent, m t (kernels with a length ratio 1/m)
+    // or max(1, rho) t
+    constexpr int M = sym_pow<KIND>();
+    const double steep = M ? (double)M : fmax(1.0, (double)op.rho);
+    norm = s2d * steep * op.qmax[1] <= kNormMaxT;
+    if (norm)
+      run(std::true_type{});
+    else
+      run(std::false_type{});
+    __syncthreads();   // the row factors in sR
+  } else {
+    run(std::false_type{});
   }
 
   const int sG_ = mfma_scale_exp(op.qmax[0], kTwoAcc);
@@ -573,8 +640,10 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     double* dst = part + ((int64_t)split * B + b) * npad;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int64_t i = row0 + 8 * (r / 4) + 4 * h + (r % 4);
-      dst[i] = kTwoAcc ? (double)accM[nb][r] * sm + (double)accC[nb][r] * sc : (double)accM[nb][r] * sm;
+      const int ir = 8 * (r / 4) + 4 * h + (r % 4);
+      const int64_t i = row0 + ir;
+      const double y = kTwoAcc ? (double)accM[nb][r] * sm + (double)accC[nb][r] * sc : (double)accM[nb][r] * sm;
+      dst[i] = norm ? y * sR[wave][ir] : y;
     }
   }
 }

@@ -821,7 +821,8 @@ int nfr_problem_create_periodic(nfr_context* ctx, int64_t n, const double* xyz_d
   p->view.qmax = reinterpret_cast<const double*>(reinterpret_cast<const char*>(p->view.xyz) + align256(3 * npad * sizeof(double)));
   hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, ctx->stream, xyz_dev, q_dev, n, npad, period,
                      const_cast<float4*>(p->view.src), const_cast<double*>(p->view.q), const_cast<double*>(p->view.xyz));
-  hipLaunchKernelGGL(k_qmax, dim3(1), dim3(kWG), 0, ctx->stream, p->view.q, npad, const_cast<double*>(p->view.qmax));
+  hipLaunchKernelGGL(k_qmax, dim3(1), dim3(kWG), 0, ctx->stream, p->view.q, p->view.src, npad,
+                     const_cast<double*>(p->view.qmax));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     delete p;

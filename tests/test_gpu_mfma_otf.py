@@ -6,10 +6,13 @@ Tolerances add the two error sources already bounded for the other forms
 (norm-wise against S_i = sum_j |w_ij q_j f(u_j)|):
 * the FP32 evaluation of each W entry, as in the on-the-fly FP32 form
   (coordinate, difference, exp2 roundings; also the scaled period):
-  |dy_i| <= 1e-5 S_i;
+  |dy_i| <= 1e-5 S_i; the BF16 form evaluates Gaussian kernels on
+  non-periodic surfaces by the norm expansion of r^2 while sig^2 max|x|^2
+  <= 96 (for the steeper exponential), whose roundings keep each entry within
+  3e-5 of itself;
 * the hi/lo split of W and f(u) with FP32 accumulation, as in the W_* split
   forms: 3e-5 S_i (BF16), 2e-6 S_i (FP16).
-Hence 4e-5 (BF16) and 1.2e-5 (FP16) for one application; trajectories
+Hence 6e-5 (BF16) and 1.2e-5 (FP16) for one application; trajectories
 u(T): 1e-4 (BF16, the split-BF16 target) and 2e-5 (FP16: the FP32 path's
 1e-5 plus the split form's 1e-5) relative L-infinity per state.
 """
@@ -30,7 +33,7 @@ P = pytest.importorskip("paper_2504_13379_amd")
 
 GAUSS = (1.0, 0.15, 0.5, 0.4)
 EXPK = (2.0, 0.1, 1.0, 0.3)
-TOL_APPLY = {4: 4e-5, 5: 1.2e-5}
+TOL_APPLY = {4: 6e-5, 5: 1.2e-5}
 TOL_STATE = {4: 1e-4, 5: 2e-5}
 L = 2.0 * math.pi
 
@@ -69,6 +72,7 @@ def test_fused_apply_matches_oracle(ctx, form, n, B, kind):
     y = _apply(ctx, x, q, U, kind, p, 20.0, theta, form)
     ref = NF.apply_K(x, q, U, kind, p, 20.0, theta)
     err = np.max(np.abs(y - ref) / _scale(x, q, U, kind, p, 20.0, theta))
+    print("fused form %d, kind %d, n = %d, B = %d: max |dy| / S = %.3e" % (form, kind, n, B, err), flush=True)
     assert err <= TOL_APPLY[form], err
 
 
@@ -123,8 +127,8 @@ def test_fused_fp16_scaling_handles_tiny_weights(ctx):
 
 
 def test_fused_matches_w_form_of_same_precision(ctx):
-    """Same products as the BF16 W form; they differ only by the FP32 (fused)
-    against FP64 (W build) evaluation of W before the split."""
+    """Same products as the BF16 W form; they differ only by the FP32 (fused,
+    norm expansion) against FP64 (W build) evaluation of W before the split."""
     n, B = 2000, 64
     rng = np.random.default_rng(5)
     x = S.fibonacci_sphere(n)
@@ -140,7 +144,27 @@ def test_fused_matches_w_form_of_same_precision(ctx):
     yf2 = prob.apply(k, f, u, form=4).cpu().numpy()
     assert np.array_equal(yf, yf2)
     scale = _scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta)
-    assert np.max(np.abs(yf - yw) / scale) <= 1e-5 + 2 * 3e-5
+    assert np.max(np.abs(yf - yw) / scale) <= 3e-5 + 2 * 3e-5
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.45, 3.0])
+def test_fused_bf16_translation_invariance_across_r2_paths(ctx, shift):
+    """The operator is invariant under translation.  On the unit sphere with the
+    ensemble's Gaussian (sig^2 = log2(e) / 0.15^2 = 64.1) the shifts put
+    sig^2 max|x|^2 at 64 (norm expansion), 135 and 1026 (differences): each
+    result matches the oracle on the unshifted sphere."""
+    n, B = 1500, 40
+    rng = np.random.default_rng(77)
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.15, 0.3, size=B)
+    xs = x + np.array([shift, 0.0, 0.0])
+    y = _apply(ctx, xs, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, 4)
+    ref = NF.apply_K(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta)
+    err = np.max(np.abs(y - ref) / _scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta))
+    print("fused form 4, unit sphere shifted by %.2f: max |dy| / S = %.3e" % (shift, err), flush=True)
+    assert err <= TOL_APPLY[4], err
 
 
 @pytest.mark.parametrize("form", [4, 5])
@@ -153,6 +177,8 @@ def test_fused_full_size_ellipsoid_sampled_rows(ctx, form):
     y = _apply(ctx, x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, form)
     ref = NF.apply_K(x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows=rows)
     err = np.max(np.abs(y[:, rows] - ref) / _scale(x, q, w.u0, w.kernel_kind, w.kernel, w.beta, w.theta, rows))
+    print("fused form %d, N = %d, B = %d: one application, max |dy| / S over 24 rows = %.3e" % (form, w.n, w.b, err),
+          flush=True)
     assert err <= TOL_APPLY[form], err
 
 
@@ -176,6 +202,8 @@ def test_fused_integrate_ensemble_per_member(ctx, ensemble_case, form, use_graph
                    use_graph=use_graph)
     torch.cuda.synchronize()
     err = NF.rel_linf(u.cpu().numpy(), ref)
+    print("fused form %d, ensemble N = %d, %d steps, graph %s: max member error %.3e" % (form, w.n, w.steps, use_graph,
+                                                                                       err.max()), flush=True)
     assert err.shape == (64,)
     assert np.all(err <= TOL_STATE[form]), err.max()
 
@@ -205,4 +233,5 @@ def test_fused_large_n_sampled_rows(ctx, form):
     rows = rng.choice(n, 24, replace=False)
     ref = NF.apply_K(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, rows=rows)
     err = np.max(np.abs(y[:, rows] - ref) / _scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, rows))
+    print("fused form %d, N = %d, B = %d: max |dy| / S over 24 rows = %.3e" % (form, n, B, err), flush=True)
     assert err <= TOL_APPLY[form], err
