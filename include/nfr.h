@@ -193,7 +193,11 @@ size_t nfr_problem_bytes(int64_t n);
  * contribute.  xyz_dev: n x 3 row-major FP64 (device); q_dev: n FP64 (device).
  * The inputs are read by a kernel enqueued on the context stream and may be
  * freed once it has run.  The handle (host memory) references pack_dev, which
- * must stay allocated until nfr_problem_destroy. */
+ * must stay allocated until nfr_problem_destroy.  The pack also holds a tile
+ * order of the nodes (their Morton order, ties by index; built on the device
+ * by a bitonic sort), in which the fused BF16 form runs so that blocks of
+ * nearby nodes can skip the steep exponential; every call still takes and
+ * returns states in the caller's node order. */
 int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev,
                        void* pack_dev, size_t pack_bytes, nfr_problem** out);
 
@@ -217,6 +221,23 @@ int nfr_problem_destroy(nfr_problem* prob);
 int64_t nfr_problem_n(const nfr_problem* prob);
 /* Padded node count (multiple of 256): the row stride of a W matrix. */
 int64_t nfr_problem_npad(const nfr_problem* prob);
+
+/* Far blocks of the fused BF16 form (ONTHEFLY_BF16X3) for this problem and
+ * kernel: an application evaluates W in blocks of 32 target rows by 16 source
+ * columns of the tile order, and a block whose bounding spheres are so far
+ * apart that every pair has (1 - rho) t > 27 - log2|kappa| (paper eq. winh's
+ * Mexican hat with the excitatory exponential the steeper one: t =
+ * r^2 log2(e) / s_e^2, rho = s_e^2 / s_i^2, kappa = -A_i / A_e) takes only the
+ * inhibitory exponential, the excitatory one being below half a unit in the
+ * last place of the FP32 sum.  Returns the number of such blocks and of all
+ * blocks ((npad / 32) x (npad / 16)); far_blocks = 0 when the kernel is not
+ * eligible (not Gaussian, periodic, an integer length ratio, rho > 3/4 or
+ * |kappa| < 2^-20).  ws_dev: caller-owned device scratch of at least
+ * nfr_far_blocks_workspace_size(prob) bytes.  Synchronises the context stream;
+ * a diagnostic (the cost scales as npad^2 / 512), not part of the hot path. */
+size_t nfr_far_blocks_workspace_size(const nfr_problem* prob);
+int nfr_far_blocks(nfr_problem* prob, const nfr_kernel* kernel, void* ws_dev, size_t ws_bytes,
+                   int64_t* far_blocks, int64_t* total_blocks);
 
 /* ---------------------------------------------------------------- W form */
 

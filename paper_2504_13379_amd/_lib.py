@@ -84,6 +84,8 @@ def _declare(lib):
         "nfr_problem_destroy": (c_int, [P]),
         "nfr_problem_n": (c_int64, [P]),
         "nfr_problem_npad": (c_int64, [P]),
+        "nfr_far_blocks_workspace_size": (c_size_t, [P]),
+        "nfr_far_blocks": (c_int, [P, POINTER(NfrKernel), P, c_size_t, POINTER(c_int64), POINTER(c_int64)]),
         "nfr_w_bytes": (c_size_t, [c_int64, c_int]),
         "nfr_w_build": (c_int, [P, POINTER(NfrKernel), c_int, P, c_size_t]),
         "nfr_apply_workspace_size": (c_size_t, [P, c_int, c_int]),

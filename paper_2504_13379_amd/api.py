@@ -262,6 +262,16 @@ class Problem:
                                     ws.data_ptr(), ws_bytes))
         return ubar0, torch.tensor(list(pbar), dtype=torch.float64)
 
+    def far_blocks(self, kernel: L.NfrKernel) -> tuple[int, int]:
+        """nfr_far_blocks: (blocks of the fused BF16 form that skip the steep exponential,
+        all blocks) for this kernel; synchronises the context stream."""
+        nbytes = L.lib().nfr_far_blocks_workspace_size(self.handle)
+        ws = _dev_buffer(nbytes, self.ctx.device, self.ctx.stream)
+        far, tot = ctypes.c_int64(), ctypes.c_int64()
+        self.ctx.order_after_caller()
+        L.check(L.lib().nfr_far_blocks(self.handle, byref(kernel), ws.data_ptr(), nbytes, byref(far), byref(tot)))
+        return int(far.value), int(tot.value)
+
     def integrate_workspace(self, B: int, form: int) -> torch.Tensor:
         return _dev_buffer(L.lib().nfr_integrate_workspace_size(self.handle, B, form), self.ctx.device, self.ctx.stream)
 

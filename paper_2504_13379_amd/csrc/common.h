@@ -26,7 +26,26 @@ struct ProblemView {
   const double* q = nullptr;
   const double* xyz = nullptr;
   const double* qmax = nullptr;   // on the device: [0] max_j |q_j|, [1] max_j |x_j|^2 (FP32 coordinates)
+  // Tile order (kernels_tile.h): perm[s] = node in slot s, the packed
+  // coordinates and weights in slot order, and bounding spheres of blocks of
+  // 32 and 16 slots.  A view with `tiled` set has src and q in slot order.
+  const int* perm = nullptr;
+  const float4* src_t = nullptr;
+  const double* q_t = nullptr;
+  const float4* bnd32 = nullptr;
+  const float4* bnd16 = nullptr;
+  bool tiled = false;
 };
+
+// The problem seen in its tile order (states indexed by slot).
+inline ProblemView tile_view(const ProblemView& pv) {
+  ProblemView t = pv;
+  t.src = pv.src_t;
+  t.q = pv.q_t;
+  t.xyz = nullptr;
+  t.tiled = true;
+  return t;
+}
 
 // Kernel evaluation in the on-the-fly pair sum.  Coordinates are multiplied by
 // `sig` so that the excitatory exponent becomes exp2(-t) with

@@ -24,8 +24,11 @@
 // (a multiple of 64) with zeros.
 #pragma once
 
+#include <utility>
+
 #include "common.h"
 #include "kernels_core.h"
+#include "kernels_tile.h"
 
 namespace nfr {
 
@@ -400,6 +403,13 @@ struct MfmaOtfParams {
   float kappa;         // -A_i / A_e (PairParams)
   double amp;          // A_e
   const double* qmax;  // [0] max_j |q_j| (FP16 source lift sG), [1] max_j |x_j|^2 (norm expansion)
+  // far blocks (BF16, norm expansion, nodes in the tile order of
+  // kernels_tile.h): bounding spheres of the 32-row and 16-column blocks and
+  // the squared distance beyond which the steep exponential drops out of the
+  // FP32 sum; bnd16 null: every block takes both exponentials
+  const float4* bnd32;
+  const float4* bnd16;
+  float d2far;
 };
 
 #ifndef NFR_MFMA_OTF_MIN_WGS
@@ -434,7 +444,44 @@ struct MfmaOtfParams {
 #ifndef NFR_MFMA_OTF_NORM
 #define NFR_MFMA_OTF_NORM 1
 #endif
+// BF16 remainders by a dot-product instruction (see the split in k_mfma_otf).
+#ifndef NFR_MFMA_OTF_DOT2
+#define NFR_MFMA_OTF_DOT2 1
+#endif
 constexpr double kNormMaxT = 96.0;
+// Column values of the norm expansion reach each lane by a DPP row broadcast
+// fused into the multiply-add (row_newbcast: every lane of a 16-lane row reads
+// lane 16 r + E of the operand) instead of an LDS read per entry: each wave
+// holds a step's column values in 8 registers (per pair of MFMA steps and
+// coordinate), loaded by 8 four-byte LDS reads per step, against 32 128-bit
+// LDS reads before, which kept the LDS at 80 % of its 128 B/clock.
+#ifndef NFR_MFMA_OTF_DPP
+#define NFR_MFMA_OTF_DPP 1
+#endif
+
+template <int... I, typename F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// f(std::integral_constant<int, i>) for i = 0 .. N - 1, in order.
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+// Lane 16 r + E of v, in every lane of row r.
+template <int E>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + E, 0xf, 0xf, true));
+}
+// acc += row_bcast<E>(v) * x in one instruction (the broadcast is the DPP
+// source operand of the multiply-add; v is written by LDS loads only).
+template <int E>
+__device__ __forceinline__ void fmac_row_bcast(float& acc, float v, float x) {
+  asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "+v"(acc)
+      : "v"(v), "v"(x), "n"(E));
+}
 template <typename T, int KIND, int NB>
 __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
                                                      const T* __restrict__ Glo, int64_t npad, int B, int64_t kchunk,
@@ -471,6 +518,12 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
   if (k_end > npad) k_end = npad;
   const int nsteps = (int)((k_end - k_begin) / kMfmaStep);
 
+  // (-1, 0) and (0, -1) as packed BF16 pairs (low half first), in scalar registers
+  int m10i = 0, m01i = 0;
+  if constexpr (!kTwoAcc && NFR_MFMA_OTF_DOT2) {
+    asm volatile("s_mov_b32 %0, 0xbf80" : "=s"(m10i));
+    asm volatile("s_mov_b32 %0, 0xbf800000" : "=s"(m01i));
+  }
   // FP16 entries are lifted by 2^sU so that |u| <= 1 + |kappa| sits below 2^14.
   const int sU = mfma_scale_exp(1.0 + fabs((double)op.kappa), kTwoAcc);
   const float lift = (float)ldexp(1.0, sU);
@@ -521,9 +574,12 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
       }
     }
   };
-  // The whole pipeline for one way of evaluating t (kNorm: norm expansion).
-  auto run = [&](auto norm_tag) {
+  // The whole pipeline for one way of evaluating t (kNorm: norm expansion;
+  // kFar: blocks of entries far apart skip the steep exponential).
+  auto run = [&](auto norm_tag, auto far_tag) {
     constexpr bool kNorm = decltype(norm_tag)::value;
+    constexpr bool kFar = decltype(far_tag)::value;
+    static_assert(!kFar || (kNorm && sym_pow<KIND>() == 0), "far blocks need the norm expansion and two exponentials");
     const float xi = kNorm ? pr.x : pr.x * op.sig, yi = kNorm ? pr.y : pr.y * op.sig,
                 zi = kNorm ? pr.z : pr.z * op.sig;
     // norm expansion: the row's sig^2 |x_i|^2 and the column values rounded
@@ -537,11 +593,35 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     // bound on the steeper exponent's n_i), inside FP32 and BF16 range.
     const double ni = s2d * ((double)pr.x * pr.x + (double)pr.y * pr.y + (double)pr.z * pr.z);
     float kap = op.kappa;
-    if (kNorm) {
+    if constexpr (kFar) {
+      // u = R_i kappa_i (e1' / kappa_i + e2'): the row factor R_i kappa_i =
+      // kappa 2^(-rho n_i) goes to the epilogue, kap = 1 / kappa_i multiplies
+      // e1' (so an entry of a far block is e2' alone)
+      kap = (float)(exp2(-(1.0 - (double)op.rho) * ni) / (double)op.kappa);
+      if (h == 0) sR[wave][m] = (double)op.kappa * exp2(-(double)op.rho * ni);
+    } else if (kNorm) {
       constexpr int M = sym_pow<KIND>();
       kap = (float)((double)op.kappa * (M ? exp2((M - 1) * ni) : exp2((1.0 - (double)op.rho) * ni)));
       if (h == 0) sR[wave][m] = M ? exp2(-M * ni) : exp2(-ni);
     }
+    // far blocks: bit 4 (t % 16) + kb of fmask is set when the wave's 32 rows
+    // and the 16 columns of MFMA step kb of pipeline step t are far apart;
+    // lane l tests column block 64 g + l of the chunk for the group g = t / 16
+    // of 16 pipeline steps.  The row block's bounds sit in scalar registers
+    // (wave-uniform address) and a group's column bounds are live only while
+    // its mask is made, so the far path adds no vector registers to the loop.
+    uint64_t fmask = 0;
+    float4 rbnd = make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+    if constexpr (kFar) {
+      const int64_t rblk = (int64_t)__builtin_amdgcn_readfirstlane((int)(row0 / kTileRowBlock));
+      rbnd = op.bnd32[rblk];
+    }
+    auto make_mask = [&](int g) {
+      const int64_t cb = k_begin / kTileColBlock + 64 * (int64_t)g + lane, cend = k_end / kTileColBlock;
+      const bool ok = cb < cend;
+      const float4 bn = op.bnd16[ok ? cb : cend - 1];
+      fmask = __ballot(ok && tile_far(rbnd, bn, op.d2far));
+    };
     const double wsd = wave < 3 ? -2.0 * s2d : s2d;
     auto store_next = [&](int t) {
       const int buf = t % kOtfBufs;
@@ -549,22 +629,64 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
       for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[buf][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
       sS[buf][wave][lane] = kNorm ? (float)((double)sn * wsd) : sn * op.sig;
     };
-    auto eval = [&](int buf, int kb, V& whi, V& wlo) {
+    // norm expansion with broadcasts: X[p][r] holds coordinate row r of the
+    // step's columns for MFMA steps 2p and 2p + 1, lane 16 R + 8 s + e holding
+    // column 16 (2p + s) + 8 (R / 2) + e (R = row of 16 lanes, h = R / 2), so
+    // that row_newbcast:(8 s + e) hands lane m + 32 h the column 16 kb + 8 h + e
+    // of MFMA step kb = 2p + s (the A operand's column of its entry e)
+    constexpr bool kDpp = kNorm && NFR_MFMA_OTF_DPP;
+    static_assert(kMfmaKb % 2 == 0, "column registers hold MFMA steps in pairs");
+    float X[kMfmaKb / 2][4];
+    const int jl = 16 * ((lane & 15) >> 3) + 8 * (lane >> 5) + (lane & 7);
+    auto load_cols = [&](int buf) {
+#pragma unroll
+      for (int p = 0; p < kMfmaKb / 2; ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X[p][r] = sS[buf][r][32 * p + jl];
+    };
+    int tstep = 0;
+    auto eval = [&](int buf, auto kbc, V& whi, V& wlo) {
+      constexpr int kb = decltype(kbc)::value;
       const int col = 16 * kb + 8 * h;
       float w[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      float tb[8];
+      if constexpr (kDpp) {
+        // the same fused multiply-adds in the same order as from LDS, the 8
+        // entries interleaved (a broadcast multiply-add must not read an
+        // accumulator written by the instruction just before it)
+        constexpr int p = kb / 2, E0 = 8 * (kb % 2);
+        static_for<8>([&](auto ec) { tb[ec] = row_bcast<E0 + decltype(ec)::value>(X[p][3]); });
+        static_for<8>([&](auto ec) { fmac_row_bcast<E0 + decltype(ec)::value>(tb[ec], X[p][2], zi); });
+        static_for<8>([&](auto ec) { fmac_row_bcast<E0 + decltype(ec)::value>(tb[ec], X[p][1], yi); });
+        static_for<8>([&](auto ec) { fmac_row_bcast<E0 + decltype(ec)::value>(tb[ec], X[p][0], xi); });
+      } else if constexpr (kNorm) {
+        static_for<8>([&](auto ec) {
+          constexpr int e = decltype(ec)::value;
+          tb[e] = fmaf(xi, sS[buf][0][col + e], fmaf(yi, sS[buf][1][col + e], fmaf(zi, sS[buf][2][col + e], sS[buf][3][col + e])));
+        });
+      }
+      bool far = false;
+      if constexpr (kFar) far = (fmask >> (4 * (tstep & 15) + kb)) & 1;
+      if (far) {
+        // (1 - rho) t beyond 27 - log2|kappa| in every entry: the steep term is
+        // below half an ulp of the broad one, whose value the sum takes
+        static_for<8>([&](auto ec) { w[ec] = __builtin_amdgcn_exp2f(-(tb[ec] * op.rho)); });
+      } else static_for<8>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
         float tt;
-        if (kNorm) {
-          tt = fmaf(xi, sS[buf][0][col + e], fmaf(yi, sS[buf][1][col + e], fmaf(zi, sS[buf][2][col + e], sS[buf][3][col + e])));
+        if constexpr (kNorm) {
+          tt = tb[e];
         } else {
           const float r2 = pair_r2<KIND>(xi - sS[buf][0][col + e], yi - sS[buf][1][col + e],
                                          zi - sS[buf][2][col + e], op.per);
           tt = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
         }
-        w[e] = pair_u<KIND>(tt, op.rho, kap);
+        if constexpr (kFar)
+          w[e] = fmaf(kap, __builtin_amdgcn_exp2f(-tt), __builtin_amdgcn_exp2f(-(tt * op.rho)));
+        else
+          w[e] = pair_u<KIND>(tt, op.rho, kap);
         if (kTwoAcc) w[e] *= lift;
-      }
+      });
       // split pairwise: one conversion instruction rounds two entries
 #pragma unroll
       for (int e = 0; e < 8; e += 2) {
@@ -572,8 +694,20 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
         typedef __attribute__((ext_vector_type(2))) T h2_t;
         const f2_t wv = {w[e], w[e + 1]};
         const h2_t hv = __builtin_convertvector(wv, h2_t);
-        const f2_t hf = __builtin_convertvector(hv, f2_t);
-        f2_t rv = wv - hf;
+        f2_t rv;
+        if constexpr (!kTwoAcc && NFR_MFMA_OTF_DOT2) {
+          // remainders w - hi in one instruction per entry: the packed pair's
+          // dot product with (-1, 0) or (0, -1), plus w (exact: the BF16
+          // products are exact in FP32 and w - hi is representable).  The
+          // constant pairs come from registers: as an inline constant the
+          // compiler encodes (-1, 0) as -1.0, which this instruction reads as
+          // the FP32 pattern, i.e. the pair (0, -1) (checked on the device)
+          rv[0] = __builtin_amdgcn_fdot2_f32_bf16(hv, __builtin_bit_cast(h2_t, m10i), w[e], false);
+          rv[1] = __builtin_amdgcn_fdot2_f32_bf16(hv, __builtin_bit_cast(h2_t, m01i), w[e + 1], false);
+        } else {
+          const f2_t hf = __builtin_convertvector(hv, f2_t);
+          rv = wv - hf;
+        }
         if (c) rv *= (float)(1 << c);
         const h2_t lv = __builtin_convertvector(rv, h2_t);
         whi[e] = hv[0];
@@ -584,15 +718,17 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     };
     auto compute = [&](int t) {
       const int buf = t % kOtfBufs;
+      tstep = t;
+      if constexpr (kDpp) load_cols(buf);
       V h0, l0, h1, l1;
-      eval(buf, 0, h0, l0);
-#pragma unroll
-      for (int kb = 0; kb < kMfmaKb; kb += 2) {
-        if (kb + 1 < kMfmaKb) eval(buf, kb + 1, h1, l1);
+      eval(buf, std::integral_constant<int, 0>{}, h0, l0);
+      static_for<kMfmaKb / 2>([&](auto pc) {
+        constexpr int kb = 2 * decltype(pc)::value;
+        eval(buf, std::integral_constant<int, kb + 1>{}, h1, l1);
         mma(buf, kb, h0, l0);
-        if (kb + 2 < kMfmaKb) eval(buf, kb + 2, h0, l0);
-        if (kb + 1 < kMfmaKb) mma(buf, kb + 1, h1, l1);
-      }
+        if constexpr (kb + 2 < kMfmaKb) eval(buf, std::integral_constant<int, kb + 2>{}, h0, l0);
+        mma(buf, kb + 1, h1, l1);
+      });
     };
     // step t: issue the loads of step t + 1, evaluate and multiply step t from
     // LDS buffer t % kOtfBufs, (one buffer: barrier), store step t + 1 into the
@@ -602,6 +738,9 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
       store_next(0);
       __syncthreads();
       for (int t = 0; t < nsteps; ++t) {
+        if constexpr (kFar) {
+          if ((t & 15) == 0) make_mask(t / 16);
+        }
         load_next(t + 1);
         // keep the prefetch at the top: left to itself the scheduler sinks it
         // to just before its LDS store, exposing its latency every step
@@ -621,13 +760,22 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     constexpr int M = sym_pow<KIND>();
     const double steep = M ? (double)M : fmax(1.0, (double)op.rho);
     norm = s2d * steep * op.qmax[1] <= kNormMaxT;
-    if (norm)
-      run(std::true_type{});
-    else
-      run(std::false_type{});
+    if constexpr (M == 0) {
+      if (norm && op.bnd16)
+        run(std::true_type{}, std::true_type{});
+      else if (norm)
+        run(std::true_type{}, std::false_type{});
+      else
+        run(std::false_type{}, std::false_type{});
+    } else {
+      if (norm)
+        run(std::true_type{}, std::false_type{});
+      else
+        run(std::false_type{}, std::false_type{});
+    }
     __syncthreads();   // the row factors in sR
   } else {
-    run(std::false_type{});
+    run(std::false_type{}, std::false_type{});
   }
 
   const int sG_ = mfma_scale_exp(op.qmax[0], kTwoAcc);

@@ -19,6 +19,7 @@
 #include "kernels_adjoint.h"
 #include "kernels_batch.h"
 #include "kernels_quad.h"
+#include "kernels_tile.h"
 
 #include <algorithm>
 
@@ -175,6 +176,28 @@ PairParams pair_params_pow(const nfr_kernel& k, const ProblemView& pv) {
     pp.per = (float)(pv.period * sig_i);
   }
   return pp;
+}
+
+// Far blocks of the fused BF16 form (kernels_tile.h) apply to a Gaussian
+// kernel with two exponentials on a non-periodic problem whose broad
+// exponential is the inhibitory one, with rho <= 3/4 (then the near entries
+// e1' / kappa_i + e2' stay within FP32 range) and |kappa| >= 2^-20 (k is
+// normalised).  Returns the squared distance beyond which every pair has
+// (1 - rho) t > 27 - log2|kappa|, two bits of margin over the 25 at which the
+// steep term falls below half an ulp of the broad one; 0 when not eligible.
+float far_d2(const nfr_kernel& k, const ProblemView& pv, int form) {
+  if (form != NFR_FORM_ONTHEFLY_BF16X3 || kind_code(k, pv) != 0 || sym_pow_code(k) != 0) return 0.0f;
+  const PairParams pp = pair_params_pow(k, pv);
+  const double kap = std::fabs((double)pp.kappa), rho = pp.rho;
+  if (!(kap >= 0x1p-20) || !(rho > 0.0) || !(rho <= 0.75)) return 0.0f;
+  const double s2 = (double)pp.sig * pp.sig;
+  return (float)((27.0 - std::log2(kap)) / ((1.0 - rho) * s2));
+}
+
+// Calls of the fused BF16 form run in the problem's tile order when its far
+// blocks apply (states gathered at the start, scattered back at the end).
+bool use_tile_order(const nfr_kernel& k_in, const ProblemView& pv, int form) {
+  return far_d2(norm_kernel(k_in), pv, form) > 0.0f;
 }
 
 KernelF64 kernel64(const nfr_kernel& k, const ProblemView& pv) {
@@ -383,6 +406,8 @@ struct Workspace {
   double* part = nullptr;
   double* v = nullptr;
   double* ksum = nullptr;
+  double* ut = nullptr;        // fused BF16 form: states in the tile order (n x B)
+  double* yt = nullptr;        // fused BF16 form, one application: the result in the tile order
   OtfPlan otf;                 // multi-state on-the-fly FP32 plan (unused by other forms)
   int nsplit = 1;              // partial-sum slots per node and state in `part`
   size_t bytes = 0;
@@ -414,6 +439,10 @@ Workspace carve(void* base, const ProblemView& pv, int B, int form, bool steppin
     w.v = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
     w.ksum = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
     if (use_small_stage(pv, form, B)) w.g2 = reinterpret_cast<float*>(take(gbytes));
+  }
+  if (form == NFR_FORM_ONTHEFLY_BF16X3) {
+    w.ut = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
+    if (!stepping) w.yt = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
   }
   w.bytes = off;
   return w;
@@ -461,6 +490,16 @@ int launch_prep(const ProblemView& pv, int form, int B, const double* u, const F
   }
   NFR_HIP_LAUNCH();
   return NFR_OK;
+}
+
+// States between the problem's node order and its tile order.
+void launch_tile_gather(const ProblemView& pv, int B, const double* u, double* ut, hipStream_t s) {
+  const int64_t total = pv.n * (int64_t)B;
+  hipLaunchKernelGGL(k_tile_gather, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, u, pv.perm, pv.n, total, ut);
+}
+void launch_tile_scatter(const ProblemView& pv, int B, const double* ut, double* u, hipStream_t s) {
+  const int64_t total = pv.n * (int64_t)B;
+  hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, ut, pv.perm, pv.n, total, u);
 }
 
 // Pair sums into w.part for the current w.g.
@@ -515,7 +554,9 @@ int launch_pairs_raw(const ProblemView& pv, const nfr_kernel& k_in, int form, in
 #undef NFR_F32M_CASE
   } else if (!mfma_has_w(form)) {
     const PairParams pp = pair_params_pow(k, pv);
-    const MfmaOtfParams op{pp.sig, pp.rho, pp.per, pp.kappa, pp.amp, pv.qmax};
+    const float d2 = pv.tiled ? far_d2(k, pv, form) : 0.0f;
+    const MfmaOtfParams op{pp.sig, pp.rho, pp.per, pp.kappa, pp.amp, pv.qmax,
+                           d2 > 0.0f ? pv.bnd32 : nullptr, d2 > 0.0f ? pv.bnd16 : nullptr, d2};
 #define NFR_MFMA_OTF_CASE(K) \
   case K: launch_mfma_otf<K>(pv, form, op, B, w.g, w.part, s); break;
     switch (kind_code(k, pv) | (sym_pow_code(k) << 2)) {
@@ -638,6 +679,39 @@ int check_w(const nfr_problem* p, int form, const void* w_dev) {
 }  // namespace
 
 // ================================================================ C ABI
+
+namespace {
+// Regions of a problem's pack buffer, in order: packed coordinates, weights,
+// FP64 coordinates, the two maxima, then the tile order (kernels_tile.h):
+// slot -> node, coordinates and weights in slot order, block bounds, the
+// bounding box and the sort keys (used while the problem is created).
+struct PackLayout {
+  size_t src, q, xyz, qmax, perm, src_t, q_t, bnd32, bnd16, box, keys, bytes;
+};
+PackLayout pack_layout(int64_t n) {
+  const int64_t npad = round_up(n, kPad);
+  PackLayout L;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t r = off;
+    off += align256(b);
+    return r;
+  };
+  L.src = take(npad * sizeof(float4));
+  L.q = take(npad * sizeof(double));
+  L.xyz = take(3 * npad * sizeof(double));
+  L.qmax = take(2 * sizeof(double));
+  L.perm = take(npad * sizeof(int));
+  L.src_t = take(npad * sizeof(float4));
+  L.q_t = take(npad * sizeof(double));
+  L.bnd32 = take(npad / kTileRowBlock * sizeof(float4));
+  L.bnd16 = take(npad / kTileColBlock * sizeof(float4));
+  L.box = take(6 * sizeof(double));
+  L.keys = take(tile_pow2(npad) * sizeof(uint64_t));
+  L.bytes = off;
+  return L;
+}
+}  // namespace
 
 extern "C" {
 
@@ -786,11 +860,10 @@ int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t b
 
 const char* nfr_context_arch(const nfr_context* ctx) { return ctx ? ctx->arch : ""; }
 
+
 size_t nfr_problem_bytes(int64_t n) {
   if (n < 1 || n > kMaxN) return 0;
-  const int64_t npad = round_up(n, kPad);
-  return align256(npad * sizeof(float4)) + align256(npad * sizeof(double)) + align256(3 * npad * sizeof(double)) +
-         align256(sizeof(double));
+  return pack_layout(n).bytes;
 }
 
 int nfr_problem_create_periodic(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev,
@@ -815,14 +888,45 @@ int nfr_problem_create_periodic(nfr_context* ctx, int64_t n, const double* xyz_d
   p->view.n = n;
   p->view.npad = npad;
   p->view.period = period;
-  p->view.src = reinterpret_cast<const float4*>(base);
-  p->view.q = reinterpret_cast<const double*>(base + align256(npad * sizeof(float4)));
-  p->view.xyz = reinterpret_cast<const double*>(base + align256(npad * sizeof(float4)) + align256(npad * sizeof(double)));
-  p->view.qmax = reinterpret_cast<const double*>(reinterpret_cast<const char*>(p->view.xyz) + align256(3 * npad * sizeof(double)));
-  hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, ctx->stream, xyz_dev, q_dev, n, npad, period,
-                     const_cast<float4*>(p->view.src), const_cast<double*>(p->view.q), const_cast<double*>(p->view.xyz));
-  hipLaunchKernelGGL(k_qmax, dim3(1), dim3(kWG), 0, ctx->stream, p->view.q, p->view.src, npad,
-                     const_cast<double*>(p->view.qmax));
+  const PackLayout L = pack_layout(n);
+  float4* src = reinterpret_cast<float4*>(base + L.src);
+  double* q = reinterpret_cast<double*>(base + L.q);
+  double* xyz = reinterpret_cast<double*>(base + L.xyz);
+  double* qmax = reinterpret_cast<double*>(base + L.qmax);
+  int* perm = reinterpret_cast<int*>(base + L.perm);
+  float4* src_t = reinterpret_cast<float4*>(base + L.src_t);
+  double* q_t = reinterpret_cast<double*>(base + L.q_t);
+  float4* bnd32 = reinterpret_cast<float4*>(base + L.bnd32);
+  float4* bnd16 = reinterpret_cast<float4*>(base + L.bnd16);
+  double* box = reinterpret_cast<double*>(base + L.box);
+  uint64_t* keys = reinterpret_cast<uint64_t*>(base + L.keys);
+  p->view.src = src;
+  p->view.q = q;
+  p->view.xyz = xyz;
+  p->view.qmax = qmax;
+  p->view.perm = perm;
+  p->view.src_t = src_t;
+  p->view.q_t = q_t;
+  p->view.bnd32 = bnd32;
+  p->view.bnd16 = bnd16;
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, st, xyz_dev, q_dev, n, npad, period, src, q,
+                     xyz);
+  hipLaunchKernelGGL(k_qmax, dim3(1), dim3(kWG), 0, st, q, src, npad, qmax);
+  // tile order: Morton keys of the packed coordinates, bitonic sort, slot arrays, block bounds
+  const int64_t np2 = tile_pow2(npad);
+  hipLaunchKernelGGL(k_tile_box, dim3(1), dim3(kWG), 0, st, src, n, box);
+  hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)ceil_div(np2, kWG)), dim3(kWG), 0, st, src, n, np2, box, keys);
+  for (int64_t k = 2; k <= np2; k <<= 1)
+    for (int64_t j = k >> 1; j > 0; j >>= 1)
+      hipLaunchKernelGGL(k_bitonic, dim3((unsigned)ceil_div(np2, kWG)), dim3(kWG), 0, st, keys, np2, k, j);
+  hipLaunchKernelGGL(k_tile_build, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, st, keys, n, npad, src, q, perm,
+                     src_t, q_t);
+  const int64_t nb32 = npad / kTileRowBlock, nb16 = npad / kTileColBlock;
+  hipLaunchKernelGGL(k_tile_bounds<kTileRowBlock>, dim3((unsigned)ceil_div(nb32, kWG)), dim3(kWG), 0, st, src_t, n, nb32,
+                     bnd32);
+  hipLaunchKernelGGL(k_tile_bounds<kTileColBlock>, dim3((unsigned)ceil_div(nb16, kWG)), dim3(kWG), 0, st, src_t, n, nb16,
+                     bnd16);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     delete p;
@@ -852,6 +956,39 @@ int nfr_problem_destroy(nfr_problem* prob) {
 
 int64_t nfr_problem_n(const nfr_problem* prob) { return prob ? prob->view.n : -1; }
 int64_t nfr_problem_npad(const nfr_problem* prob) { return prob ? prob->view.npad : -1; }
+
+size_t nfr_far_blocks_workspace_size(const nfr_problem* prob) {
+  if (!prob) return 0;
+  return align256(size_t(prob->view.npad / kTileRowBlock) * sizeof(int64_t));
+}
+
+int nfr_far_blocks(nfr_problem* prob, const nfr_kernel* kernel, void* ws_dev, size_t ws_bytes, int64_t* far_blocks,
+                   int64_t* total_blocks) {
+  int st;
+  if ((st = check_problem(prob)) || (st = check_kernel(kernel))) return st;
+  if (!far_blocks || !total_blocks) return fail(NFR_ERR_INVALID_ARG, "NULL output pointer");
+  const ProblemView& pv = prob->view;
+  const int64_t nrow = pv.npad / kTileRowBlock, ncol = pv.npad / kTileColBlock;
+  *total_blocks = nrow * ncol;
+  *far_blocks = 0;
+  const float d2 = far_d2(norm_kernel(*kernel), pv, NFR_FORM_ONTHEFLY_BF16X3);
+  if (!(d2 > 0.0f)) return NFR_OK;
+  const size_t need = nfr_far_blocks_workspace_size(prob);
+  if (!ws_dev || ws_bytes < need) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  NFR_HIP(hipSetDevice(prob->ctx->device));
+  hipStream_t s = prob->ctx->stream;
+  int64_t* counts = static_cast<int64_t*>(ws_dev);
+  hipLaunchKernelGGL(k_tile_far_count, dim3((unsigned)ceil_div(nrow, kWG)), dim3(kWG), 0, s, pv.bnd32, pv.bnd16, nrow, ncol,
+                     d2, counts);
+  NFR_HIP_LAUNCH();
+  std::vector<int64_t> h(nrow);
+  NFR_HIP(hipMemcpyAsync(h.data(), counts, nrow * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  NFR_HIP(hipStreamSynchronize(s));
+  int64_t sum = 0;
+  for (int64_t v : h) sum += v;
+  *far_blocks = sum;
+  return NFR_OK;
+}
 
 size_t nfr_w_bytes(int64_t n, int form) {
   if (n < 1 || n > kMaxN) return 0;
@@ -910,18 +1047,27 @@ int apply_check(const nfr_problem* prob, const nfr_kernel* kernel, const nfr_fir
 int apply_launch(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* firing, int B, const double* u_dev,
                  double* y_dev, int form, const void* w_dev, const Workspace& w) {
   int st;
-  const ProblemView& pv = prob->view;
+  const bool tiled = use_tile_order(*kernel, prob->view, form);
+  const ProblemView pv = tiled ? tile_view(prob->view) : prob->view;
   NFR_HIP(hipSetDevice(prob->ctx->device));
   hipStream_t s = prob->ctx->stream;
   const Firing fr = firing_of(*firing);
-  if ((st = launch_prep(pv, form, B, u_dev, fr, w, nullptr, s))) return st;
+  const double* u_in = u_dev;
+  double* y_out = y_dev;
+  if (tiled) {
+    launch_tile_gather(pv, B, u_dev, w.ut, s);
+    u_in = w.ut;
+    y_out = w.yt;
+  }
+  if ((st = launch_prep(pv, form, B, u_in, fr, w, nullptr, s))) return st;
   if ((st = launch_pairs(prob->ctx, pv, *kernel, form, B, w_dev, w))) return st;
   const int nsplit = w.nsplit;
   const int64_t total = pv.n * (int64_t)B;
   if (is_mfma_form(form))
-    launch_mfma_reduce(pv, form, B, w.part, nsplit, y_dev, s);
+    launch_mfma_reduce(pv, form, B, w.part, nsplit, y_out, s);
   else
-    NFR_LAUNCH_SLOTS(k_reduce_partials, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, y_dev);
+    NFR_LAUNCH_SLOTS(k_reduce_partials, nsplit, total, s, w.part, nsplit, pv.n, pv.npad, B, y_out);
+  if (tiled) launch_tile_scatter(pv, B, w.yt, y_dev, s);
   NFR_HIP_LAUNCH();
   return NFR_OK;
 }
@@ -971,8 +1117,10 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
   if (!(dt > 0.0)) return fail(NFR_ERR_INVALID_ARG, "dt must be > 0");
   if (steps < 0) return fail(NFR_ERR_INVALID_ARG, "steps must be >= 0");
   if (ckpt_dev && ckpt_every < 1) return fail(NFR_ERR_INVALID_ARG, "ckpt_every must be >= 1");
-  const ProblemView& pv = prob->view;
-  form = resolve_form(form, pv.n, B);
+  form = resolve_form(form, prob->view.n, B);
+  // the fused BF16 form steps the states in the tile order (w.ut)
+  const bool tiled = use_tile_order(*kernel, prob->view, form);
+  const ProblemView pv = tiled ? tile_view(prob->view) : prob->view;
   if ((st = check_w(prob, form, w_dev))) return st;
   const Workspace w = carve(ws_dev, pv, B, form, true);
   if (!ws_dev || ws_bytes < w.bytes) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, w.bytes);
@@ -984,19 +1132,31 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
   const size_t state_bytes = size_t(pv.n) * B * sizeof(double);
   if (ckpt_dev) NFR_HIP(hipMemcpyAsync(ckpt_dev, u_dev, state_bytes, hipMemcpyDeviceToDevice, s));
   if (steps == 0) return NFR_OK;
-  if ((st = launch_prep(pv, form, B, u_dev, fr, w, w.v, s))) return st;
+  double* u_run = u_dev;
+  if (tiled) {
+    launch_tile_gather(pv, B, u_dev, w.ut, s);
+    NFR_HIP_LAUNCH();
+    u_run = w.ut;
+  }
+  if ((st = launch_prep(pv, form, B, u_run, fr, w, w.v, s))) return st;
 
   auto one_step = [&]() -> int {
     for (int stage = 1; stage <= 4; ++stage) {
       int r;
-      if ((r = launch_stage(prob->ctx, pv, *kernel, form, B, w_dev, w, stage, dt, u_dev, fr))) return r;
+      if ((r = launch_stage(prob->ctx, pv, *kernel, form, B, w_dev, w, stage, dt, u_run, fr))) return r;
     }
     return NFR_OK;
   };
   auto checkpoint = [&](int64_t done) -> int {
-    if (ckpt_dev && done % ckpt_every == 0)
-      NFR_HIP(hipMemcpyAsync(ckpt_dev + (done / ckpt_every) * (int64_t)pv.n * B, u_dev, state_bytes,
-                             hipMemcpyDeviceToDevice, s));
+    if (ckpt_dev && done % ckpt_every == 0) {
+      double* dst = ckpt_dev + (done / ckpt_every) * (int64_t)pv.n * B;
+      if (tiled) {
+        launch_tile_scatter(pv, B, u_run, dst, s);
+        NFR_HIP_LAUNCH();
+      } else {
+        NFR_HIP(hipMemcpyAsync(dst, u_dev, state_bytes, hipMemcpyDeviceToDevice, s));
+      }
+    }
     return NFR_OK;
   };
 
@@ -1075,6 +1235,10 @@ int nfr_integrate(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing*
   for (; done < steps; ++done) {
     if ((st = one_step())) return st;
     if ((st = checkpoint(done + 1))) return st;
+  }
+  if (tiled) {
+    launch_tile_scatter(pv, B, u_run, u_dev, s);
+    NFR_HIP_LAUNCH();
   }
   return NFR_OK;
 }
