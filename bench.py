@@ -72,14 +72,20 @@ def slots_per_unordered_pair(kind, m):
     return eval_slots(kind, m) + 2
 
 
-def fused_slots_per_w(kind, m, fp16=False, norm=False):
+def fused_slots_per_w(kind, m, fp16=False, norm=False, far=False):
     """Slots per W entry of the fused on-the-fly split forms: the evaluation of u
-    above (the weights sit in G), and 3 for the hi/lo split (two conversions of a pair of entries at half a slot each, the hi value
-    back to FP32, the subtraction); FP16 adds the lift of u (its 2^11 remainder
-    scaling fuses into the subtraction).  With the norm expansion of r^2 (BF16,
-    see fused_norm_path) the 3 subtractions, the square and 2 multiply-adds of
-    r^2 are 3 multiply-adds, the row's |x_i|^2 being a row factor: 3 slots fewer."""
-    return eval_slots(kind, m) - (3 if norm else 0) + 3 + (1 if fp16 else 0)
+    above (the weights sit in G) and the hi/lo split: FP16 3 (two conversions of
+    a pair of entries at half a slot each, the hi value back to FP32, the
+    subtraction) plus the lift of u; BF16 2 (the remainder w - hi is one
+    dot-product instruction).  With the norm expansion of r^2 (BF16, see
+    fused_norm_path) the 3 subtractions, the square and 2 multiply-adds of r^2
+    are 3 multiply-adds, the row's |x_i|^2 being a row factor: 3 slots fewer.
+    An entry of a far block (BF16, norm expansion, two exponentials; see
+    nfr_far_blocks) takes the 3 multiply-adds, one exp2 and the split: 9."""
+    if far:
+        return 3 + TRANS_COST + 2
+    split = 3 + 1 if fp16 else 2
+    return eval_slots(kind, m) - (3 if norm else 0) + split
 
 
 # The fused BF16 kernel evaluates r^2 of Gaussian kernels on non-periodic
@@ -206,8 +212,10 @@ ENS_FORMS = {"otf_bf16x3": 4, "bf16x3": 2, "otf_fp16x3": 5, "fp16x3": 3, "otf_fp
 SPLIT_FORMS = ("otf_bf16x3", "bf16x3", "otf_fp16x3", "fp16x3")
 
 
-def ensemble_roofline(nm, npad, kind, kernel, avg_s, max_r2):
-    """Roofline of the dominant (pair-sum) kernel of form `nm` at one launch per operator application."""
+def ensemble_roofline(nm, npad, kind, kernel, avg_s, max_r2, far_frac=0.0):
+    """Roofline of the dominant (pair-sum) kernel of form `nm` at one launch per operator
+    application; far_frac: the fraction of the fused BF16 form's W blocks that skip the
+    steep exponential (nfr_far_blocks)."""
     m = sym_pow(kind, kernel[1], kernel[3])
     if nm in ("bf16x3", "fp16x3"):
         wbytes = 2.0 * 2 * npad * npad     # hi + lo, 2 bytes each, every element once
@@ -235,11 +243,12 @@ def ensemble_roofline(nm, npad, kind, kernel, avg_s, max_r2):
     norm = not fp16 and fused_norm_path(kind, kernel, m, max_r2)
     kname = "k_mfma_otf<%s,%d,2>" % ("fp16" if fp16 else "bf16", kind + 4 * (m - 1 if m else 0))
     wvals = float(npad) ** 2
-    spw = fused_slots_per_w(kind, m, fp16, norm)
+    far_frac = far_frac if (norm and not fp16) else 0.0
+    spw = (1.0 - far_frac) * fused_slots_per_w(kind, m, fp16, norm) + far_frac * fused_slots_per_w(kind, m, far=True)
     achieved = wvals * spw / avg_s
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tslot/s",
             "frac": achieved / VALU_LANES_PER_S, "traffic": measured_traffic(kname), "kernel": kname,
-            "slots_per_w": spw, "r2": "norm expansion" if norm else "differences",
+            "slots_per_w": spw, "far_block_fraction": far_frac, "r2": "norm expansion" if norm else "differences",
             "mfma_tflops": wvals * 384.0 / avg_s / 1e12, "mfma_frac": wvals * 384.0 / avg_s / MFMA_BF16_PEAK}
 
 
@@ -270,6 +279,8 @@ def ensemble_headline(P, torch, args):
     u0 = torch.from_numpy(w.u0.copy()).cuda()
     u = u0.clone()
     pairs = 4.0 * w.steps * float(w.n) ** 2 * w.b
+    far_blocks, all_blocks = prob.far_blocks(k)
+    far_frac = far_blocks / all_blocks
     forms = {}
     keep = {}
 
@@ -306,7 +317,7 @@ def ensemble_headline(P, torch, args):
         forms[nm] = {"value": pairs / sec, "unit": "pair-interactions/s", "ms_per_integration": sec * 1e3,
                      "w_build_ms": t_build * 1e3, "kernel_avg_ms": avg_ms, **lps,
                      "rel_linf_vs_fp64_max": finite(err.max()), "rel_linf_vs_fp64_median": finite(np.median(err)),
-                     "roofline": ensemble_roofline(nm, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3, max_r2)}
+                     "roofline": ensemble_roofline(nm, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3, max_r2, far_frac)}
         keep[nm] = err
         del W
         torch.cuda.empty_cache()
@@ -344,7 +355,7 @@ def ensemble_headline(P, torch, args):
             "times_ms": [t * 1e3 for t in times], "kernel_avg_ms": avg_ms, "kernel_launches_timed": n_l,
             "timed_launch": "directly launched (HIP events around each pair-sum launch)",
             "rel_linf_vs_fp64": [finite(e) for e in err], "rel_linf_vs_fp64_max": finite(err.max()),
-            "roofline": ensemble_roofline(best, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3, max_r2),
+            "roofline": ensemble_roofline(best, prob.npad, w.kernel_kind, w.kernel, avg_ms * 1e-3, max_r2, far_frac),
             "launches": launches_per_step(P, ctx)}
     del W
     torch.cuda.empty_cache()

@@ -231,8 +231,9 @@ int64_t nfr_problem_npad(const nfr_problem* prob);
  * inhibitory exponential, the excitatory one being below half a unit in the
  * last place of the FP32 sum.  Returns the number of such blocks and of all
  * blocks ((npad / 32) x (npad / 16)); far_blocks = 0 when the kernel is not
- * eligible (not Gaussian, periodic, an integer length ratio, rho > 3/4 or
- * |kappa| < 2^-20).  ws_dev: caller-owned device scratch of at least
+ * eligible (not Gaussian, periodic, an integer length ratio, rho > 3/4,
+ * |kappa| < 2^-20, or coordinates so large against s_e that the kernel
+ * evaluates r^2 from differences: log2(e) max|x|^2 / s_e^2 > 96).  ws_dev: caller-owned device scratch of at least
  * nfr_far_blocks_workspace_size(prob) bytes.  Synchronises the context stream;
  * a diagnostic (the cost scales as npad^2 / 512), not part of the hot path. */
 size_t nfr_far_blocks_workspace_size(const nfr_problem* prob);

@@ -971,12 +971,21 @@ int nfr_far_blocks(nfr_problem* prob, const nfr_kernel* kernel, void* ws_dev, si
   const int64_t nrow = pv.npad / kTileRowBlock, ncol = pv.npad / kTileColBlock;
   *total_blocks = nrow * ncol;
   *far_blocks = 0;
-  const float d2 = far_d2(norm_kernel(*kernel), pv, NFR_FORM_ONTHEFLY_BF16X3);
+  const nfr_kernel kn = norm_kernel(*kernel);
+  const float d2 = far_d2(kn, pv, NFR_FORM_ONTHEFLY_BF16X3);
   if (!(d2 > 0.0f)) return NFR_OK;
   const size_t need = nfr_far_blocks_workspace_size(prob);
   if (!ws_dev || ws_bytes < need) return fail(NFR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
   NFR_HIP(hipSetDevice(prob->ctx->device));
   hipStream_t s = prob->ctx->stream;
+  // the kernel takes far blocks only on its norm expansion path, as it decides
+  // on the device: sig^2 max(1, rho) max_j |x_j|^2 <= kNormMaxT
+  double qm[2];
+  NFR_HIP(hipMemcpyAsync(qm, pv.qmax, sizeof qm, hipMemcpyDeviceToHost, s));
+  NFR_HIP(hipStreamSynchronize(s));
+  const PairParams pp = pair_params_pow(kn, pv);
+  const double s2d = (double)pp.sig * pp.sig;
+  if (!(s2d * std::fmax(1.0, (double)pp.rho) * qm[1] <= kNormMaxT)) return NFR_OK;
   int64_t* counts = static_cast<int64_t*>(ws_dev);
   hipLaunchKernelGGL(k_tile_far_count, dim3((unsigned)ceil_div(nrow, kWG)), dim3(kWG), 0, s, pv.bnd32, pv.bnd16, nrow, ncol,
                      d2, counts);

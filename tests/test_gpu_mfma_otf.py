@@ -235,3 +235,91 @@ def test_fused_large_n_sampled_rows(ctx, form):
     err = np.max(np.abs(y[:, rows] - ref) / _scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, rows))
     print("fused form %d, N = %d, B = %d: max |dy| / S over 24 rows = %.3e" % (form, n, B, err), flush=True)
     assert err <= TOL_APPLY[form], err
+
+
+# ---------------------------------------------------------------- tile order and far blocks
+
+def _two_caps(n, gap):
+    """n nodes on two copies of a cap of the unit sphere (chordal radius about
+    0.35), moved so that their centres sit at x = -gap/2 and x = gap/2."""
+    x = S.fibonacci_sphere(40 * n)
+    a = x[x[:, 2] > 0.94][: n // 2] - np.array([0.0, 0.0, 0.97])
+    assert a.shape[0] == n // 2
+    return np.concatenate([a - np.array([gap / 2, 0.0, 0.0]), a + np.array([gap / 2, 0.0, 0.0])])
+
+
+def test_far_blocks_eligibility(ctx):
+    """nfr_far_blocks: some but not all blocks of the ellipsoid ensemble's kernel are far;
+    kernels outside the far path's conditions report none."""
+    w = C.ellipsoid_ensemble(4000, 8, steps=1)
+    q = C.area_share_weights(w.surface)
+    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
+    far, tot = prob.far_blocks(P.kernel_struct(NF.GAUSS_MH, *GAUSS))
+    npad = prob.npad
+    assert tot == (npad // 32) * (npad // 16)
+    assert 0.2 * tot < far < tot, (far, tot)
+    for kind, p in [(NF.EXP_MH, EXPK),                             # exponential kernel
+                    (NF.GAUSS_MH, (1.0, 0.15, 0.0, 0.4)),          # no inhibitory term
+                    (NF.GAUSS_MH, (1.0, 0.36, 0.5, 0.4)),          # rho = 0.81 > 3/4
+                    (NF.GAUSS_MH, (1.0, 0.2, 0.5, 0.2 * math.sqrt(2.0)))]:   # integer ratio (one exponential)
+        assert prob.far_blocks(P.kernel_struct(kind, *p))[0] == 0, (kind, p)
+    rng = np.random.default_rng(8)
+    flat = S.flat_square(2000, L, rng, 0.3)
+    per = P.Problem(ctx, torch.from_numpy(flat.xyz).cuda(), torch.from_numpy(Q.plane_weights(flat.xyz)).cuda(),
+                    period=L)
+    assert per.far_blocks(P.kernel_struct(NF.GAUSS_MH, 1.0, 0.3, 0.5, 0.8))[0] == 0   # periodic
+
+
+@pytest.mark.parametrize("gap", [1.2, 1.6])
+def test_fused_far_blocks_two_caps(ctx, gap):
+    """Two caps `gap` apart (1.2: the caps' nearest nodes 0.5 apart, so some blocks
+    between them are near; 1.6: every block between them is far), the blocks
+    within a cap near: far blocks evaluate only the inhibitory exponential, and
+    one application matches the oracle, which evaluates every entry in full.
+    sig^2 max|x|^2 stays below 96, so the kernel takes the norm expansion that
+    the far path needs."""
+    rng = np.random.default_rng(int(gap * 10))
+    x = _two_caps(3000, gap)
+    assert math.log2(math.e) / GAUSS[1] ** 2 * np.max(np.sum(x * x, axis=1)) < 96.0
+    n, B = x.shape[0], 64
+    q = rng.uniform(0.5, 1.5, size=n) * 0.5 / n
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.15, 0.3, size=B)
+    prob = P.Problem(ctx, torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
+    k = P.kernel_struct(NF.GAUSS_MH, *GAUSS)
+    far, tot = prob.far_blocks(k)
+    assert far > (0.3 if gap < 1.5 else 0.45) * tot, (far, tot)
+    y = _apply(ctx, x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, 4)
+    ref = NF.apply_K(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta)
+    err = np.max(np.abs(y - ref) / _scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta))
+    print("fused form 4, two caps %.1f apart: %.2f of blocks far, max |dy| / S = %.3e" % (gap, far / tot, err),
+          flush=True)
+    assert err <= TOL_APPLY[4], err
+
+
+def test_fused_tile_order_checkpoints_and_resume(ctx):
+    """The fused BF16 form steps the states in the problem's tile order: every
+    checkpoint comes back in the caller's node order (against the oracle's
+    states at the same steps), and resuming from a checkpoint reproduces the
+    uninterrupted run bit for bit."""
+    w = C.ellipsoid_ensemble(2000, 64, steps=6)
+    q = Q.surface_weights(w.surface)
+    op = NF.DenseOperator(w.surface.xyz, q, w.kernel_kind, w.kernel)
+    _, saved = NF.rk4(op, w.u0, w.beta, w.theta, w.dt, w.steps, save_every=2)
+    prob = P.Problem(ctx, torch.from_numpy(w.surface.xyz).cuda(), torch.from_numpy(q).cuda())
+    k = P.kernel_struct(w.kernel_kind, *w.kernel)
+    f = P.Firing(w.beta, torch.from_numpy(w.theta).cuda())
+    assert prob.far_blocks(k)[0] > 0
+    u = torch.from_numpy(w.u0.copy()).cuda()
+    ck = prob.integrate(k, f, u, w.dt, w.steps, form=4, ckpt_every=2)
+    torch.cuda.synchronize()
+    ck = ck.cpu().numpy()
+    assert ck.shape == (4, 64, w.n)
+    for i, ref in enumerate(saved):
+        err = NF.rel_linf(ck[i], ref)
+        assert np.all(err <= TOL_STATE[4]), (i, err.max())
+    np.testing.assert_array_equal(ck[-1], u.cpu().numpy())
+    u2 = torch.from_numpy(ck[1].copy()).cuda()    # resume from step 2
+    prob.integrate(k, f, u2, w.dt, 4, form=4)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u2.cpu().numpy(), u.cpu().numpy())

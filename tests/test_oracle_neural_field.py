@@ -307,3 +307,22 @@ def test_manufactured_solution_converges_with_quadrature():
                           lambda k, c: F[k, {0.0: 0, 0.5: 1, 1.0: 2}[c]])
         errs.append(np.max(np.abs(u[0] - m.u(dt * steps))) / np.max(np.abs(m.u(dt * steps))))
     assert errs[1] < errs[0] / 4 and errs[1] < 1e-5, errs
+
+
+def test_far_block_threshold_drops_steep_term_in_fp32():
+    """The fused BF16 form evaluates only the broad exponential for pairs with
+    (1 - rho) t > 27 - log2|kappa| (t = r^2 log2(e) / s_e^2, rho = s_e^2 / s_i^2,
+    kappa = -A_i / A_e).  There the steep term 2^-t is below an eighth of a unit
+    in the last place of the FP32 value kappa 2^(-rho t), so the FP32 sum equals
+    the broad term alone: checked in FP32 arithmetic for several kernels."""
+    rng = np.random.default_rng(0)
+    for kappa in (-0.5, -1e-3, -3.0, 0.25, -2.0 ** -20):
+        for rho in (0.1, 0.140625, 0.5, 0.75):
+            tmin = (27.0 - np.log2(abs(kappa))) / (1.0 - rho)
+            t = tmin * (1.0 + rng.uniform(0.0, 3.0, size=20000)) + 1e-9
+            broad = (kappa * np.exp2(-rho * t)).astype(np.float32)
+            steep = np.exp2(-t)
+            total = (broad.astype(np.float64) + steep).astype(np.float32)
+            assert np.array_equal(total, broad), (kappa, rho)
+            ulp = np.spacing(np.abs(broad)).astype(np.float64)
+            assert np.all(steep < ulp / 8), (kappa, rho)
