@@ -646,11 +646,12 @@ def adjoint_leg(P, torch, args):
     L.nfr_context_set_timing(ctx.handle, 0)
     evals = 3 * 4.0 * w.steps * float(w.n) ** 2        # forward, segment recompute, adjoint sweep
     # algorithmic slots: forward and recompute on the symmetric kernel, the adjoint sweep on its
-    # four-channel symmetric transpose kernel (rho t multiply kept, e1 = e2^m, e*t products, 8 FMAs)
+    # four-channel symmetric transpose kernel (r^2 6, the rho t multiply only without an integer
+    # ratio (with rho = 1/m the coordinates are in inhibitory units), e1 = e2^m, e*t products, 8 FMAs)
     npad = -(-w.n // 256) * 256
     m = sym_pow(w.kernel_kind, w.kernel[1], w.kernel[3])
     trans = (2 if w.kernel_kind == 0 else 3) - (1 if m else 0)
-    adj_slots = 7 + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 2 + 8
+    adj_slots = (6 if m else 7) + trans * TRANS_COST + (0 if not m else (1 if m == 2 else 2)) + 2 + 8
     slots = 4.0 * w.steps * float(npad) ** 2 / 2 * (2 * slots_per_unordered_pair(w.kernel_kind, m) + adj_slots)
     return {"workload": "torus N=16384, exp Mexican hat, RK4 dt=0.02 x %d steps, checkpoints every %d, "
                         "loss |u(T)|^2" % (w.steps, every),

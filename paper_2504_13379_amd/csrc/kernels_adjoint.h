@@ -28,7 +28,9 @@ namespace nfr {
 // Slots: part[(c * nt + s) * npad + i] for channel c, slot s (the row sums of
 // (I, J) go to slot J of the nodes of I, the column sums to slot I of the
 // nodes of J).  The coordinates are in the forward kernel's units (t the
-// excitatory argument); with rho = 1/m the kernel uses e1 = e2^m.
+// excitatory argument); with rho = 1/m they are in units of the inhibitory
+// length instead, t the inhibitory argument, e2 = exp2(-t) and e1 = e2^m, and
+// the T channels hold sum lambda e t_i = T / m.
 // Waves per workgroup of the transpose kernel (they split a tile's source
 // groups like the forward kernel's; one group per wave measured fastest at
 // N = 16384: 1, 2, 4 waves took 0.089, 0.082, 0.077 ms per pair launch).
@@ -82,7 +84,9 @@ __device__ inline void sym_adj_tile(const float4* __restrict__ src, const float*
       for (int k = 0; k < kSymTPT; ++k) {
         const float r2 = pair_r2<KIND>(xi[k] - sx, yi[k] - sy, zi[k] - sz, pp.per);
         const float t = ((KIND & 1) == 0) ? r2 : __builtin_amdgcn_sqrtf(r2);
-        const float e2 = __builtin_amdgcn_exp2f(-(t * rho));
+        // with rho = 1/m the coordinates are in units of the inhibitory length
+        // (t is the inhibitory argument; the combine scales T1, T2 by m)
+        const float e2 = sym_pow<KIND>() == 0 ? __builtin_amdgcn_exp2f(-(t * rho)) : __builtin_amdgcn_exp2f(-t);
         const float e1 = sym_pow<KIND>() == 0 ? __builtin_amdgcn_exp2f(-t) : ipow<sym_pow<KIND>()>(e2);
         const float e1t = e1 * t;
         const float e2t = e2 * t;

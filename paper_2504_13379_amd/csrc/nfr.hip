@@ -1311,6 +1311,11 @@ AdjCoef adj_coef(const nfr_kernel& k) {
     c.kse = 1.0 / (k.s_e * kLog2e);
     c.ksi = k.s_e / (k.s_i * k.s_i * kLog2e);
   }
+  // rho = 1/m: the pair kernel's T sums are in the inhibitory argument, t / m
+  if (const int code = sym_pow_code(k)) {
+    c.kse *= code + 1;
+    c.ksi *= code + 1;
+  }
   return c;
 }
 
@@ -1341,7 +1346,7 @@ int nfr_adjoint(nfr_problem* prob, const nfr_kernel* kernel, const nfr_firing* f
   nfr_context* ctx = prob->ctx;
   hipStream_t s = ctx->stream;
   const Firing fr = firing_of(*firing);
-  const PairParams pp = pair_params(*kernel, pv);
+  const PairParams pp = pair_params_pow(*kernel, pv);
   const AdjCoef co = adj_coef(*kernel);
   const int nt = (int)adj_tiles(pv.npad);
   const int adj_code = kind_code(*kernel, pv) | (sym_pow_code(*kernel) << 2);
