@@ -114,7 +114,7 @@ def sym_kernel_name(kind, m, periodic=False):
 
 
 # Sources that define the profiled kernels (their code and tile constants).
-TRAFFIC_SOURCES = ("common.h", "kernels_core.h", "kernels_mfma.h")
+TRAFFIC_SOURCES = ("common.h", "kernels_core.h", "kernels_mfma.h", "kernels_tile.h")
 
 
 def traffic_sources_sha256() -> str:
