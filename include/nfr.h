@@ -194,10 +194,11 @@ size_t nfr_problem_bytes(int64_t n);
  * The inputs are read by a kernel enqueued on the context stream and may be
  * freed once it has run.  The handle (host memory) references pack_dev, which
  * must stay allocated until nfr_problem_destroy.  The pack also holds a tile
- * order of the nodes (their Morton order, ties by index; built on the device
- * by a bitonic sort), in which the fused BF16 form runs so that blocks of
- * nearby nodes can skip the steep exponential; every call still takes and
- * returns states in the caller's node order. */
+ * order of the nodes (recursive bisection along each segment's longest axis
+ * down to blocks of 16 nodes, built on the device by bitonic sorts), in which
+ * the fused BF16 form runs so that blocks of nearby nodes can skip the steep
+ * exponential; every call still takes and returns states in the caller's
+ * node order. */
 int nfr_problem_create(nfr_context* ctx, int64_t n, const double* xyz_dev, const double* q_dev,
                        void* pack_dev, size_t pack_bytes, nfr_problem** out);
 

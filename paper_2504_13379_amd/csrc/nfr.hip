@@ -92,6 +92,8 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr int64_t kMaxN = 4000000;   // keeps every grid dimension below 65536 blocks
 constexpr int kMaxB = 4096;
+// node indices and segment counts fit the tile order's sort keys (kernels_tile.h)
+static_assert(kMaxN <= (int64_t(1) << kTileNodeBits) && kMaxN / kTileLeaf < (int64_t(1) << kTileSegBits), "tile keys");
 
 bool is_finite_d(double x) { return std::isfinite(x); }
 
@@ -706,7 +708,7 @@ PackLayout pack_layout(int64_t n) {
   L.q_t = take(npad * sizeof(double));
   L.bnd32 = take(npad / kTileRowBlock * sizeof(float4));
   L.bnd16 = take(npad / kTileColBlock * sizeof(float4));
-  L.box = take(6 * sizeof(double));
+  L.box = take(size_t(6) * (size_t(1) << tile_levels(n)) * sizeof(double));   // one box per segment
   L.keys = take(tile_pow2(npad) * sizeof(uint64_t));
   L.bytes = off;
   return L;
@@ -913,15 +915,22 @@ int nfr_problem_create_periodic(nfr_context* ctx, int64_t n, const double* xyz_d
   hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, st, xyz_dev, q_dev, n, npad, period, src, q,
                      xyz);
   hipLaunchKernelGGL(k_qmax, dim3(1), dim3(kWG), 0, st, q, src, npad, qmax);
-  // tile order: Morton keys of the packed coordinates, bitonic sort, slot arrays, block bounds
+  // tile order (kernels_tile.h): recursive bisection, each level a bitonic sort
+  // of (segment, coordinate along the segment's longest axis, node) keys;
+  // then the slot arrays and block bounds
   const int64_t np2 = tile_pow2(npad);
-  hipLaunchKernelGGL(k_tile_box, dim3(1), dim3(kWG), 0, st, src, n, box);
-  hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)ceil_div(np2, kWG)), dim3(kWG), 0, st, src, n, np2, box, keys);
-  for (int64_t k = 2; k <= np2; k <<= 1)
-    for (int64_t j = k >> 1; j > 0; j >>= 1)
-      hipLaunchKernelGGL(k_bitonic, dim3((unsigned)ceil_div(np2, kWG)), dim3(kWG), 0, st, keys, np2, k, j);
-  hipLaunchKernelGGL(k_tile_build, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, st, keys, n, npad, src, q, perm,
-                     src_t, q_t);
+  const dim3 gk((unsigned)ceil_div(np2, kWG));
+  hipLaunchKernelGGL(k_tile_init, dim3((unsigned)ceil_div(n, kWG)), dim3(kWG), 0, st, n, perm);
+  const int levels = tile_levels(n);
+  for (int l = 0; l < levels; ++l) {
+    hipLaunchKernelGGL(k_tile_seg_box, dim3((unsigned)(int64_t(1) << l)), dim3(kWG), 0, st, src, perm, n, l, box);
+    hipLaunchKernelGGL(k_tile_seg_keys, gk, dim3(kWG), 0, st, src, perm, n, np2, l, box, keys);
+    for (int64_t k = 2; k <= np2; k <<= 1)
+      for (int64_t j = k >> 1; j > 0; j >>= 1) hipLaunchKernelGGL(k_bitonic, gk, dim3(kWG), 0, st, keys, np2, k, j);
+    hipLaunchKernelGGL(k_tile_take, dim3((unsigned)ceil_div(n, kWG)), dim3(kWG), 0, st, keys, n, perm);
+  }
+  hipLaunchKernelGGL(k_tile_build, dim3((unsigned)ceil_div(npad, kWG)), dim3(kWG), 0, st, n, npad, src, q, perm, src_t,
+                     q_t);
   const int64_t nb32 = npad / kTileRowBlock, nb16 = npad / kTileColBlock;
   hipLaunchKernelGGL(k_tile_bounds<kTileRowBlock>, dim3((unsigned)ceil_div(nb32, kWG)), dim3(kWG), 0, st, src_t, n, nb32,
                      bnd32);

@@ -59,16 +59,18 @@ def test_size_queries(L):
 def test_problem_layout_and_tune_workspace(L):
     """Packed problem: float4 coordinates | FP64 weights | FP64 coordinates |
     two FP64 maxima | tile order: int32 slot -> node, float4 coordinates, FP64
-    weights, float4 bounds of 32- and 16-slot blocks, the FP64 bounding box and
-    64-bit sort keys for the next power of two; each 256-byte aligned, N padded
-    to 256."""
+    weights, float4 bounds of 32- and 16-slot blocks, an FP64 bounding box per
+    segment of the deepest bisection level (2^L, L = ceil(log2(ceil(N / 16))))
+    and 64-bit sort keys for the next power of two; each 256-byte aligned, N
+    padded to 256."""
     a = lambda b: (b + 255) // 256 * 256
     for n in (1, 255, 256, 1000, 65536, 70000):
         npad = (n + 255) // 256 * 256
         np2 = 1 << (npad - 1).bit_length()
+        levels = (-(-n // 16) - 1).bit_length()
         assert L.nfr_problem_bytes(n) == (a(npad * 16) + a(npad * 8) + a(3 * npad * 8) + a(16) + a(npad * 4)
                                           + a(npad * 16) + a(npad * 8) + a(npad // 32 * 16) + a(npad // 16 * 16)
-                                          + a(48) + a(np2 * 8))
+                                          + a(48 << levels) + a(np2 * 8))
     assert L.nfr_tune_workspace_size(512, 64) == 0        # n_max below 1024
     assert L.nfr_tune_workspace_size(65536, 1) == 0       # B_max below 2
     assert L.nfr_tune_workspace_size(65536, 64) > L.nfr_tune_workspace_size(65536, 16) > 0
