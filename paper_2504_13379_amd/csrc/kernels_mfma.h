@@ -415,6 +415,13 @@ struct MfmaOtfParams {
 #ifndef NFR_MFMA_OTF_MIN_WGS
 #define NFR_MFMA_OTF_MIN_WGS 2
 #endif
+// BF16: four workgroups per compute unit (128 registers, 4 waves per SIMD);
+// with t from the matrix cores the compiler would take 148 registers (3 waves)
+// and the kernel ran 1.5 % slower (1.788 against 1.762 ms per application at
+// N = 65536, B = 64); at 128 it spills a few values held across the loop only.
+#ifndef NFR_MFMA_OTF_BF16_MIN_WGS
+#define NFR_MFMA_OTF_BF16_MIN_WGS 4
+#endif
 // LDS buffers of the staged G tile.  FP16 keeps two (one step's tile is
 // written while the other is read; one barrier per step).  BF16 uses one
 // (a second barrier per step) and halves its LDS: 2.29 -> 2.22-2.24 ms per
@@ -458,6 +465,14 @@ constexpr double kNormMaxT = 96.0;
 #ifndef NFR_MFMA_OTF_DPP
 #define NFR_MFMA_OTF_DPP 1
 #endif
+// Norm expansion with t from the FP32 matrix cores: per 32 columns two
+// 32x32x2 FP32 MFMAs take the four products of every entry off the vector
+// units (which then only evaluate the exponentials and split): 1.85 -> 1.76 ms
+// per application at N = 65536, B = 64 (same GPU session), against the
+// broadcast multiply-adds below.
+#ifndef NFR_MFMA_OTF_TMMA
+#define NFR_MFMA_OTF_TMMA 1
+#endif
 
 template <int... I, typename F>
 __device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F&& f) {
@@ -483,7 +498,7 @@ __device__ __forceinline__ void fmac_row_bcast(float& acc, float v, float x) {
       : "v"(v), "v"(x), "n"(E));
 }
 template <typename T, int KIND, int NB>
-__global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
+__global__ __launch_bounds__(kWG, MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : NFR_MFMA_OTF_BF16_MIN_WGS) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
                                                      const T* __restrict__ Glo, int64_t npad, int B, int64_t kchunk,
                                                      MfmaOtfParams op, double* __restrict__ part) {
   typedef typename MfmaTraits<T>::vec V;
@@ -623,7 +638,12 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
       const float4 bn = op.bnd16[ok ? cb : cend - 1];
       fmask = __ballot(ok && tile_far(rbnd, bn, op.d2far));
     };
-    const double wsd = wave < 3 ? -2.0 * s2d : s2d;
+    // t from the matrix cores (below); in the far form the column values carry
+    // rho, so that the matrix product is rho a, the broad exponential's argument
+    constexpr bool kTmma = kNorm && NFR_MFMA_OTF_TMMA;
+    constexpr bool kFarT = kFar && kTmma && !kTwoAcc && c == 0;
+    const double wsd = (wave < 3 ? -2.0 * s2d : s2d) * (kFarT ? (double)op.rho : 1.0);
+    const float irho = kFarT ? (float)(1.0 / (double)op.rho) : 0.0f;
     auto store_next = [&](int t) {
       const int buf = t % kOtfBufs;
 #pragma unroll
@@ -635,8 +655,25 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
     // column 16 (2p + s) + 8 (R / 2) + e (R = row of 16 lanes, h = R / 2), so
     // that row_newbcast:(8 s + e) hands lane m + 32 h the column 16 kb + 8 h + e
     // of MFMA step kb = 2p + s (the A operand's column of its entry e)
-    constexpr bool kDpp = kNorm && NFR_MFMA_OTF_DPP;
+    constexpr bool kDpp = kNorm && !kTmma && NFR_MFMA_OTF_DPP;
     static_assert(kMfmaKb % 2 == 0, "column registers hold MFMA steps in pairs");
+    // t by matrix cores: for the 32 columns of MFMA steps 2p and 2p + 1, the
+    // product of the columns' (-2 sig^2 x, -2 sig^2 y, -2 sig^2 z, sig^2 |x|^2)
+    // (A operand, 32 x 4) and the rows' (x, y, z, 1) (B operand, 4 x 32) is
+    // the transposed block of t - n_i: lane m + 32 h holds row m and output
+    // rows 8 (v / 4) + 4 h + v % 4.  Lane j reads column j with bits 2 and 3
+    // swapped, so output v = 8 s + e of lane m + 32 h is column 16 s + 8 h + e:
+    // entry e of MFMA step 2p + s in the layout of the split's A operand.
+    // Both blocks of a pipeline step are multiplied at its start (TT[p]).
+    const float tb0 = h ? yi : xi, tb1 = h ? 1.0f : zi;
+    const int tcol = (m & 0x13) | ((m & 4) << 1) | ((m & 8) >> 1);
+    f32x16_t TT[kMfmaKb / 2];
+    auto tmma = [&](int buf, int p) {
+      const float a0 = sS[buf][h][32 * p + tcol], a1 = sS[buf][2 + h][32 * p + tcol];
+      const f32x16_t zero = {};
+      TT[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, tb0, zero, 0, 0, 0);
+      TT[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, tb1, TT[p], 0, 0, 0);
+    };
     float X[kMfmaKb / 2][4];
     const int jl = 16 * ((lane & 15) >> 3) + 8 * (lane >> 5) + (lane & 7);
     auto load_cols = [&](int buf) {
@@ -646,12 +683,44 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
         for (int r = 0; r < 4; ++r) X[p][r] = sS[buf][r][32 * p + jl];
     };
     int tstep = 0;
+    // split pairwise: one conversion instruction rounds two entries
+    auto split = [&](const float (&w)[8], V& whi, V& wlo, auto dot2_tag) {
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        typedef __attribute__((ext_vector_type(2))) float f2_t;
+        typedef __attribute__((ext_vector_type(2))) T h2_t;
+        const f2_t wv = {w[e], w[e + 1]};
+        const h2_t hv = __builtin_convertvector(wv, h2_t);
+        f2_t rv;
+        if constexpr (decltype(dot2_tag)::value) {
+          // remainders w - hi in one instruction per entry: the packed pair's
+          // dot product with (-1, 0) or (0, -1), plus w (exact: the BF16
+          // products are exact in FP32 and w - hi is representable).  The
+          // constant pairs come from registers: as an inline constant the
+          // compiler encodes (-1, 0) as -1.0, which this instruction reads as
+          // the FP32 pattern, i.e. the pair (0, -1) (checked on the device)
+          rv[0] = __builtin_amdgcn_fdot2_f32_bf16(hv, __builtin_bit_cast(h2_t, m10i), w[e], false);
+          rv[1] = __builtin_amdgcn_fdot2_f32_bf16(hv, __builtin_bit_cast(h2_t, m01i), w[e + 1], false);
+        } else {
+          const f2_t hf = __builtin_convertvector(hv, f2_t);
+          rv = wv - hf;
+        }
+        if (c) rv *= (float)(1 << c);
+        const h2_t lv = __builtin_convertvector(rv, h2_t);
+        whi[e] = hv[0];
+        whi[e + 1] = hv[1];
+        wlo[e] = lv[0];
+        wlo[e + 1] = lv[1];
+      }
+    };
     auto eval = [&](int buf, auto kbc, V& whi, V& wlo) {
       constexpr int kb = decltype(kbc)::value;
       const int col = 16 * kb + 8 * h;
       float w[8];
       float tb[8];
-      if constexpr (kDpp) {
+      if constexpr (kTmma) {
+        static_for<8>([&](auto ec) { tb[ec] = TT[kb / 2][8 * (kb % 2) + decltype(ec)::value]; });
+      } else if constexpr (kDpp) {
         // the same fused multiply-adds in the same order as from LDS, the 8
         // entries interleaved (a broadcast multiply-add must not read an
         // accumulator written by the instruction just before it)
@@ -691,48 +760,67 @@ __global__ __launch_bounds__(kWG, NFR_MFMA_OTF_MIN_WGS) void k_mfma_otf(const fl
           w[e] = pair_u<KIND>(tt, op.rho, kap);
         if (kTwoAcc) w[e] *= lift;
       });
-      // split pairwise: one conversion instruction rounds two entries
-#pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        typedef __attribute__((ext_vector_type(2))) float f2_t;
-        typedef __attribute__((ext_vector_type(2))) T h2_t;
-        const f2_t wv = {w[e], w[e + 1]};
-        const h2_t hv = __builtin_convertvector(wv, h2_t);
-        f2_t rv;
-        if constexpr (!kTwoAcc && NFR_MFMA_OTF_DOT2) {
-          // remainders w - hi in one instruction per entry: the packed pair's
-          // dot product with (-1, 0) or (0, -1), plus w (exact: the BF16
-          // products are exact in FP32 and w - hi is representable).  The
-          // constant pairs come from registers: as an inline constant the
-          // compiler encodes (-1, 0) as -1.0, which this instruction reads as
-          // the FP32 pattern, i.e. the pair (0, -1) (checked on the device)
-          rv[0] = __builtin_amdgcn_fdot2_f32_bf16(hv, __builtin_bit_cast(h2_t, m10i), w[e], false);
-          rv[1] = __builtin_amdgcn_fdot2_f32_bf16(hv, __builtin_bit_cast(h2_t, m01i), w[e + 1], false);
-        } else {
-          const f2_t hf = __builtin_convertvector(hv, f2_t);
-          rv = wv - hf;
-        }
-        if (c) rv *= (float)(1 << c);
-        const h2_t lv = __builtin_convertvector(rv, h2_t);
-        whi[e] = hv[0];
-        whi[e + 1] = hv[1];
-        wlo[e] = lv[0];
-        wlo[e + 1] = lv[1];
-      }
+      split(w, whi, wlo, std::bool_constant<!kTwoAcc && NFR_MFMA_OTF_DOT2>{});
+    };
+    // far form with t from the matrix cores (TT = rho a): every entry's broad
+    // exponential (pre) is split from the near blocks' steep term and the
+    // split (fin), so that the products of MFMA step kb share a basic block
+    // with the broad exponentials of step kb + 1.  The remainders take a
+    // shift and a subtraction instead of the dot-product instruction, which
+    // does not run beside the matrix cores (a probe: 24 of them took their
+    // full time on top of 6 MFMAs, where conversions, shifts and FP32 adds or
+    // multiply-adds were 93-100 % hidden): 1.74 -> 1.72 ms per application.
+    auto pre = [&](auto kbc, float (&w)[8]) {
+      constexpr int kb = decltype(kbc)::value;
+      static_for<8>([&](auto ec) { w[ec] = __builtin_amdgcn_exp2f(-TT[kb / 2][8 * (kb % 2) + decltype(ec)::value]); });
+    };
+    auto fin = [&](auto kbc, float (&w)[8], V& whi, V& wlo) {
+      constexpr int kb = decltype(kbc)::value;
+      // (1 - rho) t beyond 27 - log2|kappa| in every entry of a far block: the
+      // steep term is below half an ulp of the broad one, whose value the sum takes
+      const bool far = (fmask >> (4 * (tstep & 15) + kb)) & 1;
+      if (!far)
+        static_for<8>([&](auto ec) {
+          constexpr int e = decltype(ec)::value;
+          w[e] = fmaf(kap, __builtin_amdgcn_exp2f(-(TT[kb / 2][8 * (kb % 2) + e] * irho)), w[e]);
+        });
+      split(w, whi, wlo, std::false_type{});
     };
     auto compute = [&](int t) {
       const int buf = t % kOtfBufs;
       tstep = t;
       if constexpr (kDpp) load_cols(buf);
-      V h0, l0, h1, l1;
-      eval(buf, std::integral_constant<int, 0>{}, h0, l0);
-      static_for<kMfmaKb / 2>([&](auto pc) {
-        constexpr int kb = 2 * decltype(pc)::value;
-        eval(buf, std::integral_constant<int, kb + 1>{}, h1, l1);
-        mma(buf, kb, h0, l0);
-        if constexpr (kb + 2 < kMfmaKb) eval(buf, std::integral_constant<int, kb + 2>{}, h0, l0);
-        mma(buf, kb + 1, h1, l1);
-      });
+      if constexpr (kTmma) static_for<kMfmaKb / 2>([&](auto pc) { tmma(buf, decltype(pc)::value); });
+      if constexpr (kFarT) {
+        using K0 = std::integral_constant<int, 0>;
+        using K1 = std::integral_constant<int, 1>;
+        using K2 = std::integral_constant<int, 2>;
+        using K3 = std::integral_constant<int, 3>;
+        V h0, l0, h1, l1;
+        float wa[8], wb[8];
+        pre(K0{}, wa);
+        fin(K0{}, wa, h0, l0);
+        pre(K1{}, wb);
+        mma(buf, 0, h0, l0);
+        fin(K1{}, wb, h1, l1);
+        pre(K2{}, wa);
+        mma(buf, 1, h1, l1);
+        fin(K2{}, wa, h0, l0);
+        pre(K3{}, wb);
+        mma(buf, 2, h0, l0);
+        fin(K3{}, wb, h1, l1);
+        mma(buf, 3, h1, l1);
+      } else {
+        V h0, l0, h1, l1;
+        eval(buf, std::integral_constant<int, 0>{}, h0, l0);
+        static_for<kMfmaKb / 2>([&](auto pc) {
+          constexpr int kb = 2 * decltype(pc)::value;
+          eval(buf, std::integral_constant<int, kb + 1>{}, h1, l1);
+          mma(buf, kb, h0, l0);
+          if constexpr (kb + 2 < kMfmaKb) eval(buf, std::integral_constant<int, kb + 2>{}, h0, l0);
+          mma(buf, kb + 1, h1, l1);
+        });
+      }
     };
     // step t: issue the loads of step t + 1, evaluate and multiply step t from
     // LDS buffer t % kOtfBufs, (one buffer: barrier), store step t + 1 into the
