@@ -72,20 +72,31 @@ def slots_per_unordered_pair(kind, m):
     return eval_slots(kind, m) + 2
 
 
-def fused_slots_per_w(kind, m, fp16=False, norm=False, far=False):
+def fused_slots_per_w(kind, m, fp16=False, norm=False, far=None):
     """Slots per W entry of the fused on-the-fly split forms: the evaluation of u
     above (the weights sit in G) and the hi/lo split: FP16 3 (two conversions of
     a pair of entries at half a slot each, the hi value back to FP32, the
     subtraction) plus the lift of u; BF16 2 (the remainder w - hi is one
-    dot-product instruction).  With the norm expansion of r^2 (BF16, see
-    fused_norm_path) the 3 subtractions, the square and 2 multiply-adds of r^2
-    are 3 multiply-adds, the row's |x_i|^2 being a row factor: 3 slots fewer.
-    An entry of a far block (BF16, norm expansion, two exponentials; see
-    nfr_far_blocks) takes the 3 multiply-adds, one exp2 and the split: 9."""
-    if far:
-        return 3 + TRANS_COST + 2
+    dot-product instruction).  With the norm expansion (BF16, see
+    fused_norm_path) t comes from the FP32 matrix cores (FUSED_T_FLOPS_PER_W):
+    the 3 subtractions, the square and the 2 multiply-adds of r^2 leave the
+    vector units.  The far form (far not None: BF16, norm expansion, two
+    exponentials, nfr_far_blocks) takes rho t from the matrix product and splits
+    by shift and subtraction (3 slots, as the dot-product instruction does not
+    run beside the matrix cores): an entry of a far block is one exp2 and the
+    split (7), of a near block t = (rho t) / rho, two exp2, a multiply-add and
+    the split (13)."""
+    if far is not None:
+        return TRANS_COST + 3 if far else 1 + 2 * TRANS_COST + 1 + 3
     split = 3 + 1 if fp16 else 2
-    return eval_slots(kind, m) - (3 if norm else 0) + split
+    return eval_slots(kind, m) - (6 if norm else 0) + split
+
+
+# FP32 matrix-core flops per W entry of the norm expansion: t is the product of
+# the column's 4 values and the row's 4 values (32x32x2 FP32 MFMAs).
+FUSED_T_FLOPS_PER_W = 8.0
+# BF16 matrix-core flops per W entry of the split forms: 3 products x 2 flop x 64 states.
+FUSED_BF16_FLOPS_PER_W = 384.0
 
 
 # The fused BF16 kernel evaluates r^2 of Gaussian kernels on non-periodic
@@ -238,18 +249,35 @@ def ensemble_roofline(nm, npad, kind, kernel, avg_s, max_r2, far_frac=0.0):
                 "unit": "Tslot/s", "frac": slots / avg_s / VALU_LANES_PER_S, "traffic": measured_traffic(kname),
                 "kernel": kname}
     # fused on-the-fly split forms: every W entry evaluated once per launch on the vector
-    # units; the matrix cores do 3 products x 2 flop x 64 states per entry
+    # units (t of the norm expansion on the FP32 matrix cores); the BF16 matrix cores do
+    # 3 products x 2 flop x 64 states per entry.  The bound is the larger of the vector
+    # slot share and the matrix-core time share (BF16 flops at the BF16 peak plus FP32
+    # flops at the FP32 peak); for the matrix cores `achieved` is in BF16-equivalent
+    # flop/s (FP32 flops weighted by the ratio of the two peaks).
     fp16 = nm == "otf_fp16x3"
     norm = not fp16 and fused_norm_path(kind, kernel, m, max_r2)
     kname = "k_mfma_otf<%s,%d,2>" % ("fp16" if fp16 else "bf16", kind + 4 * (m - 1 if m else 0))
     wvals = float(npad) ** 2
     far_frac = far_frac if (norm and not fp16) else 0.0
-    spw = (1.0 - far_frac) * fused_slots_per_w(kind, m, fp16, norm) + far_frac * fused_slots_per_w(kind, m, far=True)
-    achieved = wvals * spw / avg_s
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tslot/s",
-            "frac": achieved / VALU_LANES_PER_S, "traffic": measured_traffic(kname), "kernel": kname,
-            "slots_per_w": spw, "far_block_fraction": far_frac, "r2": "norm expansion" if norm else "differences",
-            "mfma_tflops": wvals * 384.0 / avg_s / 1e12, "mfma_frac": wvals * 384.0 / avg_s / MFMA_BF16_PEAK}
+    if far_frac > 0.0:
+        spw = (1.0 - far_frac) * fused_slots_per_w(kind, m, far=False) + far_frac * fused_slots_per_w(kind, m, far=True)
+    else:
+        spw = fused_slots_per_w(kind, m, fp16, norm)
+    alu = wvals * spw / avg_s
+    f32 = FUSED_T_FLOPS_PER_W if norm else 0.0
+    mtime = wvals * (FUSED_BF16_FLOPS_PER_W / MFMA_BF16_PEAK + f32 / MFMA_F32_PEAK)
+    mfrac = mtime / avg_s
+    common = {"traffic": measured_traffic(kname), "kernel": kname, "slots_per_w": spw, "far_block_fraction": far_frac,
+              "r2": "norm expansion (t on the FP32 matrix cores)" if norm else "differences",
+              "alu_frac": alu / VALU_LANES_PER_S,
+              "mfma_bf16_tflops": wvals * FUSED_BF16_FLOPS_PER_W / avg_s / 1e12,
+              "mfma_f32_tflops": wvals * f32 / avg_s / 1e12, "mfma_time_frac": mfrac}
+    if mfrac >= alu / VALU_LANES_PER_S:
+        return {"bound": "mfma", "achieved": mfrac * MFMA_BF16_PEAK / 1e12, "peak": MFMA_BF16_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": mfrac, "achieved_is": "BF16-equivalent (FP32 flops x BF16/FP32 peak)",
+                **common}
+    return {"bound": "alu", "achieved": alu / 1e12, "peak": VALU_LANES_PER_S / 1e12, "unit": "Tslot/s",
+            "frac": alu / VALU_LANES_PER_S, **common}
 
 
 def ensemble_headline(P, torch, args):
@@ -715,7 +743,8 @@ def probes(P, torch, ctx):
     for name, which, size in (("fma_lane_ops", 0, 20000), ("fma_vop3_lane_ops", 6, 20000), ("exp_lane_ops", 1, 5000),
                               ("sqrt_lane_ops", 2, 5000), ("fma_exp_mix_lane_ops", 7, 5000),
                               ("mfma_bf16_flops", 5, 20000), ("mfma_f32_flops", 8, 20000),
-                              ("mfma_f32_beside_fma_flops", 9, 20000), ("mfma_bf16_beside_fma_flops", 10, 20000)):
+                              ("mfma_f32_beside_fma_flops", 9, 20000), ("mfma_bf16_beside_fma_flops", 10, 20000),
+                              ("mfma_bf16_beside_dot2_flops", 11, 20000), ("mfma_bf16_beside_mask_fma_flops", 12, 20000)):
         best = 0.0
         for _ in range(2):                          # the first launch may run before the clock has ramped
             r = ctypes.c_double()

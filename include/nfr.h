@@ -162,7 +162,11 @@ int nfr_context_last_graph(const nfr_context* ctx, int64_t* nodes, int64_t* step
  *                   beside eight FMA chains (32 FMAs per iteration, no data
  *                   shared): equal to MFMA_F32 if the vector units run while
  *                   the matrix cores do, half of it if the two alternate;
- *   MFMA_BF16_FMA:  the same with four 32x32x16 BF16 MFMAs per iteration.
+ *   MFMA_BF16_FMA:  the same with four 32x32x16 BF16 MFMAs per iteration;
+ *   MFMA_BF16_DOT2: the four BF16 MFMAs beside 32 v_dot2c_f32_bf16 (eight
+ *                   chains) per iteration;
+ *   MFMA_BF16_MASK: the four BF16 MFMAs beside 16 masks and 16 FMAs (eight
+ *                   chains of x <- x - 2^-30 (x & 0xffff0000)) per iteration.
  * buf_dev must hold 4*size bytes plus one float per thread of a grid of
  * 8 workgroups per compute unit (HBM_READ), 8*size bytes (HBM_COPY), or one
  * float per thread (others). */
@@ -177,7 +181,9 @@ enum nfr_probe_kind {
   NFR_PROBE_FMA_EXP = 7,
   NFR_PROBE_MFMA_F32 = 8,
   NFR_PROBE_MFMA_F32_FMA = 9,
-  NFR_PROBE_MFMA_BF16_FMA = 10
+  NFR_PROBE_MFMA_BF16_FMA = 10,
+  NFR_PROBE_MFMA_BF16_DOT2 = 11,
+  NFR_PROBE_MFMA_BF16_MASK = 12
 };
 int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t buf_bytes, double* rate);
 

@@ -244,4 +244,57 @@ __global__ __launch_bounds__(kWG) void k_probe_mfma_bf16_fma(int64_t iters, floa
   out[gid] = r;
 }
 
+// The same four BF16 MFMAs per iteration beside 32 other vector instructions
+// in eight independent chains: OP 0 v_dot2c_f32_bf16 (x <- x + pair . k, the
+// one-instruction remainder of a BF16 split), OP 1 a mask and a multiply-add
+// (x <- x - 2^-30 (x & 0xffff0000), the shape of the shift-and-subtract
+// remainder).
+template <int OP>
+__global__ __launch_bounds__(kWG) void k_probe_mfma_bf16_vop(int64_t iters, float* __restrict__ out) {
+  typedef __attribute__((ext_vector_type(2))) __bf16 probe_bf16x2;
+  const int64_t gid = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  probe_bf16x8 a, b;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    a[e] = (__bf16)(1e-3f * (float)((threadIdx.x + e) & 7));
+    b[e] = (__bf16)(1e-3f * (float)((threadIdx.x * 3 + e) & 7));
+  }
+  probe_f32x16 c0 = {}, c1 = {};
+  float x[kProbeChains];
+  probe_bf16x2 p[kProbeChains];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) {
+    x[c] = 1.0f + 1e-7f * (float)(threadIdx.x + c);
+    p[c][0] = (__bf16)(1e-6f * (float)((threadIdx.x + c) & 7));
+    p[c][1] = (__bf16)(1e-6f * (float)((threadIdx.x + 5 * c) & 7));
+  }
+  const probe_bf16x2 k = {(__bf16)0.5f, (__bf16)-0.25f};
+  for (int64_t it = 0; it < iters; ++it) {
+    c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c1, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c1, 0, 0, 0);
+    if constexpr (OP == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < kProbeChains; ++c) x[c] = __builtin_amdgcn_fdot2_f32_bf16(p[c], k, x[c], false);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < kProbeChains; ++c) {
+          const float hi = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x[c]) & 0xffff0000u);
+          x[c] = fmaf(-0x1p-30f, hi, x[c]);
+        }
+    }
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) r += c0[e] + c1[e];
+#pragma unroll
+  for (int c = 0; c < kProbeChains; ++c) r += x[c];
+  out[gid] = r;
+}
+
 }  // namespace nfr

@@ -802,7 +802,7 @@ int nfr_context_timing(nfr_context* ctx, int64_t* launches, double* total_ms) {
 
 int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t buf_bytes, double* rate) {
   if (!ctx || !buf_dev || !rate) return fail(NFR_ERR_INVALID_ARG, "NULL argument");
-  if (which < NFR_PROBE_FMA || which > NFR_PROBE_MFMA_BF16_FMA) return fail(NFR_ERR_INVALID_ARG, "unknown probe %d", which);
+  if (which < NFR_PROBE_FMA || which > NFR_PROBE_MFMA_BF16_MASK) return fail(NFR_ERR_INVALID_ARG, "unknown probe %d", which);
   if (size < 1) return fail(NFR_ERR_INVALID_ARG, "size must be >= 1");
   const int64_t grid = (int64_t)ctx->cu_count * 8;
   const size_t out_bytes = size_t(grid) * kWG * sizeof(float);
@@ -830,6 +830,8 @@ int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t b
     case NFR_PROBE_MFMA_F32: hipLaunchKernelGGL(k_probe_mfma_f32, g, b, 0, s, size, f); break;
     case NFR_PROBE_MFMA_F32_FMA: hipLaunchKernelGGL(k_probe_mfma_f32_fma, g, b, 0, s, size, f); break;
     case NFR_PROBE_MFMA_BF16_FMA: hipLaunchKernelGGL(k_probe_mfma_bf16_fma, g, b, 0, s, size, f); break;
+    case NFR_PROBE_MFMA_BF16_DOT2: hipLaunchKernelGGL(k_probe_mfma_bf16_vop<0>, g, b, 0, s, size, f); break;
+    case NFR_PROBE_MFMA_BF16_MASK: hipLaunchKernelGGL(k_probe_mfma_bf16_vop<1>, g, b, 0, s, size, f); break;
     default: hipLaunchKernelGGL(k_probe_mfma, g, b, 0, s, size, f); break;
   }
   hipError_t le = hipGetLastError();
@@ -853,6 +855,8 @@ int nfr_probe(nfr_context* ctx, int which, int64_t size, void* buf_dev, size_t b
     case NFR_PROBE_MFMA_F32: *rate = double(grid) * (kWG / 64) * 4 * double(size) * (32.0 * 32 * 2 * 2) / sec; break;
     case NFR_PROBE_MFMA_F32_FMA: *rate = double(grid) * (kWG / 64) * 2 * double(size) * (32.0 * 32 * 2 * 2) / sec; break;
     case NFR_PROBE_MFMA_BF16_FMA:
+    case NFR_PROBE_MFMA_BF16_DOT2:
+    case NFR_PROBE_MFMA_BF16_MASK:
       *rate = double(grid) * (kWG / 64) * 4 * double(size) * (32.0 * 32 * 16 * 2) / sec;
       break;
     default: *rate = double(grid) * (kWG / 64) * 4 * double(size) * (32.0 * 32 * 16 * 2) / sec; break;
