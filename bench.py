@@ -260,6 +260,8 @@ def ensemble_roofline(nm, npad, kind, kernel, avg_s, max_r2, far_frac=0.0):
     wvals = float(npad) ** 2
     far_frac = far_frac if (norm and not fp16) else 0.0
     if far_frac > 0.0:
+        kname = "k_mfma_otf<bf16,%d,2,8>" % kind      # the far form runs in eight-wave workgroups
+    if far_frac > 0.0:
         spw = (1.0 - far_frac) * fused_slots_per_w(kind, m, far=False) + far_frac * fused_slots_per_w(kind, m, far=True)
     else:
         spw = fused_slots_per_w(kind, m, fp16, norm)

@@ -419,6 +419,12 @@ struct MfmaOtfParams {
 // with t from the matrix cores the compiler would take 148 registers (3 waves)
 // and the kernel ran 1.5 % slower (1.788 against 1.762 ms per application at
 // N = 65536, B = 64); at 128 it spills a few values held across the loop only.
+// BF16 far form in eight-wave workgroups whose wave pairs take turns on the
+// vector units and the matrix cores (the ping-pong loop in k_mfma_otf).
+#ifndef NFR_MFMA_OTF_PINGPONG
+#define NFR_MFMA_OTF_PINGPONG 1
+#endif
+constexpr bool kMfmaOtfPingPong = NFR_MFMA_OTF_PINGPONG;
 #ifndef NFR_MFMA_OTF_BF16_MIN_WGS
 #define NFR_MFMA_OTF_BF16_MIN_WGS 4
 #endif
@@ -497,8 +503,8 @@ __device__ __forceinline__ void fmac_row_bcast(float& acc, float v, float x) {
       : "+v"(acc)
       : "v"(v), "v"(x), "n"(E));
 }
-template <typename T, int KIND, int NB>
-__global__ __launch_bounds__(kWG, MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : NFR_MFMA_OTF_BF16_MIN_WGS) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
+template <typename T, int KIND, int NB, int WAVES = 4>
+__global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 4 : (MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : NFR_MFMA_OTF_BF16_MIN_WGS)) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
                                                      const T* __restrict__ Glo, int64_t npad, int B, int64_t kchunk,
                                                      MfmaOtfParams op, double* __restrict__ part) {
   typedef typename MfmaTraits<T>::vec V;
@@ -506,8 +512,14 @@ __global__ __launch_bounds__(kWG, MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : N
   constexpr bool kTwoAcc = MfmaTraits<T>::fp16;
   constexpr int NS = 32 * NB;
   constexpr int ROWCH = kMfmaStep / 8;
-  constexpr int CHUNKS = NS * 2 * ROWCH / kWG;
-  constexpr int kOtfBufs = kTwoAcc ? NFR_MFMA_OTF_FP16_LDS_BUFS : NFR_MFMA_OTF_BF16_LDS_BUFS;
+  // WAVES = 8 (BF16, far form): 256 rows per workgroup, waves w and w + 4 on
+  // one SIMD taking turns on the vector units and the matrix cores (see the
+  // ping-pong loop below); the G tile, double-buffered, serves all eight
+  static_assert(WAVES == 4 || (WAVES == 8 && !MfmaTraits<T>::fp16), "eight waves: BF16 only");
+  constexpr bool kPP = WAVES == 8;
+  constexpr int kThreads = 64 * WAVES;
+  constexpr int CHUNKS = NS * 2 * ROWCH / kThreads;
+  constexpr int kOtfBufs = kPP ? 2 : (kTwoAcc ? NFR_MFMA_OTF_FP16_LDS_BUFS : NFR_MFMA_OTF_BF16_LDS_BUFS);
   constexpr bool kNormCapable = (KIND & 3) == 0 && !kTwoAcc && NFR_MFMA_OTF_NORM;
   __shared__ __attribute__((aligned(16))) T sG[kOtfBufs][2][NS][kMfmaLdsStride];
   // column values: rows 0-2 the coordinates scaled by sig (norm expansion:
@@ -515,7 +527,7 @@ __global__ __launch_bounds__(kWG, MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : N
   // and stores row w, so no load sits behind a branch
   __shared__ __attribute__((aligned(16))) float sS[kOtfBufs][4][kMfmaStep];
   // norm expansion: row factors of the wave's 32 rows, applied in the epilogue
-  __shared__ double sR[4][32];
+  __shared__ double sR[WAVES][32];
   static_assert(kWG == 4 * 64, "one wave per coordinate row");
 
   const int64_t wg = blockIdx.x;
@@ -527,7 +539,7 @@ __global__ __launch_bounds__(kWG, MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : N
   const int wave = tid >> 6;
   const int m = lane & 31;
   const int h = lane >> 5;
-  const int64_t row0 = rb * kMfmaRowsPerWG + wave * 32;
+  const int64_t row0 = rb * (32 * WAVES) + wave * 32;
   const int64_t k_begin = (int64_t)split * kchunk;
   int64_t k_end = k_begin + kchunk;
   if (k_end > npad) k_end = npad;
@@ -549,7 +561,7 @@ __global__ __launch_bounds__(kWG, MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : N
   int g_hl[CHUNKS], g_st[CHUNKS], g_col[CHUNKS];
 #pragma unroll
   for (int q = 0; q < CHUNKS; ++q) {
-    const int cc = tid + kWG * q;
+    const int cc = tid + kThreads * q;
     const int row = cc / ROWCH;
     g_hl[q] = row / NS;
     g_st[q] = row % NS;
@@ -571,7 +583,7 @@ __global__ __launch_bounds__(kWG, MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : N
     const int64_t tc = t < nsteps ? t : nsteps - 1;
 #pragma unroll
     for (int q = 0; q < CHUNKS; ++q) gn[q] = *reinterpret_cast<const u32x4_t*>(gsrc[q] + tc * kMfmaStep);
-    sn = reinterpret_cast<const float*>(src + k_begin + tc * kMfmaStep + lane)[wave];
+    sn = reinterpret_cast<const float*>(src + k_begin + tc * kMfmaStep + lane)[wave & 3];
   };
   auto mma = [&](int buf, int kb, const V& whi, const V& wlo) {
     const int col = 16 * kb + 8 * h;
@@ -642,13 +654,13 @@ __global__ __launch_bounds__(kWG, MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : N
     // rho, so that the matrix product is rho a, the broad exponential's argument
     constexpr bool kTmma = kNorm && NFR_MFMA_OTF_TMMA;
     constexpr bool kFarT = kFar && kTmma && !kTwoAcc && c == 0;
-    const double wsd = (wave < 3 ? -2.0 * s2d : s2d) * (kFarT ? (double)op.rho : 1.0);
+    const double wsd = ((wave & 3) < 3 ? -2.0 * s2d : s2d) * (kFarT ? (double)op.rho : 1.0);
     const float irho = kFarT ? (float)(1.0 / (double)op.rho) : 0.0f;
     auto store_next = [&](int t) {
       const int buf = t % kOtfBufs;
 #pragma unroll
       for (int q = 0; q < CHUNKS; ++q) *reinterpret_cast<u32x4_t*>(&sG[buf][g_hl[q]][g_st[q]][g_col[q]]) = gn[q];
-      sS[buf][wave][lane] = kNorm ? (float)((double)sn * wsd) : sn * op.sig;
+      if (wave < 4) sS[buf][wave][lane] = kNorm ? (float)((double)sn * wsd) : sn * op.sig;
     };
     // norm expansion with broadcasts: X[p][r] holds coordinate row r of the
     // step's columns for MFMA steps 2p and 2p + 1, lane 16 R + 8 s + e holding
@@ -822,6 +834,66 @@ __global__ __launch_bounds__(kWG, MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : N
         });
       }
     };
+    // Ping-pong (eight waves, far form): waves w and w + 4 share a SIMD, and
+    // the step runs in four phases separated by barriers, in which one of the
+    // two evaluates (vector units) while the other multiplies (matrix cores):
+    //   phase  waves 0-3 (group A)        waves 4-7 (group B)
+    //   0      evaluate t, steps 0-1      multiply t - 1, steps 2-3
+    //   1      multiply t, steps 0-1      evaluate t, steps 0-1
+    //   2      evaluate t, steps 2-3      multiply t, steps 0-1    (+ store t + 1)
+    //   3      multiply t, steps 2-3      evaluate t, steps 2-3
+    // so the SIMD always has a vector stream and a matrix stream that do not
+    // wait for each other.  Buffer (t + 1) % 2 is stored in phase 2: its last
+    // readers (group B's products of step t - 1) finished in phase 0.
+    if constexpr (kPP && kFarT) {
+      const bool grpB = wave >= 4;
+      V h0, l0, h1, l1;
+      float wa[8], wb[8];
+      auto valu = [&](int t, auto hfc) {
+        constexpr int hf = decltype(hfc)::value;
+        const int buf = t % kOtfBufs;
+        tstep = t;
+        if constexpr (hf == 0) static_for<kMfmaKb / 2>([&](auto pc) { tmma(buf, decltype(pc)::value); });
+        using KA = std::integral_constant<int, 2 * hf>;
+        using KB = std::integral_constant<int, 2 * hf + 1>;
+        pre(KA{}, wa);
+        fin(KA{}, wa, h0, l0);
+        pre(KB{}, wb);
+        fin(KB{}, wb, h1, l1);
+      };
+      auto mmah = [&](int t, int hf) {
+        const int buf = t % kOtfBufs;
+        mma(buf, 2 * hf, h0, l0);
+        mma(buf, 2 * hf + 1, h1, l1);
+      };
+      using H0 = std::integral_constant<int, 0>;
+      using H1 = std::integral_constant<int, 1>;
+      if (nsteps > 0) {
+        load_next(0);
+        store_next(0);
+        __syncthreads();
+        for (int t = 0; t < nsteps; ++t) {
+          if ((t & 15) == 0) make_mask(t / 16);
+          load_next(t + 1);
+          __builtin_amdgcn_sched_barrier(0);
+          if (!grpB) valu(t, H0{});
+          else if (t > 0) mmah(t - 1, 1);
+          __syncthreads();
+          if (!grpB) mmah(t, 0);
+          else valu(t, H0{});
+          __syncthreads();
+          if (!grpB) valu(t, H1{});
+          else mmah(t, 0);
+          store_next(t + 1);
+          __syncthreads();
+          if (!grpB) mmah(t, 1);
+          else valu(t, H1{});
+          __syncthreads();
+        }
+        if (grpB) mmah(nsteps - 1, 1);
+      }
+      return;
+    }
     // step t: issue the loads of step t + 1, evaluate and multiply step t from
     // LDS buffer t % kOtfBufs, (one buffer: barrier), store step t + 1 into the
     // next buffer, barrier.
@@ -1211,6 +1283,15 @@ inline void launch_mfma_otf_t(const ProblemView& pv, const MfmaOtfParams& op, in
     hipLaunchKernelGGL((k_mfma_otf<T, KIND, 1>), dim3(grid_x, 1), dim3(kWG), 0, s, pv.src,
                        static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad, B, kchunk, op, part);
   } else {
+    if constexpr (kMfmaOtfPingPong && !MfmaTraits<T>::fp16 && KIND == 0) {
+      if (op.bnd16) {
+        // far form: eight waves per workgroup (npad is a multiple of 256)
+        hipLaunchKernelGGL((k_mfma_otf<T, KIND, 2, 8>), dim3(grid_x / 2, (unsigned)(mfma_bp(B) / 64)), dim3(2 * kWG),
+                           0, s, pv.src, static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad, B, kchunk,
+                           op, part);
+        return;
+      }
+    }
     hipLaunchKernelGGL((k_mfma_otf<T, KIND, 2>), dim3(grid_x, (unsigned)(mfma_bp(B) / 64)), dim3(kWG), 0, s, pv.src,
                        static_cast<const T*>(ghi), static_cast<const T*>(glo), pv.npad, B, kchunk, op, part);
   }
