@@ -256,7 +256,7 @@ def ensemble_roofline(nm, npad, kind, kernel, avg_s, max_r2, far_frac=0.0):
     # flop/s (FP32 flops weighted by the ratio of the two peaks).
     fp16 = nm == "otf_fp16x3"
     norm = not fp16 and fused_norm_path(kind, kernel, m, max_r2)
-    kname = "k_mfma_otf<%s,%d,2>" % ("fp16" if fp16 else "bf16", kind + 4 * (m - 1 if m else 0))
+    kname = "k_mfma_otf<%s,%d,2,4>" % ("fp16" if fp16 else "bf16", kind + 4 * (m - 1 if m else 0))
     wvals = float(npad) ** 2
     far_frac = far_frac if (norm and not fp16) else 0.0
     if far_frac > 0.0:
