@@ -419,15 +419,18 @@ struct MfmaOtfParams {
 // with t from the matrix cores the compiler would take 148 registers (3 waves)
 // and the kernel ran 1.5 % slower (1.788 against 1.762 ms per application at
 // N = 65536, B = 64); at 128 it spills a few values held across the loop only.
+#ifndef NFR_MFMA_OTF_BF16_MIN_WGS
+#define NFR_MFMA_OTF_BF16_MIN_WGS 4
+#endif
 // BF16 far form in eight-wave workgroups whose wave pairs take turns on the
-// vector units and the matrix cores (the ping-pong loop in k_mfma_otf).
+// vector units and the matrix cores (the ping-pong loop in k_mfma_otf): 1.676
+// -> 1.659 ms per application at N = 65536, B = 64, measured alternately.  The
+// second launch-bounds argument is a minimum of waves per SIMD: 4 keeps the
+// eight-wave kernel at 128 registers, two workgroups per compute unit.
 #ifndef NFR_MFMA_OTF_PINGPONG
 #define NFR_MFMA_OTF_PINGPONG 1
 #endif
 constexpr bool kMfmaOtfPingPong = NFR_MFMA_OTF_PINGPONG;
-#ifndef NFR_MFMA_OTF_BF16_MIN_WGS
-#define NFR_MFMA_OTF_BF16_MIN_WGS 4
-#endif
 // LDS buffers of the staged G tile.  FP16 keeps two (one step's tile is
 // written while the other is read; one barrier per step).  BF16 uses one
 // (a second barrier per step) and halves its LDS: 2.29 -> 2.22-2.24 ms per
