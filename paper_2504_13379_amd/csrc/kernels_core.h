@@ -401,8 +401,8 @@ __global__ __launch_bounds__(64 * SPLIT) void k_otf_sym(const float4* __restrict
 // element's total (in *total, the element index in *idx).  C channels (slot
 // arrays chstride apart, as the adjoint's four) are summed together, their
 // loads in flight at once, with one barrier.  `red`: C * kWG doubles of LDS.
-template <int L, int C = 1>
-__device__ inline bool slot_total(const double* __restrict__ part, int64_t chstride, int nsplit, int64_t n,
+template <int L, int C = 1, typename PT = double>
+__device__ inline bool slot_total(const PT* __restrict__ part, int64_t chstride, int nsplit, int64_t n,
                                   int64_t npad, int B, double* red, int64_t* idx, double* total) {
   constexpr int E = kWG / L;
   const int t = threadIdx.x;
@@ -417,7 +417,7 @@ __device__ inline bool slot_total(const double* __restrict__ part, int64_t chstr
     const int64_t i = el - (int64_t)b * n;
     for (int sp = r; sp < nsplit; sp += L)
 #pragma unroll
-      for (int c = 0; c < C; ++c) y[c] += part[c * chstride + ((int64_t)sp * B + b) * npad + i];
+      for (int c = 0; c < C; ++c) y[c] += (double)part[c * chstride + ((int64_t)sp * B + b) * npad + i];
   }
   if (L > 1) {
 #pragma unroll
@@ -439,14 +439,15 @@ __device__ inline bool slot_total(const double* __restrict__ part, int64_t chstr
   return valid && r == 0;
 }
 
-// y[b*n + i] = sum of the partials of (b, i), FP64.  Grid: n*B*L threads.
-template <int L>
-__global__ __launch_bounds__(kWG) void k_reduce_partials(const double* __restrict__ part, int nsplit, int64_t n,
+// y[b*n + i] = sum of the partials of (b, i), FP64 (partials FP64, or FP32 for
+// the fused split forms).  Grid: n*B*L threads.
+template <int L, typename PT = double>
+__global__ __launch_bounds__(kWG) void k_reduce_partials(const PT* __restrict__ part, int nsplit, int64_t n,
                                                          int64_t npad, int B, double* __restrict__ y) {
   __shared__ double red[kWG];
   int64_t idx;
   double s;
-  if (slot_total<L>(part, 0, nsplit, n, npad, B, red, &idx, &s)) y[idx] = s;
+  if (slot_total<L, 1, PT>(part, 0, nsplit, n, npad, B, red, &idx, &s)) y[idx] = s;
 }
 
 // RK4 stage combination, all FP64 (L threads per (i, b), i < n; see slot_total):

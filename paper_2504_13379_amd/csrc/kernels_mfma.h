@@ -509,7 +509,7 @@ __device__ __forceinline__ void fmac_row_bcast(float& acc, float v, float x) {
 template <typename T, int KIND, int NB, int WAVES = 4>
 __global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 4 : (MfmaTraits<T>::fp16 ? NFR_MFMA_OTF_MIN_WGS : NFR_MFMA_OTF_BF16_MIN_WGS)) void k_mfma_otf(const float4* __restrict__ src, const T* __restrict__ Ghi,
                                                      const T* __restrict__ Glo, int64_t npad, int B, int64_t kchunk,
-                                                     MfmaOtfParams op, double* __restrict__ part) {
+                                                     MfmaOtfParams op, float* __restrict__ part) {
   typedef typename MfmaTraits<T>::vec V;
   constexpr int c = MfmaTraits<T>::c;
   constexpr bool kTwoAcc = MfmaTraits<T>::fp16;
@@ -952,13 +952,13 @@ __global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 4 : (MfmaTraits<T>::fp16 ?
   for (int nb = 0; nb < NB; ++nb) {
     const int b = sg * NS + nb * 32 + m;
     if (b >= B) continue;
-    double* dst = part + ((int64_t)split * B + b) * npad;
+    float* dst = part + ((int64_t)split * B + b) * npad;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int ir = 8 * (r / 4) + 4 * h + (r % 4);
       const int64_t i = row0 + ir;
       const double y = kTwoAcc ? (double)accM[nb][r] * sm + (double)accC[nb][r] * sc : (double)accM[nb][r] * sm;
-      dst[i] = norm ? y * sR[wave][ir] : y;
+      dst[i] = (float)(norm ? y * sR[wave][ir] : y);
     }
   }
 }
@@ -1122,8 +1122,8 @@ __global__ __launch_bounds__(kWG, 2) void k_mfma_otf_f32(const float4* __restric
 
 // RK4 stage combination for the split forms: as k_rk4_combine, but the next
 // stage's sources are written as Ghi/Glo (no q: it sits inside W).
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__ part, int nsplit, int64_t n,
+template <typename T, typename PT>
+__global__ __launch_bounds__(kWG) void k_mfma_combine(const PT* __restrict__ part, int nsplit, int64_t n,
                                                       int64_t npad, int B, int stage, double dt,
                                                       double* __restrict__ u, double* __restrict__ v,
                                                       double* __restrict__ ksum, Firing fr, const double* __restrict__ qd,
@@ -1135,7 +1135,7 @@ __global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
   double y = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  for (int sp = 0; sp < nsplit; ++sp) y += (double)part[((int64_t)sp * B + b) * npad + i];
   const double k = -v[idx] + y + (gamma ? gamma[idx] : 0.0);
   double ui = u[idx];
   double vn;
@@ -1163,8 +1163,8 @@ __global__ __launch_bounds__(kWG) void k_mfma_combine(const double* __restrict__
 
 // One Adams-Bashforth 5 step for the split forms (see k_ab5_combine); the next
 // sources are written as Ghi/Glo.
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_mfma_ab5_combine(const double* __restrict__ part, int nsplit, int64_t n,
+template <typename T, typename PT>
+__global__ __launch_bounds__(kWG) void k_mfma_ab5_combine(const PT* __restrict__ part, int nsplit, int64_t n,
                                                           int64_t npad, int B, double dt, Ab5Weights wt,
                                                           int4 slots03, int slot4, double* __restrict__ u,
                                                           double* __restrict__ hist, Firing fr,
@@ -1176,7 +1176,7 @@ __global__ __launch_bounds__(kWG) void k_mfma_ab5_combine(const double* __restri
   const int b = (int)(idx / n);
   const int64_t i = idx - (int64_t)b * n;
   double y = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) y += part[((int64_t)sp * B + b) * npad + i];
+  for (int sp = 0; sp < nsplit; ++sp) y += (double)part[((int64_t)sp * B + b) * npad + i];
   const double ui = u[idx];
   const double F = -ui + y;
   hist[slots03.x * nb + idx] = F;
@@ -1276,7 +1276,7 @@ inline void launch_mfma_apply(const ProblemView& pv, int form, int B, const void
 }
 
 template <typename T, int KIND>
-inline void launch_mfma_otf_t(const ProblemView& pv, const MfmaOtfParams& op, int B, const void* g, double* part,
+inline void launch_mfma_otf_t(const ProblemView& pv, const MfmaOtfParams& op, int B, const void* g, float* part,
                               hipStream_t s) {
   void *ghi, *glo;
   mfma_g_split(const_cast<void*>(g), pv.npad, B, &ghi, &glo);
@@ -1304,10 +1304,14 @@ inline void launch_mfma_otf_t(const ProblemView& pv, const MfmaOtfParams& op, in
 template <int KIND>
 inline void launch_mfma_otf(const ProblemView& pv, int form, const MfmaOtfParams& op, int B, const float* g,
                             double* part, hipStream_t s) {
+  // the fused forms write FP32 partial sums (each source chunk's FP32 matrix-core
+  // sum rounded once more; the combine adds them in FP64): half the bytes of
+  // FP64 slots, written here and read by every combine
+  float* pf = reinterpret_cast<float*>(part);
   if (mfma_is_bf16(form))
-    launch_mfma_otf_t<__bf16, KIND>(pv, op, B, g, part, s);
+    launch_mfma_otf_t<__bf16, KIND>(pv, op, B, g, pf, s);
   else
-    launch_mfma_otf_t<_Float16, KIND>(pv, op, B, g, part, s);
+    launch_mfma_otf_t<_Float16, KIND>(pv, op, B, g, pf, s);
 }
 
 // On-the-fly FP32 form on the FP32 matrix cores for template code KIND; g is
@@ -1325,37 +1329,39 @@ inline void launch_mfma_otf_f32(const ProblemView& pv, const PairParams& pp, int
                        pv.npad, B, kchunk, pp, part);
 }
 
-template <typename T>
+template <typename T, typename PT>
 inline void launch_mfma_combine_t(const ProblemView& pv, int B, int stage, double dt, double* u, double* v,
-                                  double* ksum, const double* part, int nsplit, const Firing& fr, const double* qd,
+                                  double* ksum, const PT* part, int nsplit, const Firing& fr, const double* qd,
                                   void* g, double* k1_out, const double* gamma, hipStream_t s) {
   void *ghi, *glo;
   mfma_g_split(g, pv.npad, B, &ghi, &glo);
   const int64_t total = pv.n * (int64_t)B;
-  hipLaunchKernelGGL(k_mfma_combine<T>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit, pv.n,
-                     pv.npad, B, stage, dt, u, v, ksum, fr, qd, pv.qmax, static_cast<T*>(ghi), static_cast<T*>(glo),
-                     k1_out, gamma);
+  hipLaunchKernelGGL((k_mfma_combine<T, PT>), dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit,
+                     pv.n, pv.npad, B, stage, dt, u, v, ksum, fr, qd, pv.qmax, static_cast<T*>(ghi),
+                     static_cast<T*>(glo), k1_out, gamma);
 }
 
 inline void launch_mfma_combine(const ProblemView& pv, int form, int B, int stage, double dt, double* u, double* v,
                                 double* ksum, const double* part, int nsplit, const Firing& fr, float* g,
                                 double* k1_out, const double* gamma, hipStream_t s) {
-  if (mfma_is_bf16(form))
-    launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, mfma_source_q(pv, form), g, k1_out,
-                                  gamma, s);
-  else
-    launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, mfma_source_q(pv, form), g,
-                                    k1_out, gamma, s);
+  const double* qd = mfma_source_q(pv, form);
+  const float* pf = reinterpret_cast<const float*>(part);
+  switch (form) {
+    case 2: launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, qd, g, k1_out, gamma, s); break;
+    case 3: launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, part, nsplit, fr, qd, g, k1_out, gamma, s); break;
+    case 4: launch_mfma_combine_t<__bf16>(pv, B, stage, dt, u, v, ksum, pf, nsplit, fr, qd, g, k1_out, gamma, s); break;
+    default: launch_mfma_combine_t<_Float16>(pv, B, stage, dt, u, v, ksum, pf, nsplit, fr, qd, g, k1_out, gamma, s); break;
+  }
 }
 
-template <typename T>
+template <typename T, typename PT>
 inline void launch_mfma_ab5_t(const ProblemView& pv, int B, double dt, const Ab5Weights& wt, int4 s03, int s4,
-                              double* u, double* hist, const double* part, int nsplit, const Firing& fr,
+                              double* u, double* hist, const PT* part, int nsplit, const Firing& fr,
                               const double* qd, void* g, hipStream_t s) {
   void *ghi, *glo;
   mfma_g_split(g, pv.npad, B, &ghi, &glo);
   const int64_t total = pv.n * (int64_t)B;
-  hipLaunchKernelGGL(k_mfma_ab5_combine<T>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit,
+  hipLaunchKernelGGL((k_mfma_ab5_combine<T, PT>), dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit,
                      pv.n, pv.npad, B, dt, wt, s03, s4, u, hist, fr, qd, pv.qmax, static_cast<T*>(ghi),
                      static_cast<T*>(glo));
 }
@@ -1363,17 +1369,25 @@ inline void launch_mfma_ab5_t(const ProblemView& pv, int B, double dt, const Ab5
 inline void launch_mfma_ab5(const ProblemView& pv, int form, int B, double dt, const Ab5Weights& wt, int4 s03, int s4,
                             double* u, double* hist, const double* part, int nsplit, const Firing& fr, float* g,
                             hipStream_t s) {
-  if (mfma_is_bf16(form))
-    launch_mfma_ab5_t<__bf16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, mfma_source_q(pv, form), g, s);
-  else
-    launch_mfma_ab5_t<_Float16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, mfma_source_q(pv, form), g, s);
+  const double* qd = mfma_source_q(pv, form);
+  const float* pf = reinterpret_cast<const float*>(part);
+  switch (form) {
+    case 2: launch_mfma_ab5_t<__bf16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, qd, g, s); break;
+    case 3: launch_mfma_ab5_t<_Float16>(pv, B, dt, wt, s03, s4, u, hist, part, nsplit, fr, qd, g, s); break;
+    case 4: launch_mfma_ab5_t<__bf16>(pv, B, dt, wt, s03, s4, u, hist, pf, nsplit, fr, qd, g, s); break;
+    default: launch_mfma_ab5_t<_Float16>(pv, B, dt, wt, s03, s4, u, hist, pf, nsplit, fr, qd, g, s); break;
+  }
 }
 
-inline void launch_mfma_reduce(const ProblemView& pv, int, int B, const double* part, int nsplit, double* y,
+inline void launch_mfma_reduce(const ProblemView& pv, int form, int B, const double* part, int nsplit, double* y,
                                hipStream_t s) {
   const int64_t total = pv.n * (int64_t)B;
-  hipLaunchKernelGGL(k_reduce_partials<1>, dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part, nsplit, pv.n,
-                     pv.npad, B, y);
+  if (mfma_has_w(form))
+    hipLaunchKernelGGL((k_reduce_partials<1, double>), dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s, part,
+                       nsplit, pv.n, pv.npad, B, y);
+  else
+    hipLaunchKernelGGL((k_reduce_partials<1, float>), dim3((unsigned)ceil_div(total, kWG)), dim3(kWG), 0, s,
+                       reinterpret_cast<const float*>(part), nsplit, pv.n, pv.npad, B, y);
 }
 
 }  // namespace nfr
