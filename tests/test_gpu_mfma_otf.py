@@ -76,6 +76,24 @@ def test_fused_apply_matches_oracle(ctx, form, n, B, kind):
     assert err <= TOL_APPLY[form], err
 
 
+@pytest.mark.parametrize("form", [4, 5])
+def test_fused_largest_state_count(ctx, form):
+    """B = 4096, the largest accepted state count (64 groups of 64 states; for
+    BF16 the eight-wave far form in tile order), on a ragged node set of 300
+    nodes: every state against the oracle to the form's bound."""
+    n, B = 300, 4096
+    rng = np.random.default_rng(4096 + 17 * form)
+    x = S.fibonacci_sphere(n)
+    q = rng.uniform(0.5, 1.5, size=n) * 4 * math.pi / n
+    U = rng.normal(0.2, 0.4, size=(B, n))
+    theta = rng.uniform(0.1, 0.3, size=B)
+    y = _apply(ctx, x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta, form)
+    ref = NF.apply_K(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta)
+    err = np.max(np.abs(y - ref) / _scale(x, q, U, NF.GAUSS_MH, GAUSS, 20.0, theta))
+    print("fused form %d, n = %d, B = %d: max |dy| / S = %.3e" % (form, n, B, err), flush=True)
+    assert err <= TOL_APPLY[form], err
+
+
 # Integer length ratios rho = 1/m: the excitatory exponential is taken as a
 # power of the inhibitory one, coordinates scaled by the inhibitory length.
 RATIO_KERNELS = [(NF.GAUSS_MH, (1.0, 0.2, 0.5, 0.2 * math.sqrt(2.0))),     # rho = 1/2
