@@ -436,7 +436,10 @@ Workspace carve(void* base, const ProblemView& pv, int B, int form, bool steppin
   w.nsplit = nsplit_of(pv, B, form, w.otf);
   const size_t gbytes = is_mfma_form(form) ? mfma_g_bytes(pv.npad, B) : size_t(pv.npad) * B * sizeof(float);
   w.g = reinterpret_cast<float*>(take(gbytes));
-  w.part = reinterpret_cast<double*>(take(size_t(w.nsplit) * B * pv.npad * sizeof(double)));
+  // the fused split forms keep FP32 partial sums, every other form FP64
+  const size_t part_elem = (form == NFR_FORM_ONTHEFLY_BF16X3 || form == NFR_FORM_ONTHEFLY_FP16X3) ? sizeof(float)
+                                                                                                  : sizeof(double);
+  w.part = reinterpret_cast<double*>(take(size_t(w.nsplit) * B * pv.npad * part_elem));
   if (stepping) {
     w.v = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));
     w.ksum = reinterpret_cast<double*>(take(size_t(pv.n) * B * sizeof(double)));

@@ -66,7 +66,7 @@ def test_noalloc_equals_apply_on_two_calls(ctx, first, second):
 
 
 def test_noalloc_rejects_oversized_scratch(ctx):
-    """N = 65536 with 64 states on the fused BF16 form needs 268 MB of partial
+    """N = 65536 with 64 states on the fused BF16 form needs 134 MB of FP32 partial
     sums: rejected with NFR_ERR_WORKSPACE before anything is enqueued."""
     surf = S.ellipsoid(65536)
     prob, k, f, u = _case(ctx, surf, 64, 0, (1.0, 0.15, 0.5, 0.4), 3)
